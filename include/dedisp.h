@@ -1,0 +1,254 @@
+/*
+ * libdedisp -- programmable-profile incoherent dedispersion and boxcar detection
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the multi-sample incoherent dedisperser analysed in Clarke,
+ * Macquart & Trott, "Performance of a novel fast transients detection system":
+ * for every trial DM a set of dynamic-spectrum samples is summed (eq. p_dedisp,
+ * Section 2.1), the sample set of each channel being a contiguous run of
+ * `ntap` samples starting at the cold-plasma delay of the channel's top edge
+ * (t_A, Section 3).  The dedispersed series is then searched with boxcar
+ * windows of integer widths (the boxcar detector of Section 4), each window
+ * normalised by its exact noise standard deviation (eqs. P_N_dedisp and snr).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns a dedisp_status; DEDISP_OK is 0.  No exception crosses
+ *     the ABI.  dedisp_last_error() gives a thread-local description of the last
+ *     failure.
+ *   - "host" pointers are read during the call only; "device" pointers are HIP
+ *     device memory owned by the caller, which must stay alive until `stream`
+ *     has executed the enqueued work.  Calls enqueue asynchronously on the HIP
+ *     stream `stream` (a hipStream_t, NULL = the default stream) and return.
+ *   - Filterbank layout: channel-major, x[b][c][t] at byte offset
+ *     ((b * bstride + c * stride) + t) * sizeof(elem), strides in elements.
+ *   - Dedispersed layout: y[b][d][t], t in [0, nout), strides in elements.
+ *   - A plan holds only immutable tables (host copies and lazily uploaded
+ *     device copies); calls on different streams may share it provided each
+ *     has its own workspace.
+ */
+#ifndef DEDISP_H
+#define DEDISP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dedisp_plan_s *dedisp_plan;
+typedef struct dedisp_batch_s *dedisp_batch;
+
+typedef enum {
+  DEDISP_OK = 0,
+  DEDISP_ERR_INVALID_ARG = 1, /* null pointer, non-positive size, non-finite value, bad enum */
+  DEDISP_ERR_SHAPE = 2,       /* input block shorter than the longest sample run */
+  DEDISP_ERR_OVERFLOW = 3,    /* an int32 sum could exceed 2^31 - 1 */
+  DEDISP_ERR_OOM = 4,         /* host or device allocation failed */
+  DEDISP_ERR_DEVICE = 5,      /* a HIP call failed (message in dedisp_last_error) */
+  DEDISP_ERR_UNSUPPORTED = 6  /* valid request this build does not implement */
+} dedisp_status;
+
+typedef enum { DEDISP_U8 = 0, DEDISP_F32 = 1, DEDISP_I32 = 2 } dedisp_dtype;
+
+/* How the sample run of each (trial, channel) is chosen.
+ *   SMEAR      ntap = max(1, ceil(K DM (nu_lo^-2 - nu_top^-2) / dt)): the channel's
+ *              dispersion smear in samples (Section 3, Delta tau_c between edges).
+ *   ALLNONZERO every sample holding non-zero pulse power for a rectangular pulse
+ *              of width tau'(nu) = width_s + scatter_s_1ghz * nu^scatter_index:
+ *              ntap = max(1, ceil(t_B/dt) - floor(t_A/dt)) (eq. num_samples), with
+ *              t_B taken at the channel's low edge.
+ *   GREEDY     the Section 2.2 selection: predicted cell powers of the rectangular
+ *              pulse model (App. A, eq. dispersed pulse) added in decreasing order
+ *              while eq. sel_criterion holds; channels may get ntap = 0.
+ *   EXPLICIT   caller-supplied start/ntap tables.
+ *   FIXED      ntap = ktaps for every (trial, channel) (per-tap weighted profiles).
+ * For every rule except EXPLICIT, start = floor(K DM (nu_top,c^-2 - nu_hi^-2) / dt). */
+typedef enum {
+  DEDISP_RULE_SMEAR = 0,
+  DEDISP_RULE_ALLNONZERO = 1,
+  DEDISP_RULE_GREEDY = 2,
+  DEDISP_RULE_EXPLICIT = 3,
+  DEDISP_RULE_FIXED = 4
+} dedisp_rule;
+
+/* Sample weights: UNIT (the paper's unweighted sums; exact int32 for uint8
+ * input), CHANNEL (w[c]), TAP (w[c][k], k < ktaps; requires ntap == ktaps). */
+typedef enum { DEDISP_W_UNIT = 0, DEDISP_W_CHANNEL = 1, DEDISP_W_TAP = 2 } dedisp_wmode;
+
+typedef struct {
+  int32_t rule;            /* dedisp_rule */
+  double k_dm;             /* delay constant in s GHz^2 cm^3 / pc; 0 => 1/(2.41e-16 * 1e18) */
+  double width_s;          /* ALLNONZERO / GREEDY: intrinsic pulse width tau */
+  double scatter_s_1ghz;   /* ALLNONZERO / GREEDY: scatter width at 1 GHz */
+  double scatter_index;    /* ALLNONZERO / GREEDY: scatter frequency index (e.g. -4) */
+  double spectral_index;   /* GREEDY: alpha of P ~ (nu/nu0)^-alpha (eq. intrinsic_power) */
+  double nu0_ghz;          /* GREEDY: reference frequency; 0 => 1 GHz */
+  const int32_t *start;    /* EXPLICIT: host [ndm * nchan], copied at create */
+  const int32_t *ntap;     /* EXPLICIT: host [ndm * nchan], copied at create, >= 0 */
+  int32_t ktaps;           /* FIXED rule tap count; TAP weights per channel */
+  int32_t wmode;           /* dedisp_wmode */
+  const float *weights;    /* host [nchan] (CHANNEL) or [nchan * ktaps] (TAP), copied */
+} dedisp_profile;
+
+/* Fill `prof` with defaults: SMEAR rule, paper K, unit weights, scatter_index -4. */
+dedisp_status dedisp_profile_init(dedisp_profile *prof);
+
+/* Build a plan: the sample-set tables for `ndm` trial DMs over `nchan` channels.
+ *   freq_ghz   host [nchan] channel centre frequencies (any order), GHz
+ *   chan_bw_ghz channel width (> 0), GHz; dt_s sample time (> 0)
+ *   dm         host [ndm] trial DMs (>= 0, finite), pc cm^-3
+ * Host-only work; device tables are uploaded on first use.  Errors:
+ * INVALID_ARG for bad sizes/values, OOM. */
+dedisp_status dedisp_plan_create(dedisp_plan *out, int32_t nchan, const double *freq_ghz,
+                                 double chan_bw_ghz, double dt_s, int32_t ndm, const double *dm,
+                                 const dedisp_profile *prof);
+dedisp_status dedisp_plan_destroy(dedisp_plan plan);
+
+/* Copy the tables to host arrays start/ntap [ndm * nchan] (either may be NULL). */
+dedisp_status dedisp_plan_tables(dedisp_plan plan, int32_t *start, int32_t *ntap);
+
+/* Plan shape: number of channels, trials, the longest run max(start + ntap), the
+ * tap count of TAP weights (1 otherwise) and the weight mode.  Any may be NULL. */
+dedisp_status dedisp_plan_info(dedisp_plan plan, int32_t *nchan, int32_t *ndm, int32_t *max_span,
+                               int32_t *ktaps, int32_t *wmode);
+
+/* Valid output length for a block of nsamp samples: nout = nsamp - max(start + ntap) + 1
+ * (eq. p_dedisp restricted to outputs whose samples all lie in the block).
+ * SHAPE if nout < 1. */
+dedisp_status dedisp_plan_out_len(dedisp_plan plan, int64_t nsamp, int64_t *nout);
+
+/* eq. p_dedisp: y[b][d][t] = sum_c sum_{k < ntap[d,c]} w_{c,k} x[b][c][t + start[d,c] + k]
+ * for 0 <= t < nout.  Supported (input, weights) -> output:
+ *   U8 + UNIT    -> I32 (exact) or F32
+ *   U8 + CHANNEL -> F32 (per-channel products summed in fp32 blocks, fp64 across blocks)
+ *   F32 + TAP    -> F32 (FIR over the taps, then the one-sample sum)
+ *   F32 + UNIT / CHANNEL -> F32
+ * d_in device, d_out device [nbatch][ndm][nout].  Errors: SHAPE when
+ * nsamp < max_span, OVERFLOW when an int32 sum could exceed 2^31 - 1,
+ * UNSUPPORTED for other combinations, DEVICE on HIP failure.
+ * d_weights (device, nullable): when non-NULL, replaces the plan's CHANNEL or TAP
+ * weights for this call (same layout); used when the weights are being learned. */
+dedisp_status dedisp_dedisperse(dedisp_plan plan, const void *d_in, int32_t in_dtype,
+                                int64_t nsamp, int64_t in_stride, int64_t in_bstride,
+                                int32_t nbatch, void *d_out, int32_t out_dtype, int64_t out_stride,
+                                int64_t out_bstride, const float *d_weights, void *stream);
+
+/* Workspace (device bytes) needed by dedisp_detect / dedisp_search for nsamp
+ * samples and nw widths. */
+dedisp_status dedisp_work_bytes(dedisp_plan plan, int64_t nsamp, int32_t nw, size_t *bytes);
+
+/* Boxcar S/N search (eq. snr with the Section 4 boxcar) of a dedispersed block:
+ * for every trial d, width W (host widths[nw], 1 <= W <= nout, nw <= 64) and
+ * start t (0 <= t <= nout - W):
+ *   B = sum_{j<W} y[d][t+j],  snr = (B - M[d,W]) / S[d,W],
+ *   M = sum_c mu_c sum_tau a[tau],  S^2 = sum_c sigma_c^2 sum_tau a[tau]^2,
+ * where a is the trial's channel weight run convolved with a length-W box, and
+ * mu/sigma are device fp64 [nchan] per-channel noise mean / std.  Per trial the
+ * best (snr, t, W) is written to device d_snr (f64), d_t, d_w (i32) [ndm];
+ * exact ties go to the smaller W, then the smaller t.  y is I32 or F32. */
+dedisp_status dedisp_detect(dedisp_plan plan, const void *d_y, int32_t y_dtype, int64_t nout,
+                            int64_t y_stride, const int32_t *widths, int32_t nw,
+                            const double *d_chan_mean, const double *d_chan_sigma, double *d_snr,
+                            int32_t *d_t, int32_t *d_w, void *d_work, size_t work_bytes,
+                            void *stream);
+
+/* Fused dedisperse + detect for one uint8 (UNIT weights) or other supported
+ * block without materialising y.  Same results as dedisp_dedisperse followed by
+ * dedisp_detect. */
+dedisp_status dedisp_search(dedisp_plan plan, const void *d_in, int32_t in_dtype, int64_t nsamp,
+                            int64_t in_stride, const int32_t *widths, int32_t nw,
+                            const double *d_chan_mean, const double *d_chan_sigma, double *d_snr,
+                            int32_t *d_t, int32_t *d_w, void *d_work, size_t work_bytes,
+                            void *stream);
+
+/* Adjoint of dedisp_dedisperse (the transpose of eq. p_dedisp), for gradients:
+ *   grad_w[c][k] += sum_b sum_d sum_t g[b][d][t] x[b][c][t + start + k]   (fp64, device,
+ *                   [nchan][K], K = ktaps for TAP weights, 1 otherwise)
+ *   grad_in[b][c][i] = sum_d sum_k w_{c,k} g[b][d][i - start - k]           (fp32, device)
+ * grad_w is overwritten (not accumulated); either output may be NULL.
+ * g is device fp32 [nbatch][ndm][nout]; x is the forward input (U8 or F32);
+ * d_weights as in dedisp_dedisperse. */
+dedisp_status dedisp_dedisperse_backward(dedisp_plan plan, const float *d_grad_y, int64_t nout,
+                                         int64_t gy_stride, int64_t gy_bstride, int32_t nbatch,
+                                         const void *d_in, int32_t in_dtype, int64_t nsamp,
+                                         int64_t in_stride, int64_t in_bstride, float *d_grad_in,
+                                         double *d_grad_w, const float *d_weights, void *stream);
+
+/* Weight gradient for a sparse output gradient with nnz entries (b, d, t, val)
+ * (device arrays): grad_w[c][k] = sum_e val_e x[b_e][c][t_e + start[d_e,c] + k].
+ * Used when the loss reads a few known outputs (a matched-filter S/N at known
+ * pulse positions).  grad_w is overwritten.  Entries whose b, d or t fall
+ * outside [0, nbatch) x [0, ndm) x [0, nout) contribute nothing. */
+dedisp_status dedisp_backward_sparse(dedisp_plan plan, int32_t nnz, const int32_t *d_b,
+                                     const int32_t *d_d, const int32_t *d_t, const float *d_val,
+                                     const void *d_in, int32_t in_dtype, int64_t nsamp,
+                                     int64_t in_stride, int64_t in_bstride, int32_t nbatch,
+                                     double *d_grad_w, void *stream);
+
+/* Gather selected outputs y[b_e][d_e][t_e] (e < nnz) of the dedispersion sum
+ * without computing the rest (the forward of the sparse path), summed in fp64
+ * and rounded to fp32 into d_out [nnz].  Out-of-range entries yield NaN. */
+dedisp_status dedisp_dedisperse_gather(dedisp_plan plan, int32_t nnz, const int32_t *d_b,
+                                       const int32_t *d_d, const int32_t *d_t, const void *d_in,
+                                       int32_t in_dtype, int64_t nsamp, int64_t in_stride,
+                                       int64_t in_bstride, int32_t nbatch, float *d_out,
+                                       const float *d_weights, void *stream);
+
+/* Trial DMs by eq. trial DMs (Section 5.3):
+ *   DM_n = DM_0 + (2 eps / C) sum_{i<n} sqrt(DM_i^2 + DM_diag^2 + DM_tau^2),
+ * DM_diag = dt / (2 K dnu) / mean(nu_c^-3), DM_tau the same with tau_av_s for dt,
+ * nu_c the channel centres; DM_tau is used only when include_dm_tau != 0.
+ * Trials are produced while DM_n <= dm_max and at most `cap` of them; host
+ * out[cap] receives them and *n_out their number.  k_dm = 0 => paper K. */
+dedisp_status dedisp_trial_dms(double dm0, double dm_max, double eps, int32_t nchan,
+                               const double *freq_ghz, double chan_bw_ghz, double dt_s,
+                               double tau_av_s, int32_t include_dm_tau, double k_dm, int32_t cap,
+                               double *out, int32_t *n_out);
+
+/* Batched search over many beams, each with its own plan (own DM grid) and
+ * block length, as one persistent launch.  plans[nbeam] must share nchan and
+ * use UNIT weights with uint8 input.  widths host [nw]. */
+dedisp_status dedisp_batch_create(dedisp_batch *out, int32_t nbeam, const dedisp_plan *plans,
+                                  const int64_t *nsamp, const int32_t *widths, int32_t nw);
+dedisp_status dedisp_batch_destroy(dedisp_batch batch);
+dedisp_status dedisp_batch_work_bytes(dedisp_batch batch, size_t *bytes);
+/* d_in: host array [nbeam] of device pointers to each beam's uint8 block
+ * (row stride in_stride[b]); d_chan_mean/sigma device fp64 [nchan] shared by all
+ * beams; outputs device, concatenated over beams in beam order (sum of ndm_b).
+ * If use_graph != 0 the launch sequence is captured once into a hipGraph and
+ * replayed on later calls with the same pointers. */
+dedisp_status dedisp_batch_run(dedisp_batch batch, const void *const *d_in, const int64_t *in_stride,
+                               const double *d_chan_mean, const double *d_chan_sigma,
+                               double *d_snr, int32_t *d_t, int32_t *d_w, void *d_work,
+                               size_t work_bytes, int32_t use_graph, void *stream);
+/* Total trials across beams (length of the batch outputs). */
+dedisp_status dedisp_batch_info(dedisp_batch batch, int64_t *total_trials, int64_t *total_sums);
+
+/* Choose the search kernel's tile shape for this plan and block length by timing
+ * the candidates on `stream` with caller-provided scratch input; the choice is
+ * stored in the plan (and cached per shape in the file named by the environment
+ * variable DEDISP_TUNE_CACHE, if set).  d_in must hold nsamp valid samples. */
+dedisp_status dedisp_autotune(dedisp_plan plan, const void *d_in, int64_t nsamp, int64_t in_stride,
+                              const int32_t *widths, int32_t nw, const double *d_chan_mean,
+                              const double *d_chan_sigma, void *d_work, size_t work_bytes,
+                              void *stream, int32_t *chosen);
+/* Force a tile configuration (index into the kernel's candidate list), or -1 for default. */
+dedisp_status dedisp_set_tile(dedisp_plan plan, int32_t tile);
+
+/* Instrumentation.  When set, every dedisp_search call on this plan records
+ * ev_start[i] on its stream immediately before its dominant kernel (the
+ * dedispersion sum, or the fused search kernel) and ev_stop[i] immediately
+ * after it, with i cycling over [0, n).  The events are caller-created
+ * hipEvent_t handles that must outlive their use; n = 0 disables.  This is the
+ * one piece of mutable plan state: do not change it while calls are in flight. */
+dedisp_status dedisp_set_kernel_events(dedisp_plan plan, void *const *ev_start,
+                                       void *const *ev_stop, int32_t n);
+
+const char *dedisp_status_string(dedisp_status s);
+const char *dedisp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DEDISP_H */

@@ -1,0 +1,163 @@
+// Internal declarations shared by the host plan code and the HIP launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/dedisp.h"
+
+namespace dd {
+
+// Thread-local error text behind dedisp_last_error().
+void set_error(const std::string &msg);
+dedisp_status fail(dedisp_status s, const std::string &msg);
+dedisp_status hip_fail(hipError_t e, const char *what);
+
+#define DD_HIP(call)                                            \
+  do {                                                          \
+    hipError_t e_ = (call);                                     \
+    if (e_ != hipSuccess) return ::dd::hip_fail(e_, #call);     \
+  } while (0)
+
+constexpr int kMaxWidths = 64;
+
+// Boxcar widths passed to kernels by value: sorted ascending, unique.
+struct WidthList {
+  int32_t n;
+  int32_t w[kMaxWidths];
+};
+
+// Per-(DM tile, channel group) descriptors of the tiled search kernel.
+struct TiledTables;
+
+struct DevTables {
+  int32_t *start = nullptr;   // [ndm][nchan]
+  int32_t *ntap = nullptr;    // [ndm][nchan]
+  float *weights = nullptr;   // [nchan] or [nchan][ktaps]
+};
+
+}  // namespace dd
+
+struct dedisp_plan_s {
+  int32_t nchan = 0, ndm = 0;
+  double chan_bw = 0, dt = 0, kdm = 0;
+  std::vector<double> freq, dm;
+  dedisp_profile prof{};
+  std::vector<int32_t> start, ntap;     // [ndm][nchan]
+  std::vector<float> weights;           // copied weights
+  int32_t ktaps = 1;
+  int32_t wmode = DEDISP_W_UNIT;
+  int32_t max_span = 0;                 // max(start + ntap)
+  int32_t min_start = 0;
+  int32_t max_ntap = 0;
+  int64_t sum_max_ntap = 0;             // sum_c max_d ntap[d,c]
+  int32_t tile_choice = -1;             // forced / tuned tile configuration
+
+  // Device copies, uploaded on first use (per plan, on the current device).
+  std::mutex mu;
+  bool uploaded = false;
+  int device = -1;
+  dd::DevTables dev;
+  dd::TiledTables *tiled = nullptr;     // optimised-search tables (built lazily)
+
+  // Instrumentation events around the dominant kernel (dedisp_set_kernel_events).
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  size_t ev_next = 0;
+};
+
+namespace dd {
+dedisp_status ensure_device(dedisp_plan p);
+
+// Records the instrumentation events (if any) around one dominant-kernel launch.
+struct KernelTimer {
+  dedisp_plan_s *p;
+  hipStream_t s;
+  size_t slot = 0;
+  bool on = false;
+  KernelTimer(dedisp_plan_s *plan, hipStream_t stream) : p(plan), s(stream) {
+    if (!p->ev_start.empty()) {
+      on = true;
+      slot = p->ev_next % p->ev_start.size();
+      p->ev_next++;
+    }
+  }
+  hipError_t begin() { return on ? hipEventRecord(p->ev_start[slot], s) : hipSuccess; }
+  hipError_t end() { return on ? hipEventRecord(p->ev_stop[slot], s) : hipSuccess; }
+};
+
+// Per-call replacement of the plan's device weights (learned weights), scoped to
+// the calling thread for the duration of one entry point.
+extern thread_local const float *tl_weights;
+struct WeightOverride {
+  const float *prev;
+  explicit WeightOverride(const float *w) : prev(tl_weights) { if (w) tl_weights = w; }
+  ~WeightOverride() { tl_weights = prev; }
+};
+inline const float *weights_of(const dedisp_plan_s *p) {
+  return tl_weights ? tl_weights : p->dev.weights;
+}
+void free_tiled(TiledTables *t);
+
+// Launchers (kernels_*.hip).  All enqueue on `stream` and return hipError_t.
+hipError_t launch_prefix_u8(const uint8_t *x, int64_t in_stride, int64_t in_bstride, int32_t nchan,
+                            int32_t nbatch, int64_t nsamp, int32_t *P, hipStream_t s);
+hipError_t launch_dedisp_prefix(const dedisp_plan_s *p, const int32_t *P, int64_t pstride,
+                                int64_t pbstride, int32_t nbatch, int64_t nout, void *y,
+                                int32_t out_dtype, int64_t out_stride, int64_t out_bstride,
+                                hipStream_t s);
+hipError_t launch_dedisp_direct_f32(const dedisp_plan_s *p, const float *x, int64_t in_stride,
+                                    int64_t in_bstride, int32_t nbatch, int64_t nout, float *y,
+                                    int64_t out_stride, int64_t out_bstride, hipStream_t s);
+hipError_t launch_fir_f32(const dedisp_plan_s *p, const float *x, int64_t in_stride,
+                          int64_t in_bstride, int32_t nbatch, int64_t nz, float *z,
+                          hipStream_t s);
+hipError_t launch_dedisp_1tap_f32(const dedisp_plan_s *p, const float *z, int64_t zstride,
+                                  int64_t zbstride, int32_t nbatch, int64_t nout, float *y,
+                                  int64_t out_stride, int64_t out_bstride, hipStream_t s);
+hipError_t launch_norm(const dedisp_plan_s *p, const WidthList &wl, const double *mu,
+                       const double *sigma, double *M, double *S, hipStream_t s);
+hipError_t launch_boxcar(const dedisp_plan_s *p, const void *y, int32_t y_dtype, int64_t nout,
+                         int64_t y_stride, const WidthList &wl, const double *M, const double *S,
+                         void *partials, int32_t nchunk, hipStream_t s);
+hipError_t launch_reduce(int32_t ndm, int32_t nchunk, const void *partials, double *snr,
+                         int32_t *t, int32_t *w, hipStream_t s);
+hipError_t launch_adjoint_z(const dedisp_plan_s *p, const float *g, int64_t nout, int64_t gstride,
+                            int64_t gbstride, int32_t nbatch, int64_t nz, float *z,
+                            hipStream_t s);
+hipError_t launch_grad_w_tap(const dedisp_plan_s *p, const float *z, int64_t nz, const void *x,
+                             int32_t in_dtype, int64_t in_stride, int64_t in_bstride,
+                             int32_t nbatch, double *gw, hipStream_t s);
+hipError_t launch_grad_x_tap(const dedisp_plan_s *p, const float *z, int64_t nz, int64_t nsamp,
+                             int32_t nbatch, float *gx, int64_t in_stride, int64_t in_bstride,
+                             hipStream_t s);
+hipError_t launch_adjoint_direct(const dedisp_plan_s *p, const float *g, int64_t nout,
+                                 int64_t gstride, int64_t gbstride, int32_t nbatch, const void *x,
+                                 int32_t in_dtype, int64_t nsamp, int64_t in_stride,
+                                 int64_t in_bstride, float *gx, double *gw, hipStream_t s);
+hipError_t launch_sparse_grad_w(const dedisp_plan_s *p, int32_t nnz, const int32_t *b,
+                                const int32_t *d, const int32_t *t, const float *val,
+                                const void *x, int32_t in_dtype, int64_t in_stride,
+                                int64_t in_bstride, int32_t nbatch, int64_t nout, double *gw,
+                                hipStream_t s);
+hipError_t launch_gather(const dedisp_plan_s *p, int32_t nnz, const int32_t *b, const int32_t *d,
+                         const int32_t *t, const void *x, int32_t in_dtype, int64_t in_stride,
+                         int64_t in_bstride, int32_t nbatch, int64_t nout, float *out,
+                         hipStream_t s);
+
+// Tiled fused search for uint8 input with unit weights (kernels_search.hip).
+bool search_supported(const dedisp_plan_s *p, const WidthList &wl);
+size_t search_work_bytes(const dedisp_plan_s *p, int32_t nw, int64_t nout);
+dedisp_status run_search_tiled(dedisp_plan p, const uint8_t *x, int64_t nsamp, int64_t in_stride,
+                               int64_t nout, const WidthList &wl, const double *mu,
+                               const double *sigma, double *snr, int32_t *t, int32_t *w,
+                               void *work, hipStream_t s);
+
+// Size of one per-chunk detection candidate record in the workspace.
+constexpr size_t kCandBytes = 16;
+constexpr int kBoxChunk = 256;  // starts per detection block
+
+}  // namespace dd

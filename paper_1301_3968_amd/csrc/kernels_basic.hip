@@ -1,0 +1,671 @@
+// General-purpose kernels of libdedisp for gfx950: prefix pre-pass, the
+// dedispersion sum for every weight mode, the boxcar detector, its reduction and
+// the adjoint (gradient) kernels.  The tiled search kernel for uint8 data with
+// unit weights lives in kernels_search.hip.
+//
+// Sums follow eq. p_dedisp (Section 2.1): for trial d, channel c contributes the
+// run of ntap[d,c] samples starting at start[d,c] + t.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+
+#include "internal.h"
+
+namespace dd {
+namespace {
+
+constexpr int kThreads = 256;
+
+// ----------------------------------------------------------------------------------
+// Per-channel inclusive prefix of uint8 samples: P[c][0] = 0, P[c][i+1] = P[c][i] + x[c][i].
+// One block per (channel, batch); each thread scans a contiguous chunk.
+// Values are exact in int32 for blocks shorter than 2^31 / 255 samples.
+// ----------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads)
+k_prefix_u8(const uint8_t *__restrict__ x, int64_t in_stride, int64_t in_bstride, int64_t nsamp,
+            int32_t *__restrict__ P, int64_t pstride, int64_t pbstride) {
+  const int c = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const uint8_t *row = x + (int64_t)b * in_bstride + (int64_t)c * in_stride;
+  int32_t *out = P + (int64_t)b * pbstride + (int64_t)c * pstride;
+  const int64_t chunk = (nsamp + kThreads - 1) / kThreads;
+  const int64_t i0 = min((int64_t)tid * chunk, nsamp), i1 = min(i0 + chunk, nsamp);
+  int32_t s = 0;
+  for (int64_t i = i0; i < i1; ++i) s += row[i];
+  __shared__ int32_t part[kThreads];
+  part[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < kThreads; off <<= 1) {
+    int32_t v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int32_t run = tid == 0 ? 0 : part[tid - 1];
+  if (tid == 0) out[0] = 0;
+  for (int64_t i = i0; i < i1; ++i) {
+    run += row[i];
+    out[i + 1] = run;
+  }
+}
+
+// y[d][t] = sum_c (P[c][t+s+n] - P[c][t+s]) (int32, exact), or with channel
+// weights sum_c w_c * (window sum), accumulated in fp32 over blocks of 32
+// channels and in fp64 across blocks.
+template <bool kWeighted, typename OutT>
+__global__ void __launch_bounds__(kThreads)
+k_dedisp_prefix(const int32_t *__restrict__ P, int64_t pstride, int64_t pbstride,
+                const int32_t *__restrict__ start, const int32_t *__restrict__ ntap,
+                const float *__restrict__ w, int32_t nchan, int64_t nout, OutT *__restrict__ y,
+                int64_t out_stride, int64_t out_bstride) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int d = blockIdx.y, b = blockIdx.z;
+  if (t >= nout) return;
+  const int32_t *Pb = P + (int64_t)b * pbstride;
+  const int32_t *sd = start + (int64_t)d * nchan;
+  const int32_t *nd = ntap + (int64_t)d * nchan;
+  if constexpr (!kWeighted) {
+    int32_t acc = 0;
+    for (int c = 0; c < nchan; ++c) {
+      const int32_t *row = Pb + (int64_t)c * pstride + t + sd[c];
+      acc += row[nd[c]] - row[0];
+    }
+    y[(int64_t)b * out_bstride + (int64_t)d * out_stride + t] = (OutT)acc;
+  } else {
+    double tot = 0.0;
+    for (int c0 = 0; c0 < nchan; c0 += 32) {
+      float part = 0.0f;
+      const int c1 = min(nchan, c0 + 32);
+      for (int c = c0; c < c1; ++c) {
+        const int32_t *row = Pb + (int64_t)c * pstride + t + sd[c];
+        part = __fmaf_rn(w[c], (float)(row[nd[c]] - row[0]), part);
+      }
+      tot += (double)part;
+    }
+    y[(int64_t)b * out_bstride + (int64_t)d * out_stride + t] = (OutT)tot;
+  }
+}
+
+// fp32 input, unit or channel weights: direct tap sums, fp32 within a block of
+// 32 channels, fp64 across blocks.
+template <bool kWeighted>
+__global__ void __launch_bounds__(kThreads)
+k_dedisp_direct_f32(const float *__restrict__ x, int64_t in_stride, int64_t in_bstride,
+                    const int32_t *__restrict__ start, const int32_t *__restrict__ ntap,
+                    const float *__restrict__ w, int32_t nchan, int64_t nout, float *__restrict__ y,
+                    int64_t out_stride, int64_t out_bstride) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int d = blockIdx.y, b = blockIdx.z;
+  if (t >= nout) return;
+  const float *xb = x + (int64_t)b * in_bstride;
+  const int32_t *sd = start + (int64_t)d * nchan;
+  const int32_t *nd = ntap + (int64_t)d * nchan;
+  double tot = 0.0;
+  for (int c0 = 0; c0 < nchan; c0 += 32) {
+    float part = 0.0f;
+    const int c1 = min(nchan, c0 + 32);
+    for (int c = c0; c < c1; ++c) {
+      const float *row = xb + (int64_t)c * in_stride + t + sd[c];
+      float s = 0.0f;
+      for (int k = 0; k < nd[c]; ++k) s += row[k];
+      part = kWeighted ? __fmaf_rn(w[c], s, part) : part + s;
+    }
+    tot += (double)part;
+  }
+  y[(int64_t)b * out_bstride + (int64_t)d * out_stride + t] = (float)tot;
+}
+
+// FIR over the taps: z[b][c][i] = sum_{k<K} w[c][k] x[b][c][i+k], 0 <= i < nz.
+__global__ void __launch_bounds__(kThreads)
+k_fir_f32(const float *__restrict__ x, int64_t in_stride, int64_t in_bstride,
+          const float *__restrict__ w, int32_t K, int64_t nz, float *__restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int c = blockIdx.y, b = blockIdx.z;
+  if (i >= nz) return;
+  const float *row = x + (int64_t)b * in_bstride + (int64_t)c * in_stride + i;
+  const float *wc = w + (int64_t)c * K;
+  float acc = 0.0f;
+  for (int k = 0; k < K; ++k) acc = __fmaf_rn(wc[k], row[k], acc);
+  z[((int64_t)b * gridDim.y + c) * nz + i] = acc;
+}
+
+// One-sample sum over FIR outputs: y[b][d][t] = sum_c z[b][c][t + s[d,c]].
+__global__ void __launch_bounds__(kThreads)
+k_dedisp_1tap_f32(const float *__restrict__ z, int64_t zstride, int64_t zbstride,
+                  const int32_t *__restrict__ start, int32_t nchan, int64_t nout,
+                  float *__restrict__ y, int64_t out_stride, int64_t out_bstride) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int d = blockIdx.y, b = blockIdx.z;
+  if (t >= nout) return;
+  const float *zb = z + (int64_t)b * zbstride + t;
+  const int32_t *sd = start + (int64_t)d * nchan;
+  double tot = 0.0;
+  for (int c0 = 0; c0 < nchan; c0 += 32) {
+    float part = 0.0f;
+    const int c1 = min(nchan, c0 + 32);
+    for (int c = c0; c < c1; ++c) part += zb[(int64_t)c * zstride + sd[c]];
+    tot += (double)part;
+  }
+  y[(int64_t)b * out_bstride + (int64_t)d * out_stride + t] = (float)tot;
+}
+
+// ----------------------------------------------------------------------------------
+// Boxcar noise statistics: M[d][j], S[d][j] for width W_j (eqs. P_N_dedisp and snr
+// extended to W consecutive outputs).  a = (channel weight run) * box_W.
+// ----------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads)
+k_norm(const int32_t *__restrict__ ntap, int32_t nchan, int32_t ndm, int32_t wmode, int32_t K,
+       const float *__restrict__ w, const double *__restrict__ mu,
+       const double *__restrict__ sigma, WidthList wl, double *__restrict__ M,
+       double *__restrict__ S) {
+  const int idx = blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= ndm * wl.n) return;
+  const int d = idx / wl.n, j = idx % wl.n;
+  const int W = wl.w[j];
+  double m = 0.0, v = 0.0;
+  for (int c = 0; c < nchan; ++c) {
+    const int n = ntap[(int64_t)d * nchan + c];
+    if (n == 0) continue;
+    double s1, s2;
+    if (wmode == DEDISP_W_TAP) {
+      // explicit convolution of the tap weights with a length-W box
+      s1 = 0.0;
+      s2 = 0.0;
+      for (int tau = 0; tau < n + W - 1; ++tau) {
+        double a = 0.0;
+        const int k0 = max(0, tau - W + 1), k1 = min(n - 1, tau);
+        for (int k = k0; k <= k1; ++k) a += (double)w[(int64_t)c * K + k];
+        s1 += a;
+        s2 += a * a;
+      }
+    } else {
+      // n-box convolved with W-box: a trapezoid 1, 2, .., m, .., m, .., 2, 1
+      const int lo = min(n, W), hi = max(n, W);
+      const double ld = lo;
+      s1 = (double)n * (double)W;
+      s2 = 2.0 * ((ld - 1.0) * ld * (2.0 * ld - 1.0) / 6.0) + (double)(hi - lo + 1) * ld * ld;
+      if (wmode == DEDISP_W_CHANNEL) {
+        const double wc = (double)w[c];
+        s1 *= wc;
+        s2 *= wc * wc;
+      }
+    }
+    m += mu[c] * s1;
+    v += sigma[c] * sigma[c] * s2;
+  }
+  M[idx] = m;
+  S[idx] = sqrt(v);
+}
+
+struct Cand {
+  double snr;
+  int32_t t;
+  int32_t w;
+};
+
+__device__ __forceinline__ bool better(double s1, int w1, int t1, double s2, int w2, int t2) {
+  if (s1 != s2) return s1 > s2;
+  if (w1 != w2) return w1 < w2;
+  return t1 < t2;
+}
+
+// Boxcar search of one chunk of kBoxChunk starts of one trial.  Thread t grows
+// the window sum B one output at a time (the same summation order as a direct
+// sum), evaluating snr = (B - M)/S at every listed width.
+template <typename YT>
+__global__ void __launch_bounds__(kBoxChunk)
+k_boxcar(const YT *__restrict__ y, int64_t nout, int64_t y_stride, WidthList wl,
+         const double *__restrict__ M, const double *__restrict__ S, Cand *__restrict__ part,
+         int32_t nchunk) {
+  const int d = blockIdx.y, chunk = blockIdx.x, tid = threadIdx.x;
+  const int64_t t = (int64_t)chunk * kBoxChunk + tid;
+  const YT *yd = y + (int64_t)d * y_stride;
+  double best = -INFINITY;
+  int bw = 0, bt = -1;
+  if (t < nout) {
+    double acc = 0.0;
+    int j = 0;
+    const int wmax = wl.w[wl.n - 1];
+    for (int q = 0; q < wmax && t + q < nout; ++q) {
+      acc += (double)yd[t + q];
+      if (q + 1 == wl.w[j]) {
+        const double r = (acc - M[d * wl.n + j]) / S[d * wl.n + j];
+        if (better(r, wl.w[j], (int)t, best, bw, bt)) {
+          best = r;
+          bw = wl.w[j];
+          bt = (int)t;
+        }
+        ++j;
+      }
+    }
+  }
+  __shared__ double s_snr[kBoxChunk];
+  __shared__ int s_w[kBoxChunk], s_t[kBoxChunk];
+  s_snr[tid] = best;
+  s_w[tid] = bw;
+  s_t[tid] = bt;
+  __syncthreads();
+  for (int off = kBoxChunk / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      const int o = tid + off;
+      if (s_t[o] >= 0 && (s_t[tid] < 0 || better(s_snr[o], s_w[o], s_t[o], s_snr[tid], s_w[tid], s_t[tid]))) {
+        s_snr[tid] = s_snr[o];
+        s_w[tid] = s_w[o];
+        s_t[tid] = s_t[o];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) part[(int64_t)d * nchunk + chunk] = Cand{s_snr[0], s_t[0], s_w[0]};
+}
+
+// Per trial, the best of its chunk candidates.
+__global__ void __launch_bounds__(kThreads)
+k_reduce(int32_t ndm, int32_t nchunk, const Cand *__restrict__ part, double *__restrict__ snr,
+         int32_t *__restrict__ tout, int32_t *__restrict__ wout) {
+  const int d = blockIdx.x, tid = threadIdx.x;
+  double best = -INFINITY;
+  int bw = 0, bt = -1;
+  for (int i = tid; i < nchunk; i += kThreads) {
+    const Cand c = part[(int64_t)d * nchunk + i];
+    if (c.t >= 0 && (bt < 0 || better(c.snr, c.w, c.t, best, bw, bt))) {
+      best = c.snr;
+      bw = c.w;
+      bt = c.t;
+    }
+  }
+  __shared__ double s_snr[kThreads];
+  __shared__ int s_w[kThreads], s_t[kThreads];
+  s_snr[tid] = best;
+  s_w[tid] = bw;
+  s_t[tid] = bt;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      const int o = tid + off;
+      if (s_t[o] >= 0 && (s_t[tid] < 0 || better(s_snr[o], s_w[o], s_t[o], s_snr[tid], s_w[tid], s_t[tid]))) {
+        s_snr[tid] = s_snr[o];
+        s_w[tid] = s_w[o];
+        s_t[tid] = s_t[o];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    snr[d] = s_t[0] >= 0 ? s_snr[0] : -INFINITY;
+    tout[d] = s_t[0];
+    wout[d] = s_w[0];
+  }
+}
+
+// ----------------------------------------------------------------------------------
+// Adjoint kernels (transposes of the dedispersion sum), all in gather form so that
+// every output is written by exactly one thread in a fixed summation order.
+// ----------------------------------------------------------------------------------
+
+// zbar[b][c][i] = sum_d g[b][d][i - s[d,c]] over trials whose output index lies in [0, nout).
+__global__ void __launch_bounds__(kThreads)
+k_adjoint_z(const float *__restrict__ g, int64_t nout, int64_t gstride, int64_t gbstride,
+            const int32_t *__restrict__ start, int32_t nchan, int32_t ndm, int64_t nz,
+            float *__restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int c = blockIdx.y, b = blockIdx.z;
+  if (i >= nz) return;
+  const float *gb = g + (int64_t)b * gbstride;
+  double acc = 0.0;
+  for (int d = 0; d < ndm; ++d) {
+    const int64_t t = i - start[(int64_t)d * nchan + c];
+    if (t >= 0 && t < nout) acc += (double)gb[(int64_t)d * gstride + t];
+  }
+  z[((int64_t)b * nchan + c) * nz + i] = (float)acc;
+}
+
+// gw[c][k] = sum_b sum_i zbar[b][c][i] x[b][c][i+k], fp64, one block per channel.
+template <typename XT>
+__global__ void __launch_bounds__(kThreads)
+k_grad_w_tap(const float *__restrict__ z, int64_t nz, const XT *__restrict__ x, int64_t in_stride,
+             int64_t in_bstride, int32_t nbatch, int32_t nchan, int32_t K, double *__restrict__ gw) {
+  const int c = blockIdx.x, tid = threadIdx.x;
+  double acc[64];
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  for (int b = 0; b < nbatch; ++b) {
+    const float *zr = z + ((int64_t)b * nchan + c) * nz;
+    const XT *xr = x + (int64_t)b * in_bstride + (int64_t)c * in_stride;
+    for (int64_t i = tid; i < nz; i += kThreads) {
+      const double zv = (double)zr[i];
+      for (int k = 0; k < K; ++k) acc[k] += zv * (double)xr[i + k];
+    }
+  }
+  __shared__ double red[kThreads];
+  for (int k = 0; k < K; ++k) {
+    red[tid] = acc[k];
+    __syncthreads();
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+      if (tid < off) red[tid] += red[tid + off];
+      __syncthreads();
+    }
+    if (tid == 0) gw[(int64_t)c * K + k] = red[0];
+    __syncthreads();
+  }
+}
+
+// gx[b][c][i] = sum_k w[c][k] zbar[b][c][i-k].
+__global__ void __launch_bounds__(kThreads)
+k_grad_x_tap(const float *__restrict__ z, int64_t nz, const float *__restrict__ w, int32_t K,
+             int64_t nsamp, int32_t nchan, float *__restrict__ gx, int64_t in_stride,
+             int64_t in_bstride) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int c = blockIdx.y, b = blockIdx.z;
+  if (i >= nsamp) return;
+  const float *zr = z + ((int64_t)b * nchan + c) * nz;
+  double acc = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const int64_t j = i - k;
+    if (j >= 0 && j < nz) acc += (double)w[(int64_t)c * K + k] * (double)zr[j];
+  }
+  gx[(int64_t)b * in_bstride + (int64_t)c * in_stride + i] = (float)acc;
+}
+
+// Unit / channel weights, any tap counts: gx[b][c][i] = sum_d w_c sum_{k<n} g[b][d][i-s-k].
+__global__ void __launch_bounds__(kThreads)
+k_grad_x_direct(const float *__restrict__ g, int64_t nout, int64_t gstride, int64_t gbstride,
+                const int32_t *__restrict__ start, const int32_t *__restrict__ ntap,
+                const float *__restrict__ w, int32_t nchan, int32_t ndm, int64_t nsamp,
+                float *__restrict__ gx, int64_t in_stride, int64_t in_bstride) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int c = blockIdx.y, b = blockIdx.z;
+  if (i >= nsamp) return;
+  const float *gb = g + (int64_t)b * gbstride;
+  double acc = 0.0;
+  for (int d = 0; d < ndm; ++d) {
+    const int64_t s = start[(int64_t)d * nchan + c];
+    const int n = ntap[(int64_t)d * nchan + c];
+    for (int k = 0; k < n; ++k) {
+      const int64_t t = i - s - k;
+      if (t >= 0 && t < nout) acc += (double)gb[(int64_t)d * gstride + t];
+    }
+  }
+  const double wc = w ? (double)w[c] : 1.0;
+  gx[(int64_t)b * in_bstride + (int64_t)c * in_stride + i] = (float)(wc * acc);
+}
+
+// Channel weights: gw[c] = sum_b sum_d sum_t g[b][d][t] sum_{k<n} x[b][c][t+s+k].
+template <typename XT>
+__global__ void __launch_bounds__(kThreads)
+k_grad_w_channel(const float *__restrict__ g, int64_t nout, int64_t gstride, int64_t gbstride,
+                 const int32_t *__restrict__ start, const int32_t *__restrict__ ntap,
+                 int32_t nchan, int32_t ndm, int32_t nbatch, const XT *__restrict__ x,
+                 int64_t in_stride, int64_t in_bstride, double *__restrict__ gw) {
+  const int c = blockIdx.x, tid = threadIdx.x;
+  double acc = 0.0;
+  for (int b = 0; b < nbatch; ++b)
+    for (int d = 0; d < ndm; ++d) {
+      const int64_t s = start[(int64_t)d * nchan + c];
+      const int n = ntap[(int64_t)d * nchan + c];
+      const XT *xr = x + (int64_t)b * in_bstride + (int64_t)c * in_stride + s;
+      const float *gr = g + (int64_t)b * gbstride + (int64_t)d * gstride;
+      for (int64_t t = tid; t < nout; t += kThreads) {
+        double xs = 0.0;
+        for (int k = 0; k < n; ++k) xs += (double)xr[t + k];
+        acc += (double)gr[t] * xs;
+      }
+    }
+  __shared__ double red[kThreads];
+  red[tid] = acc;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) gw[c] = red[0];
+}
+
+// Sparse weight gradient: gw[c][k] = sum_e val_e x[b_e][c][t_e + s[d_e,c] + k], fp64,
+// entries summed in index order.  One thread per (c, k).
+template <typename XT>
+__global__ void __launch_bounds__(kThreads)
+k_sparse_grad_w(int32_t nnz, const int32_t *__restrict__ eb, const int32_t *__restrict__ ed,
+                const int32_t *__restrict__ et, const float *__restrict__ val,
+                const int32_t *__restrict__ start, const int32_t *__restrict__ ntap,
+                int32_t nchan, int32_t ndm, int32_t K, int32_t tapmode, const XT *__restrict__ x,
+                int64_t in_stride, int64_t in_bstride, int32_t nbatch, int64_t nout,
+                double *__restrict__ gw) {
+  const int idx = blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= nchan * K) return;
+  const int c = idx / K, k = idx % K;
+  double acc = 0.0;
+  for (int e = 0; e < nnz; ++e) {
+    if (eb[e] < 0 || eb[e] >= nbatch || ed[e] < 0 || ed[e] >= ndm || et[e] < 0 || et[e] >= nout)
+      continue;
+    const int64_t s = start[(int64_t)ed[e] * nchan + c];
+    const int n = ntap[(int64_t)ed[e] * nchan + c];
+    const XT *xr = x + (int64_t)eb[e] * in_bstride + (int64_t)c * in_stride + et[e] + s;
+    if (tapmode) {
+      if (k < n) acc += (double)val[e] * (double)xr[k];
+    } else {
+      double xs = 0.0;
+      for (int q = 0; q < n; ++q) xs += (double)xr[q];
+      acc += (double)val[e] * xs;
+    }
+  }
+  gw[idx] = acc;
+}
+
+// Selected outputs y[b_e][d_e][t_e] in fp64, rounded to fp32.
+template <typename XT>
+__global__ void __launch_bounds__(64)
+k_gather(int32_t nnz, const int32_t *__restrict__ eb, const int32_t *__restrict__ ed,
+         const int32_t *__restrict__ et, const int32_t *__restrict__ start,
+         const int32_t *__restrict__ ntap, const float *__restrict__ w, int32_t wmode, int32_t K,
+         int32_t nchan, int32_t ndm, const XT *__restrict__ x, int64_t in_stride,
+         int64_t in_bstride, int32_t nbatch, int64_t nout, float *__restrict__ out) {
+  const int e = blockIdx.x, tid = threadIdx.x;
+  if (eb[e] < 0 || eb[e] >= nbatch || ed[e] < 0 || ed[e] >= ndm || et[e] < 0 || et[e] >= nout) {
+    if (tid == 0) out[e] = __builtin_nanf("");
+    return;
+  }
+  double acc = 0.0;
+  for (int c = tid; c < nchan; c += 64) {
+    const int64_t s = start[(int64_t)ed[e] * nchan + c];
+    const int n = ntap[(int64_t)ed[e] * nchan + c];
+    const XT *xr = x + (int64_t)eb[e] * in_bstride + (int64_t)c * in_stride + et[e] + s;
+    for (int k = 0; k < n; ++k) {
+      const double wk = wmode == DEDISP_W_TAP ? (double)w[(int64_t)c * K + k]
+                        : wmode == DEDISP_W_CHANNEL ? (double)w[c] : 1.0;
+      acc += wk * (double)xr[k];
+    }
+  }
+  __shared__ double red[64];
+  red[tid] = acc;
+  __syncthreads();
+  for (int off = 32; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) out[e] = (float)red[0];
+}
+
+inline dim3 grid3(int64_t n, int y, int z) {
+  return dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)y, (unsigned)z);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------------------
+hipError_t launch_prefix_u8(const uint8_t *x, int64_t in_stride, int64_t in_bstride, int32_t nchan,
+                            int32_t nbatch, int64_t nsamp, int32_t *P, hipStream_t s) {
+  const int64_t pstride = nsamp + 1;
+  hipLaunchKernelGGL(k_prefix_u8, dim3(nchan, nbatch), dim3(kThreads), 0, s, x, in_stride,
+                     in_bstride, nsamp, P, pstride, pstride * nchan);
+  return hipGetLastError();
+}
+
+hipError_t launch_dedisp_prefix(const dedisp_plan_s *p, const int32_t *P, int64_t pstride,
+                                int64_t pbstride, int32_t nbatch, int64_t nout, void *y,
+                                int32_t out_dtype, int64_t out_stride, int64_t out_bstride,
+                                hipStream_t s) {
+  const dim3 g = grid3(nout, p->ndm, nbatch);
+  if (p->wmode == DEDISP_W_CHANNEL) {
+    hipLaunchKernelGGL((k_dedisp_prefix<true, float>), g, dim3(kThreads), 0, s, P, pstride,
+                       pbstride, p->dev.start, p->dev.ntap, weights_of(p), p->nchan, nout,
+                       (float *)y, out_stride, out_bstride);
+  } else if (out_dtype == DEDISP_I32) {
+    hipLaunchKernelGGL((k_dedisp_prefix<false, int32_t>), g, dim3(kThreads), 0, s, P, pstride,
+                       pbstride, p->dev.start, p->dev.ntap, nullptr, p->nchan, nout,
+                       (int32_t *)y, out_stride, out_bstride);
+  } else {
+    hipLaunchKernelGGL((k_dedisp_prefix<false, float>), g, dim3(kThreads), 0, s, P, pstride,
+                       pbstride, p->dev.start, p->dev.ntap, nullptr, p->nchan, nout, (float *)y,
+                       out_stride, out_bstride);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dedisp_direct_f32(const dedisp_plan_s *p, const float *x, int64_t in_stride,
+                                    int64_t in_bstride, int32_t nbatch, int64_t nout, float *y,
+                                    int64_t out_stride, int64_t out_bstride, hipStream_t s) {
+  const dim3 g = grid3(nout, p->ndm, nbatch);
+  if (p->wmode == DEDISP_W_CHANNEL)
+    hipLaunchKernelGGL(k_dedisp_direct_f32<true>, g, dim3(kThreads), 0, s, x, in_stride,
+                       in_bstride, p->dev.start, p->dev.ntap, weights_of(p), p->nchan, nout, y,
+                       out_stride, out_bstride);
+  else
+    hipLaunchKernelGGL(k_dedisp_direct_f32<false>, g, dim3(kThreads), 0, s, x, in_stride,
+                       in_bstride, p->dev.start, p->dev.ntap, nullptr, p->nchan, nout, y,
+                       out_stride, out_bstride);
+  return hipGetLastError();
+}
+
+hipError_t launch_fir_f32(const dedisp_plan_s *p, const float *x, int64_t in_stride,
+                          int64_t in_bstride, int32_t nbatch, int64_t nz, float *z,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_fir_f32, grid3(nz, p->nchan, nbatch), dim3(kThreads), 0, s, x, in_stride,
+                     in_bstride, weights_of(p), p->ktaps, nz, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_dedisp_1tap_f32(const dedisp_plan_s *p, const float *z, int64_t zstride,
+                                  int64_t zbstride, int32_t nbatch, int64_t nout, float *y,
+                                  int64_t out_stride, int64_t out_bstride, hipStream_t s) {
+  hipLaunchKernelGGL(k_dedisp_1tap_f32, grid3(nout, p->ndm, nbatch), dim3(kThreads), 0, s, z,
+                     zstride, zbstride, p->dev.start, p->nchan, nout, y, out_stride, out_bstride);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm(const dedisp_plan_s *p, const WidthList &wl, const double *mu,
+                       const double *sigma, double *M, double *S, hipStream_t s) {
+  const int64_t n = (int64_t)p->ndm * wl.n;
+  hipLaunchKernelGGL(k_norm, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                     p->dev.ntap, p->nchan, p->ndm, p->wmode, p->ktaps, weights_of(p), mu, sigma,
+                     wl, M, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_boxcar(const dedisp_plan_s *p, const void *y, int32_t y_dtype, int64_t nout,
+                         int64_t y_stride, const WidthList &wl, const double *M, const double *S,
+                         void *partials, int32_t nchunk, hipStream_t s) {
+  const dim3 g((unsigned)nchunk, (unsigned)p->ndm);
+  if (y_dtype == DEDISP_I32)
+    hipLaunchKernelGGL(k_boxcar<int32_t>, g, dim3(kBoxChunk), 0, s, (const int32_t *)y, nout,
+                       y_stride, wl, M, S, (Cand *)partials, nchunk);
+  else
+    hipLaunchKernelGGL(k_boxcar<float>, g, dim3(kBoxChunk), 0, s, (const float *)y, nout,
+                       y_stride, wl, M, S, (Cand *)partials, nchunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(int32_t ndm, int32_t nchunk, const void *partials, double *snr,
+                         int32_t *t, int32_t *w, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(ndm), dim3(kThreads), 0, s, ndm, nchunk,
+                     (const Cand *)partials, snr, t, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_z(const dedisp_plan_s *p, const float *g, int64_t nout, int64_t gstride,
+                            int64_t gbstride, int32_t nbatch, int64_t nz, float *z,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_adjoint_z, grid3(nz, p->nchan, nbatch), dim3(kThreads), 0, s, g, nout,
+                     gstride, gbstride, p->dev.start, p->nchan, p->ndm, nz, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_w_tap(const dedisp_plan_s *p, const float *z, int64_t nz, const void *x,
+                             int32_t in_dtype, int64_t in_stride, int64_t in_bstride,
+                             int32_t nbatch, double *gw, hipStream_t s) {
+  if (in_dtype == DEDISP_F32)
+    hipLaunchKernelGGL(k_grad_w_tap<float>, dim3(p->nchan), dim3(kThreads), 0, s, z, nz,
+                       (const float *)x, in_stride, in_bstride, nbatch, p->nchan, p->ktaps, gw);
+  else
+    hipLaunchKernelGGL(k_grad_w_tap<uint8_t>, dim3(p->nchan), dim3(kThreads), 0, s, z, nz,
+                       (const uint8_t *)x, in_stride, in_bstride, nbatch, p->nchan, p->ktaps, gw);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_x_tap(const dedisp_plan_s *p, const float *z, int64_t nz, int64_t nsamp,
+                             int32_t nbatch, float *gx, int64_t in_stride, int64_t in_bstride,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_x_tap, grid3(nsamp, p->nchan, nbatch), dim3(kThreads), 0, s, z, nz,
+                     weights_of(p), p->ktaps, nsamp, p->nchan, gx, in_stride, in_bstride);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_direct(const dedisp_plan_s *p, const float *g, int64_t nout,
+                                 int64_t gstride, int64_t gbstride, int32_t nbatch, const void *x,
+                                 int32_t in_dtype, int64_t nsamp, int64_t in_stride,
+                                 int64_t in_bstride, float *gx, double *gw, hipStream_t s) {
+  if (gx)
+    hipLaunchKernelGGL(k_grad_x_direct, grid3(nsamp, p->nchan, nbatch), dim3(kThreads), 0, s, g,
+                       nout, gstride, gbstride, p->dev.start, p->dev.ntap,
+                       p->wmode == DEDISP_W_CHANNEL ? weights_of(p) : nullptr, p->nchan, p->ndm,
+                       nsamp, gx, in_stride, in_bstride);
+  if (gw) {
+    if (in_dtype == DEDISP_F32)
+      hipLaunchKernelGGL(k_grad_w_channel<float>, dim3(p->nchan), dim3(kThreads), 0, s, g, nout,
+                         gstride, gbstride, p->dev.start, p->dev.ntap, p->nchan, p->ndm, nbatch,
+                         (const float *)x, in_stride, in_bstride, gw);
+    else
+      hipLaunchKernelGGL(k_grad_w_channel<uint8_t>, dim3(p->nchan), dim3(kThreads), 0, s, g, nout,
+                         gstride, gbstride, p->dev.start, p->dev.ntap, p->nchan, p->ndm, nbatch,
+                         (const uint8_t *)x, in_stride, in_bstride, gw);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sparse_grad_w(const dedisp_plan_s *p, int32_t nnz, const int32_t *b,
+                                const int32_t *d, const int32_t *t, const float *val,
+                                const void *x, int32_t in_dtype, int64_t in_stride,
+                                int64_t in_bstride, int32_t nbatch, int64_t nout, double *gw,
+                                hipStream_t s) {
+  const int K = p->ktaps;
+  const int tapmode = p->wmode == DEDISP_W_TAP;
+  const int n = p->nchan * K;
+  const dim3 g((unsigned)((n + kThreads - 1) / kThreads));
+  if (in_dtype == DEDISP_F32)
+    hipLaunchKernelGGL(k_sparse_grad_w<float>, g, dim3(kThreads), 0, s, nnz, b, d, t, val,
+                       p->dev.start, p->dev.ntap, p->nchan, p->ndm, K, tapmode, (const float *)x,
+                       in_stride, in_bstride, nbatch, nout, gw);
+  else
+    hipLaunchKernelGGL(k_sparse_grad_w<uint8_t>, g, dim3(kThreads), 0, s, nnz, b, d, t, val,
+                       p->dev.start, p->dev.ntap, p->nchan, p->ndm, K, tapmode,
+                       (const uint8_t *)x, in_stride, in_bstride, nbatch, nout, gw);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const dedisp_plan_s *p, int32_t nnz, const int32_t *b, const int32_t *d,
+                         const int32_t *t, const void *x, int32_t in_dtype, int64_t in_stride,
+                         int64_t in_bstride, int32_t nbatch, int64_t nout, float *out,
+                         hipStream_t s) {
+  if (in_dtype == DEDISP_F32)
+    hipLaunchKernelGGL(k_gather<float>, dim3(nnz), dim3(64), 0, s, nnz, b, d, t, p->dev.start,
+                       p->dev.ntap, weights_of(p), p->wmode, p->ktaps, p->nchan, p->ndm,
+                       (const float *)x, in_stride, in_bstride, nbatch, nout, out);
+  else
+    hipLaunchKernelGGL(k_gather<uint8_t>, dim3(nnz), dim3(64), 0, s, nnz, b, d, t, p->dev.start,
+                       p->dev.ntap, weights_of(p), p->wmode, p->ktaps, p->nchan, p->ndm,
+                       (const uint8_t *)x, in_stride, in_bstride, nbatch, nout, out);
+  return hipGetLastError();
+}
+
+}  // namespace dd

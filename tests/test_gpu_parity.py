@@ -1,0 +1,205 @@
+"""Parity of the HIP library (through the C ABI) with the CPU oracle.
+
+uint8 data with unit weights must match bit for bit (int32 sums, exact detection
+indices, S/N within 1e-12 relative since both sides evaluate (B - M)/S in fp64
+from the same integers).  fp32 paths are held to the tolerances derived in the
+design notes: all-positive sums within 1e-5 relative of fp64, mixed-sign sums
+within 1e-5 of the sum of absolute terms.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import torch  # noqa: F401
+    import paper_1301_3968_amd as dd
+    return dd
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _check_detect(orc, y64, n, widths, mu, sg, snr, t, W, wmode="unit", w=None):
+    M, S = orc.boxcar_norm(n, widths, mu, sg, wmode, w)
+    so, to, wo = orc.boxcar_detect(y64, widths, M, S)
+    snr, t, W = snr.cpu().numpy(), t.cpu().numpy(), W.cpu().numpy()
+    assert np.allclose(snr, so, rtol=1e-12, atol=0)
+    mism = np.nonzero((t != to) | (W != wo))[0]
+    for d in mism:
+        # Accept only a near-tie: the oracle's S/N at the GPU's (t, W) equals its best.
+        j = list(widths).index(W[d])
+        B = float(np.sum(y64[d, t[d]:t[d] + W[d]]))
+        alt = (B - M[d, j]) / S[d, j]
+        assert alt == pytest.approx(so[d], rel=1e-12), (d, t[d], W[d], to[d], wo[d])
+
+
+def test_cfg1_full(dd, orc):
+    wl = workloads.cfg1()
+    p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule=wl.rule)
+    s, n = p.tables()
+    x = _dev(wl.x)
+    y = p.dedisperse(x)
+    yo = orc.dedisperse_u8(wl.x, s, n)
+    assert np.array_equal(y.cpu().numpy().astype(np.int64), yo)
+    snr, t, W = p.search(x, wl.widths, wl.chan_mean, wl.chan_sigma)
+    _check_detect(orc, yo.astype(np.float64), n, wl.widths, wl.chan_mean, wl.chan_sigma, snr, t, W)
+    snr2, t2, W2 = p.detect(y, wl.widths, wl.chan_mean, wl.chan_sigma)
+    assert np.array_equal(snr.cpu().numpy(), snr2.cpu().numpy())
+    assert np.array_equal(t.cpu().numpy(), t2.cpu().numpy())
+    d = int(np.argmax(snr.cpu().numpy()))
+    assert abs(wl.dms[d] - 100.0) <= 10.0
+
+
+@pytest.mark.parametrize("rule", ["allnonzero", "smear"])
+def test_cfg2_reduced_all_outputs(dd, orc, rule):
+    # Several DM tiles and a ragged time tail: 96 trials over 4000 + 2246 samples.
+    wl = workloads.cfg2(nsamp=6246, ndm=96, rule=rule)
+    p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule=rule)
+    s, n = p.tables()
+    x = _dev(wl.x)
+    y = p.dedisperse(x)
+    yo = orc.dedisperse_u8(wl.x, s, n)
+    assert np.array_equal(y.cpu().numpy().astype(np.int64), yo)
+    snr, t, W = p.search(x, wl.widths, wl.chan_mean, wl.chan_sigma)
+    _check_detect(orc, yo.astype(np.float64), n, wl.widths, wl.chan_mean, wl.chan_sigma, snr, t, W)
+
+
+def test_cfg2_full_size_sampled_trials(dd, orc):
+    # Full 336 x 65536 block and 1024 trials; the oracle recomputes 6 whole trials.
+    wl = workloads.cfg2()
+    p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule=wl.rule)
+    s, n = p.tables()
+    x = _dev(wl.x)
+    snr, t, W = p.search(x, wl.widths, wl.chan_mean, wl.chan_sigma)
+    pick = np.array([0, 1, 257, 512, 1000, 1023])
+    yo = orc.dedisperse_u8(wl.x, s[pick], n[pick], tout=wl.x.shape[1] - p.max_span + 1)
+    import torch
+    _check_detect(orc, yo.astype(np.float64), n[pick], wl.widths, wl.chan_mean, wl.chan_sigma,
+                  snr[torch.as_tensor(pick).cuda()], t[torch.as_tensor(pick).cuda()],
+                  W[torch.as_tensor(pick).cuda()])
+    y = p.dedisperse(x)
+    assert np.array_equal(y[torch.as_tensor(pick).cuda()].cpu().numpy().astype(np.int64), yo)
+    # The strongest injected pulses are found near their DM.
+    sn = snr.cpu().numpy()
+    for pl in wl.pulses[:4]:
+        d = int(np.argmin(np.abs(wl.dms - pl.dm)))
+        lo, hi = max(0, d - 3), min(len(wl.dms), d + 4)
+        assert sn[lo:hi].max() > 6.0
+
+
+def test_cfg3_channel_weights_fp32(dd, orc):
+    wl = workloads.cfg3(nsamp=20000, ndm=40)
+    p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule=wl.rule, wmode="channel",
+                weights=wl.weights)
+    s, n = p.tables()
+    y = p.dedisperse(_dev(wl.x)).cpu().numpy()
+    yo = orc.dedisperse_f64(wl.x, s, n, "channel", wl.weights)
+    rel = np.abs(y - yo) / np.abs(yo)
+    assert rel.max() < 1e-5
+
+
+def test_cfg3_full_size_sampled_points(dd, orc):
+    import torch
+    wl = workloads.cfg3(nsamp=262144, ndm=4096)
+    p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule=wl.rule, wmode="channel",
+                weights=wl.weights)
+    s, n = p.tables()
+    x = _dev(wl.x)
+    y = p.dedisperse(x)
+    rng = np.random.default_rng(99)
+    nout = y.shape[1]
+    dd_ = rng.integers(0, 4096, 64)
+    tt = rng.integers(0, nout, 64)
+    tt[:2] = [0, nout - 1]
+    got = y[torch.as_tensor(dd_).cuda(), torch.as_tensor(tt).cuda()].cpu().numpy()
+    ref = orc.dedisperse_points(wl.x, s, n, np.zeros(64), dd_, tt, "channel", wl.weights)
+    assert (np.abs(got - ref) / np.abs(ref)).max() < 1e-5
+
+
+def _tap_case(B=3, T=3000, D=24, C=40, K=8):
+    rng = np.random.default_rng(1234)
+    f = workloads.channel_centres(1.2, 0.336 * C / 336, C)
+    dms = np.linspace(0, 300, D)
+    x = rng.standard_normal((B, C, T)).astype(np.float32)
+    w = (1.0 + 0.1 * rng.standard_normal((C, K))).astype(np.float32)
+    return f, dms, x, w
+
+
+def test_tap_weights_forward_and_backward(dd, orc):
+    f, dms, x, w = _tap_case()
+    B, C, T = x.shape
+    K = w.shape[1]
+    p = dd.Plan(f, 0.001, 1e-3, dms, rule="fixed", ktaps=K, wmode="tap", weights=w)
+    s, n = p.tables()
+    xd = _dev(x)
+    y = p.dedisperse(xd).cpu().numpy()
+    yo = orc.dedisperse_f64(x, s, n, "tap", w)
+    l1 = orc.dedisperse_f64(np.abs(x), s, n, "tap", np.abs(w))
+    assert (np.abs(y - yo) / l1).max() < 1e-5
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal(y.shape).astype(np.float32)
+    gx, gw = p.backward(_dev(g), xd)
+    gwo = orc.adjoint_w(x, s, n, g.astype(np.float64), "tap", K)
+    gxo = orc.adjoint_x(T, s, n, g.astype(np.float64), "tap", w)
+    gw = gw.cpu().numpy()
+    scale = np.maximum(np.abs(gwo), 1e-3 * np.abs(gwo).max())
+    assert (np.abs(gw - gwo) / scale).max() < 1e-5
+    gxl1 = orc.adjoint_x(T, s, n, np.abs(g).astype(np.float64), "tap", np.abs(w))
+    gx = gx.cpu().numpy()
+    ok = gxl1 > 0
+    assert (np.abs(gx - gxo)[ok] / gxl1[ok]).max() < 1e-5
+    assert np.all(gx[~ok] == 0)
+    # Sparse path: gradient of sum_e val_e y[b_e, d_e, t_e].
+    bb = np.array([0, 1, 2, 2]); d_ = np.array([3, 0, 23, 10]); tt = np.array([5, 100, 0, y.shape[2] - 1])
+    val = np.array([1.0, -2.0, 0.5, 3.0], np.float32)
+    gs = p.backward_sparse(xd, bb, d_, tt, _dev(val)).cpu().numpy()
+    gdense = np.zeros(y.shape)
+    np.add.at(gdense, (bb, d_, tt), val.astype(np.float64))
+    gso = orc.adjoint_w(x, s, n, gdense, "tap", K)
+    assert np.allclose(gs, gso, rtol=1e-12, atol=1e-12)
+    got = p.gather(xd, bb, d_, tt).cpu().numpy()
+    ref = orc.dedisperse_points(x, s, n, bb, d_, tt, "tap", w)
+    assert np.allclose(got, ref, rtol=2e-7, atol=1e-6)
+
+
+def test_edge_cases(dd, orc):
+    rng = np.random.default_rng(77)
+    # Descending channel order, a channel with ntap = 0, nout = 1 and a single trial.
+    C = 5
+    f = workloads.channel_centres(1.2, 0.05, C)[::-1].copy()
+    s = rng.integers(0, 7, size=(3, C)).astype(np.int32)
+    n = rng.integers(0, 4, size=(3, C)).astype(np.int32)
+    n[1, 2] = 0
+    span = int(np.max(s + n))
+    p = dd.Plan(f, 0.01, 1e-3, [0.0, 1.0, 2.0], rule="explicit", start=s, ntap=n)
+    for T in (span, span + 1, span + 255, span + 257):
+        x = rng.integers(0, 256, size=(C, T), dtype=np.uint8)
+        y = p.dedisperse(_dev(x)).cpu().numpy()
+        assert np.array_equal(y.astype(np.int64), orc.dedisperse_u8(x, s, n))
+        widths = [1] if T - span + 1 < 3 else [1, 2, 3]
+        snr, t, W = p.search(_dev(x), widths, np.full(C, 100.0), np.full(C, 10.0))
+        yo = orc.dedisperse_u8(x, s, n).astype(np.float64)
+        _check_detect(orc, yo, n, widths, np.full(C, 100.0), np.full(C, 10.0), snr, t, W)
+    with pytest.raises(dd.DedispError):
+        p.dedisperse(_dev(rng.integers(0, 256, size=(C, span - 1), dtype=np.uint8)))
+    # One channel, one trial.
+    p1 = dd.Plan([1.4], 0.01, 1e-3, [0.0])
+    x = rng.integers(0, 256, size=(1, 33), dtype=np.uint8)
+    assert np.array_equal(p1.dedisperse(_dev(x)).cpu().numpy()[0], x[0].astype(np.int32))
+
+
+def test_deterministic(dd):
+    wl = workloads.cfg2(nsamp=5000, ndm=64)
+    p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule=wl.rule)
+    x = _dev(wl.x)
+    a = p.search(x, wl.widths, wl.chan_mean, wl.chan_sigma)
+    b = p.search(x, wl.widths, wl.chan_mean, wl.chan_sigma)
+    for u, v in zip(a, b):
+        assert np.array_equal(u.cpu().numpy(), v.cpu().numpy())

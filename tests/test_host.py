@@ -1,0 +1,134 @@
+"""Host-side checks of libdedisp (no GPU needed): exported symbols, plan tables
+against the oracle's independent tables, the trial-DM rule, and error paths."""
+import ctypes
+import re
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import paper_1301_3968_amd as dd
+    return dd
+
+
+def test_exports_every_declared_symbol(dd):
+    from paper_1301_3968_amd import _lib
+    with open(os.path.join(ROOT, "include", "dedisp.h")) as f:
+        hdr = f.read()
+    declared = set(re.findall(r"\b(dedisp_[a-z_]+)\s*\(", hdr))
+    declared.discard("dedisp_plan_s")
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared == set(_lib.EXPORTS)
+
+
+CASES = [
+    ("cfg1", lambda: workloads.channel_centres(1.2, 0.3, 64), 0.3 / 64, 1e-3, np.arange(32) * 10.0),
+    ("cfg2", lambda: workloads.channel_centres(1.2, 0.336, 336), 1e-3, 1e-3, np.linspace(0, 2000, 1024)),
+    ("cfg3", lambda: workloads.channel_centres(1.2, 0.3, 4096), 0.3 / 4096, 64e-6, np.linspace(0, 1000, 4096)),
+]
+
+
+@pytest.mark.parametrize("name,fgen,bw,dt,dms", CASES)
+@pytest.mark.parametrize("kdm", [0.0, 4.15e-3])
+def test_tables_match_oracle(dd, orc, name, fgen, bw, dt, dms, kdm):
+    f = fgen()
+    K = kdm if kdm > 0 else orc.KDM_PAPER
+    so = orc.delay_start(f, bw, dt, dms, K)
+    for rule in ("smear", "allnonzero"):
+        p = dd.Plan(f, bw, dt, dms, rule=rule, k_dm=kdm)
+        s, n = p.tables()
+        no = orc.taps_smear(f, bw, dt, dms, K) if rule == "smear" else orc.taps_allnonzero(f, bw, dt, dms, kdm=K)
+        bad = np.argwhere((s != so) | (n != no))
+        assert bad.size == 0, f"{name} {rule}: first mismatch at {bad[:3]}"
+        assert p.max_span == int(np.max(so + no))
+
+
+def test_allnonzero_with_width_and_scatter(dd, orc):
+    f = workloads.channel_centres(1.2, 0.336, 336)
+    dms = np.linspace(0, 2000, 257)
+    p = dd.Plan(f, 1e-3, 1e-3, dms, rule="allnonzero", width_s=2.5e-3, scatter_s_1ghz=1e-3)
+    s, n = p.tables()
+    no = orc.taps_allnonzero(f, 1e-3, 1e-3, dms, 2.5e-3, 1e-3, -4.0)
+    assert np.array_equal(n, no)
+    assert np.array_equal(s, orc.delay_start(f, 1e-3, 1e-3, dms))
+
+
+def test_descending_channels(dd, orc):
+    f = workloads.channel_centres(1.2, 0.336, 336)[::-1].copy()
+    dms = np.linspace(0, 2000, 64)
+    p = dd.Plan(f, 1e-3, 1e-3, dms, rule="allnonzero")
+    s, n = p.tables()
+    assert np.array_equal(s, orc.delay_start(f, 1e-3, 1e-3, dms))
+    assert np.array_equal(n, orc.taps_allnonzero(f, 1e-3, 1e-3, dms))
+
+
+@pytest.mark.parametrize("flo,bw,C,dt,eps,lo,hi,count", [
+    (0.7, 0.304, 304, 1e-3, 1.492, 10, 3000, 442),
+    (21.0, 2.0, 256, 1e-4, 0.580, 50, 10000, 128),
+    (21.0, 2.0, 32, 1e-4, 0.287, 50, 10000, 128),
+])
+def test_trial_dms_match_oracle(dd, orc, flo, bw, C, dt, eps, lo, hi, count):
+    f = workloads.channel_centres(flo, bw, C)
+    a = dd.trial_dms(lo, hi, eps, f, bw / C, dt)
+    b = orc.trial_dms(lo, hi, eps, f, bw / C, dt)
+    assert len(a) == len(b) == count
+    assert np.allclose(a, b, rtol=1e-12, atol=0)
+    a2 = dd.trial_dms(lo, hi, eps, f, bw / C, dt, tau_av_s=dt, include_dm_tau=True)
+    b2 = orc.trial_dms(lo, hi, eps, f, bw / C, dt, tau_av_s=dt, include_dm_tau=True)
+    assert len(a2) == len(b2) and np.allclose(a2, b2, rtol=1e-12)
+
+
+def test_greedy_rule_matches_oracle_objective(dd, orc):
+    # Section 2.2 selection on a small band: same set sizes and S/N objective.
+    f = workloads.channel_centres(0.7, 0.032, 8)
+    dms = np.array([0.0, 30.0, 120.0, 400.0])
+    kw = dict(width_s=1e-3)
+    p = dd.Plan(f, 0.004, 1e-3, dms, rule="greedy", **kw)
+    s, n = p.tables()
+    so, no, obj = orc.greedy_tables(f, 0.004, 1e-3, dms, 1e-3)
+    assert np.array_equal(n.sum(axis=1), no.sum(axis=1))
+    ft, fl, fh = orc.channel_edges(f, 0.004)
+    for d in range(len(dms)):
+        vals = [orc.cell_power_rect(j * 1e-3, 1e-3, fl[c], ft[c], dms[d], 1e-3, nu_top=fh)
+                for c in range(len(f)) for j in range(s[d, c], s[d, c] + n[d, c])]
+        got = sum(vals) / np.sqrt(len(vals))
+        assert got == pytest.approx(obj[d], rel=1e-9)
+
+
+def test_errors(dd):
+    from paper_1301_3968_amd import _lib
+    f = workloads.channel_centres(1.2, 0.336, 8)
+    with pytest.raises(dd.DedispError) as e:
+        dd.Plan(f, -1.0, 1e-3, [0.0])
+    assert e.value.status == _lib.ERR_INVALID_ARG
+    with pytest.raises(dd.DedispError) as e:
+        dd.Plan(f, 1e-3, 1e-3, [float("nan")])
+    assert e.value.status == _lib.ERR_INVALID_ARG
+    with pytest.raises(dd.DedispError) as e:
+        dd.Plan(f, 1e-3, 1e-3, [-5.0])
+    assert e.value.status == _lib.ERR_INVALID_ARG
+    p = dd.Plan(f, 1e-3, 1e-3, [0.0, 500.0])
+    with pytest.raises(dd.DedispError) as e:
+        p.out_len(p.max_span - 1)
+    assert e.value.status == _lib.ERR_SHAPE
+    assert p.out_len(p.max_span) == 1
+    with pytest.raises(dd.DedispError) as e:
+        dd.Plan(f, 1e-3, 1e-3, [0.0], rule="tap" if False else "fixed", ktaps=0)
+    assert e.value.status == _lib.ERR_INVALID_ARG
+    s = np.zeros((1, 8), np.int32)
+    n = np.full((1, 8), 3, np.int32)
+    with pytest.raises(dd.DedispError) as e:
+        dd.Plan(f, 1e-3, 1e-3, [0.0], rule="explicit", start=s, ntap=n, wmode="tap", ktaps=4,
+                weights=np.ones((8, 4), np.float32))
+    assert e.value.status == _lib.ERR_UNSUPPORTED
+    # The thread-local message describes the failure.
+    assert b"ntap" in _lib.lib().dedisp_last_error()
