@@ -231,6 +231,10 @@ static dedisp_status build_tables(dedisp_plan p) {
       }
     }
   }
+  // An empty run contributes nothing; store it at start 0 so that no kernel
+  // ever forms an address from its (irrelevant) start.
+  for (size_t i = 0; i < p->ntap.size(); ++i)
+    if (p->ntap[i] == 0) p->start[i] = 0;
   int32_t span = 0, nmax = 0, smin = INT32_MAX;
   int64_t summax = 0;
   for (int32_t c = 0; c < C; ++c) {
