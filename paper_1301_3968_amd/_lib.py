@@ -23,7 +23,7 @@ EXPORTS = [
     "dedisp_detect", "dedisp_search", "dedisp_dedisperse_backward", "dedisp_backward_sparse",
     "dedisp_dedisperse_gather", "dedisp_trial_dms", "dedisp_batch_create", "dedisp_batch_destroy",
     "dedisp_batch_work_bytes", "dedisp_batch_run", "dedisp_batch_info", "dedisp_autotune",
-    "dedisp_set_tile", "dedisp_set_kernel_events", "dedisp_status_string", "dedisp_last_error",
+    "dedisp_set_tile", "dedisp_last_search_tile", "dedisp_set_kernel_events", "dedisp_status_string", "dedisp_last_error",
 ]
 
 
@@ -85,6 +85,7 @@ def lib():
         "dedisp_autotune": [P, P, i64, i64, P, i32, P, P, P, sz, P, P],
         "dedisp_set_tile": [P, i32],
         "dedisp_set_kernel_events": [P, P, P, i32],
+        "dedisp_last_search_tile": [P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)

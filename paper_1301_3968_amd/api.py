@@ -243,6 +243,15 @@ class Plan:
     def set_tile(self, tile: int) -> None:
         L.check(L.lib().dedisp_set_tile(self._h, tile))
 
+    def last_search_tile(self) -> int:
+        """Tile configuration of the fused kernel used by the last search (-1: unfused)."""
+        v = ctypes.c_int32()
+        L.check(L.lib().dedisp_last_search_tile(self._h, ctypes.byref(v)))
+        return v.value
+
+    def fused_search(self) -> bool:
+        return self.last_search_tile() >= 0
+
     def set_kernel_events(self, starts, stops) -> None:
         """Record torch.cuda.Event pairs around the dominant kernel of each search call
         (cycling over the pairs).  Events must already have been recorded once so that

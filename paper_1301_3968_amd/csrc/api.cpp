@@ -184,10 +184,12 @@ dedisp_status dedisp_search(dedisp_plan p, const void *d_in, int32_t in_dtype, i
   if (work_bytes < need) return fail(DEDISP_ERR_INVALID_ARG, "workspace too small");
   if ((st = dd::ensure_device(p)) != DEDISP_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  if (in_dtype == DEDISP_U8 && p->wmode == DEDISP_W_UNIT && dd::search_supported(p, wl)) {
-    return dd::run_search_tiled(p, (const uint8_t *)d_in, nsamp, in_stride, nout, wl, d_chan_mean,
-                                d_chan_sigma, d_snr, d_t, d_w, d_work, s);
+  if (in_dtype == DEDISP_U8 && p->tile_choice != -2 && dd::search_supported(p, wl)) {
+    st = dd::run_search_tiled(p, (const uint8_t *)d_in, nsamp, in_stride, nout, wl, d_chan_mean,
+                              d_chan_sigma, d_snr, d_t, d_w, d_work, s);
+    if (st != DEDISP_ERR_UNSUPPORTED) return st;   // unsupported shapes fall through
   }
+  p->last_search_tile = -1;
   // General path: materialise y in a stream-ordered temporary, then detect.
   const int32_t ydt = (in_dtype == DEDISP_U8 && p->wmode == DEDISP_W_UNIT) ? DEDISP_I32 : DEDISP_F32;
   void *y = nullptr;
@@ -257,6 +259,12 @@ dedisp_status dedisp_backward_sparse(dedisp_plan p, int32_t nnz, const int32_t *
   if ((st = dd::ensure_device(p)) != DEDISP_OK) return st;
   DD_HIP(dd::launch_sparse_grad_w(p, nnz, d_b, d_d, d_t, d_val, d_in, in_dtype, in_stride,
                                   in_bstride, nbatch, nout, d_grad_w, (hipStream_t)stream));
+  return DEDISP_OK;
+}
+
+dedisp_status dedisp_last_search_tile(dedisp_plan p, int32_t *tile) {
+  if (!p || !tile) return fail(DEDISP_ERR_INVALID_ARG, "null argument");
+  *tile = p->last_search_tile;
   return DEDISP_OK;
 }
 

@@ -55,7 +55,8 @@ struct dedisp_plan_s {
   int32_t min_start = 0;
   int32_t max_ntap = 0;
   int64_t sum_max_ntap = 0;             // sum_c max_d ntap[d,c]
-  int32_t tile_choice = -1;             // forced / tuned tile configuration
+  int32_t tile_choice = -1;             // forced / tuned tile configuration (-2: general path)
+  int32_t last_search_tile = -1;        // tile configuration of the last search (-1: general)
 
   // Device copies, uploaded on first use (per plan, on the current device).
   std::mutex mu;

@@ -153,48 +153,68 @@ k_dedisp_1tap_f32(const float *__restrict__ z, int64_t zstride, int64_t zbstride
 // Boxcar noise statistics: M[d][j], S[d][j] for width W_j (eqs. P_N_dedisp and snr
 // extended to W consecutive outputs).  a = (channel weight run) * box_W.
 // ----------------------------------------------------------------------------------
+__device__ __forceinline__ void norm_terms(int wmode, int K, const float *__restrict__ w, int c, int n,
+                                           int W, double &s1, double &s2) {
+  if (wmode == DEDISP_W_TAP) {
+    // explicit convolution of the tap weights with a length-W box
+    s1 = 0.0;
+    s2 = 0.0;
+    for (int tau = 0; tau < n + W - 1; ++tau) {
+      double a = 0.0;
+      const int k0 = max(0, tau - W + 1), k1 = min(n - 1, tau);
+      for (int k = k0; k <= k1; ++k) a += (double)w[(int64_t)c * K + k];
+      s1 += a;
+      s2 += a * a;
+    }
+  } else {
+    // n-box convolved with W-box: a trapezoid 1, 2, .., m, .., m, .., 2, 1
+    const int lo = min(n, W), hi = max(n, W);
+    const double ld = lo;
+    s1 = (double)n * (double)W;
+    s2 = 2.0 * ((ld - 1.0) * ld * (2.0 * ld - 1.0) / 6.0) + (double)(hi - lo + 1) * ld * ld;
+    if (wmode == DEDISP_W_CHANNEL) {
+      const double wc = (double)w[c];
+      s1 *= wc;
+      s2 *= wc * wc;
+    }
+  }
+}
+
+// One block per trial: channel terms summed by the block for every width.
 __global__ void __launch_bounds__(kThreads)
 k_norm(const int32_t *__restrict__ ntap, int32_t nchan, int32_t ndm, int32_t wmode, int32_t K,
        const float *__restrict__ w, const double *__restrict__ mu,
        const double *__restrict__ sigma, WidthList wl, double *__restrict__ M,
        double *__restrict__ S) {
-  const int idx = blockIdx.x * kThreads + threadIdx.x;
-  if (idx >= ndm * wl.n) return;
-  const int d = idx / wl.n, j = idx % wl.n;
-  const int W = wl.w[j];
-  double m = 0.0, v = 0.0;
-  for (int c = 0; c < nchan; ++c) {
-    const int n = ntap[(int64_t)d * nchan + c];
-    if (n == 0) continue;
-    double s1, s2;
-    if (wmode == DEDISP_W_TAP) {
-      // explicit convolution of the tap weights with a length-W box
-      s1 = 0.0;
-      s2 = 0.0;
-      for (int tau = 0; tau < n + W - 1; ++tau) {
-        double a = 0.0;
-        const int k0 = max(0, tau - W + 1), k1 = min(n - 1, tau);
-        for (int k = k0; k <= k1; ++k) a += (double)w[(int64_t)c * K + k];
-        s1 += a;
-        s2 += a * a;
-      }
-    } else {
-      // n-box convolved with W-box: a trapezoid 1, 2, .., m, .., m, .., 2, 1
-      const int lo = min(n, W), hi = max(n, W);
-      const double ld = lo;
-      s1 = (double)n * (double)W;
-      s2 = 2.0 * ((ld - 1.0) * ld * (2.0 * ld - 1.0) / 6.0) + (double)(hi - lo + 1) * ld * ld;
-      if (wmode == DEDISP_W_CHANNEL) {
-        const double wc = (double)w[c];
-        s1 *= wc;
-        s2 *= wc * wc;
-      }
+  const int d = blockIdx.x, tid = threadIdx.x;
+  __shared__ double rm[kThreads], rv[kThreads];
+  for (int j = 0; j < wl.n; ++j) {
+    const int W = wl.w[j];
+    double m = 0.0, v = 0.0;
+    for (int c = tid; c < nchan; c += kThreads) {
+      const int n = ntap[(int64_t)d * nchan + c];
+      if (n == 0) continue;
+      double s1, s2;
+      norm_terms(wmode, K, w, c, n, W, s1, s2);
+      m += mu[c] * s1;
+      v += sigma[c] * sigma[c] * s2;
     }
-    m += mu[c] * s1;
-    v += sigma[c] * sigma[c] * s2;
+    rm[tid] = m;
+    rv[tid] = v;
+    __syncthreads();
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+      if (tid < off) {
+        rm[tid] += rm[tid + off];
+        rv[tid] += rv[tid + off];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      M[(int64_t)d * wl.n + j] = rm[0];
+      S[(int64_t)d * wl.n + j] = sqrt(rv[0]);
+    }
+    __syncthreads();
   }
-  M[idx] = m;
-  S[idx] = sqrt(v);
 }
 
 struct Cand {
@@ -556,8 +576,7 @@ hipError_t launch_dedisp_1tap_f32(const dedisp_plan_s *p, const float *z, int64_
 
 hipError_t launch_norm(const dedisp_plan_s *p, const WidthList &wl, const double *mu,
                        const double *sigma, double *M, double *S, hipStream_t s) {
-  const int64_t n = (int64_t)p->ndm * wl.n;
-  hipLaunchKernelGGL(k_norm, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+  hipLaunchKernelGGL(k_norm, dim3((unsigned)p->ndm), dim3(kThreads), 0, s,
                      p->dev.ntap, p->nchan, p->ndm, p->wmode, p->ktaps, weights_of(p), mu, sigma,
                      wl, M, S);
   return hipGetLastError();

@@ -203,3 +203,32 @@ def test_deterministic(dd):
     b = p.search(x, wl.widths, wl.chan_mean, wl.chan_sigma)
     for u, v in zip(a, b):
         assert np.array_equal(u.cpu().numpy(), v.cpu().numpy())
+
+
+@pytest.fixture(scope="module")
+def cfg2_mid(orc):
+    wl = workloads.cfg2(nsamp=9000, ndm=100)
+    s = orc.delay_start(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms).astype(np.int32)
+    n = orc.taps_allnonzero(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms).astype(np.int32)
+    yo = orc.dedisperse_u8(wl.x, s, n).astype(np.float64)
+    return wl, n, yo
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, -2])
+def test_fused_search_every_tile_config(dd, orc, cfg2_mid, tile):
+    # Ragged in both DM (100 trials) and time (6755 outputs) for every tile shape.
+    wl, n, yo = cfg2_mid
+    p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule="allnonzero")
+    p.set_tile(tile)
+    snr, t, W = p.search(_dev(wl.x), wl.widths, wl.chan_mean, wl.chan_sigma)
+    assert p.last_search_tile() == (tile if tile >= 0 else -1)
+    _check_detect(orc, yo, n, wl.widths, wl.chan_mean, wl.chan_sigma, snr, t, W)
+
+
+def test_fused_search_sparse_widths(dd, orc, cfg2_mid):
+    wl, n, yo = cfg2_mid
+    p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule="allnonzero")
+    widths = [3, 32, 7]
+    snr, t, W = p.search(_dev(wl.x), widths, wl.chan_mean, wl.chan_sigma)
+    assert p.last_search_tile() >= 0
+    _check_detect(orc, yo, n, sorted(widths), wl.chan_mean, wl.chan_sigma, snr, t, W)
