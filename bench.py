@@ -71,6 +71,9 @@ def main() -> int:
     ap.add_argument("--rule", default="allnonzero", choices=["allnonzero", "smear"])
     ap.add_argument("--cpu-sample-trials", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (the reference kernel "
+                         "for scaling HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU layout "
@@ -80,10 +83,20 @@ def main() -> int:
     import numpy as np
     import torch
 
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3}))
+        return 0
+
     import paper_1301_3968_amd as dd
     import workloads
 
-    torch.cuda.set_device(0)
     print("generating the 336-channel workload", file=sys.stderr, flush=True)
     wl = workloads.cfg2(rule=args.rule)
     plan = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule=args.rule)

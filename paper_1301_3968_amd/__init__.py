@@ -9,6 +9,6 @@ from ._lib import DedispError
 
 _lib.lib()  # fail at import time when the HIP library is missing
 
-from .api import Plan, trial_dms  # noqa: E402
+from .api import Batch, Plan, trial_dms  # noqa: E402
 
-__all__ = ["Plan", "trial_dms", "DedispError"]
+__all__ = ["Batch", "Plan", "trial_dms", "DedispError"]

@@ -273,3 +273,79 @@ def trial_dms(dm0: float, dm_max: float, eps: float, freq_ghz, chan_bw_ghz: floa
     L.check(L.lib().dedisp_trial_dms(dm0, dm_max, eps, len(f), _ptr(f), chan_bw_ghz, dt_s, tau_av_s,
                                      int(include_dm_tau), k_dm, cap, _ptr(out), ctypes.byref(n)))
     return out[:n.value].copy()
+
+
+def _autotune(self, x: torch.Tensor, widths: Sequence[int], mean, sigma,
+              work: Optional[torch.Tensor] = None) -> int:
+    """Time every tile shape of the fused search on block x and keep the fastest
+    for this plan (cached in the file named by DEDISP_TUNE_CACHE, if set)."""
+    _dev_check(x, "x")
+    C, T = x.shape
+    w = self._widths(widths)
+    m, s = (mean, sigma) if isinstance(mean, torch.Tensor) else self._meansig(mean, sigma, x.device)
+    need = self.work_bytes(T, len(w))
+    if work is None or work.numel() < need:
+        work = torch.empty(need, dtype=torch.uint8, device=x.device)
+    chosen = ctypes.c_int32()
+    L.check(L.lib().dedisp_autotune(self._h, _ptr(x), T, x.stride(0), _ptr(w), len(w), _ptr(m),
+                                    _ptr(s), _ptr(work), work.numel(), _stream(),
+                                    ctypes.byref(chosen)))
+    return chosen.value
+
+
+Plan.autotune = _autotune
+
+
+class Batch:
+    """Many beams (each with its own plan and block length) searched by one
+    persistent launch; `run(..., graph=True)` replays a captured HIP graph."""
+
+    def __init__(self, plans: Sequence[Plan], nsamp: Sequence[int], widths: Sequence[int]):
+        self.plans = list(plans)
+        n = np.ascontiguousarray(nsamp, dtype=np.int64)
+        ps = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        w = np.ascontiguousarray(widths, dtype=np.int32)
+        h = ctypes.c_void_p()
+        L.check(L.lib().dedisp_batch_create(ctypes.byref(h), len(self.plans), ps, _ptr(n), _ptr(w),
+                                            len(w)))
+        self._h = h
+        self.widths = w
+        v = ctypes.c_size_t()
+        L.check(L.lib().dedisp_batch_work_bytes(h, ctypes.byref(v)))
+        self.work_bytes = v.value
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        L.check(L.lib().dedisp_batch_info(h, ctypes.byref(a), ctypes.byref(b)))
+        self.total_trials, self.total_sums = a.value, b.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            L.lib().dedisp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, xs: Sequence[torch.Tensor], mean: torch.Tensor, sigma: torch.Tensor,
+            work: Optional[torch.Tensor] = None, outputs=None, graph: bool = False):
+        """Best (snr, t, W) of every trial of every beam, concatenated in beam order."""
+        for x in xs:
+            _dev_check(x, "x")
+        dev = xs[0].device
+        ptrs = (ctypes.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        strides = np.ascontiguousarray([x.stride(0) for x in xs], dtype=np.int64)
+        if work is None or work.numel() < self.work_bytes:
+            work = torch.empty(self.work_bytes, dtype=torch.uint8, device=dev)
+        if outputs is None:
+            n = self.total_trials
+            outputs = (torch.empty(n, dtype=torch.float64, device=dev),
+                       torch.empty(n, dtype=torch.int32, device=dev),
+                       torch.empty(n, dtype=torch.int32, device=dev))
+        snr, t, W = outputs
+        self._keep = (xs, mean, sigma, work, outputs, ptrs, strides)
+        L.check(L.lib().dedisp_batch_run(self._h, ptrs, _ptr(strides), _ptr(mean), _ptr(sigma),
+                                         _ptr(snr), _ptr(t), _ptr(W), _ptr(work), work.numel(),
+                                         int(graph), _stream()))
+        return snr, t, W

@@ -42,15 +42,15 @@ struct TileCfg {
   int dpw;   // trials per wave (4 waves per workgroup)
   int r2;    // packed output pairs per lane per row: outputs per tile row = 128 * r2
 };
-static const TileCfg kCfgs[] = {{4, 8}, {8, 4}, {2, 8}, {4, 4}};
+static const TileCfg kCfgs[] = {{4, 6}, {4, 8}, {2, 8}, {8, 4}, {4, 4}, {3, 8}};
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 constexpr int kDefaultCfg = 0;
 constexpr int kHalo = 32;                 // boxcar widths up to 32
-constexpr int kStageBudget = 48 * 1024;   // LDS bytes for one channel group's windows
+constexpr int kStageBudget = 32 * 1024;   // LDS bytes for one channel group's windows
 
 struct GroupInfo {
   int32_t job_begin, njobs, lw, c_begin;   // lw: window length in samples (multiple of 8)
-  int32_t c_count, flush, pad0, pad1;
+  int32_t c_count, flush, inv_nchunk, pad1;   // inv_nchunk: bits of (float)(1 / (lw / 8))
 };
 
 struct TiledCfgTables {
@@ -177,25 +177,36 @@ struct CandRec {
   int32_t w;
 };
 
+// Maximum over the 64 lanes of a wave (uniform result): DPP row shifts reduce each
+// row of 16 lanes into its lane 15, two row broadcasts fold the rows into lane 63.
+__device__ __forceinline__ int wave_max_i32(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x111, 0xf, 0xf, false));   // row_shr:1
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x112, 0xf, 0xf, false));   // row_shr:2
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x114, 0xf, 0xf, false));   // row_shr:4
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x118, 0xf, 0xf, false));   // row_shr:8
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x142, 0xa, 0xf, false));   // row_bcast:15
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x143, 0xc, 0xf, false));   // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
 __device__ __forceinline__ int bitrev5(int v) {
   return ((v & 1) << 4) | ((v & 2) << 2) | (v & 4) | ((v & 8) >> 2) | ((v & 16) >> 4);
 }
 
-template <int DPW, int R2>
-__global__ void __launch_bounds__(256)
-k_search(SearchArgs a) {
+// Staging slots per thread per channel group: a group holds at most
+// kStageBudget / 32 chunks of 8 samples, spread over 256 threads.
+constexpr int kSlots = (kStageBudget / 32 + 255) / 256;
+
+// One (DM tile, time tile) of the fused search: channel-group loop, then the
+// boxcar stage.  Shared by the one-plan grid kernel and the multi-beam persistent
+// kernel.
+template <int DPW, int R2, typename Args>
+__device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
+                                            unsigned char *lds) {
   constexpr int TY = 128 * R2, TT = TY - kHalo, DT = 4 * DPW, SP = TY / 64;
-  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  constexpr int YROW = TY + kHalo + 4;   // ints per wave for the boxcar stage
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-
-  // XCD-aware tile order: blocks b = x (mod 8) all run on XCD x; give XCD x a
-  // contiguous run of tiles in time-major order.
-  const int nb = a.ntd * a.ntt;
-  const int b = blockIdx.x;
-  const int xcd = b & 7, k = b >> 3, q = nb >> 3, rem = nb & 7;
-  const int L = xcd * q + min(xcd, rem) + k;
-  const int tt = L / a.ntd, td = L - tt * a.ntd;
   const int64_t t0 = (int64_t)tt * TT;
 
   int acc[DPW][2 * R2];
@@ -220,37 +231,47 @@ k_search(SearchArgs a) {
       const int jj = lane / cc, c = lane - jj * cc;
       myoff = a.offs[(int64_t)(trial0 + jj) * a.nchan + gi.c_begin + c];
     }
-    __syncthreads();
-    // ---- stage the group's U windows: copy A (aligned) and copy B (shifted by one)
-    {
-      const int nchunk = gi.lw >> 3;
-      for (int j = 0; j < gi.njobs; ++j) {
+    // ---- stage the group's U windows.  Each (window, 8-sample chunk) slot becomes
+    // copy A (aligned to the window start) and copy B (one sample later).  All
+    // global loads of a thread are issued before any LDS write.
+    const int nchunk = gi.lw >> 3;
+    const int total = gi.njobs * nchunk;
+    const float inv = __int_as_float(gi.inv_nchunk);
+    uint32_t w[kSlots][5];
+    int dstA[kSlots], odd[kSlots];
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+      const int slot = tid + 256 * s;
+      dstA[s] = -1;
+      if (slot < total) {
+        int j = (int)((float)slot * inv);
+        if (j * nchunk > slot) --j;
+        else if ((j + 1) * nchunk <= slot) ++j;
+        const int ch = slot - j * nchunk;
         const int2 jb = a.jobs[gi.job_begin + j];
-        const int64_t e0 = (int64_t)jb.x * a.tpad + jb.y + t0;
+        const int64_t e0 = (int64_t)jb.x * a.tpad + jb.y + t0 + 8 * ch;
         const uint32_t *src = (const uint32_t *)(a.U + (e0 & ~(int64_t)1));
-        unsigned char *rowA = lds + j * 4 * gi.lw;
-        unsigned char *rowB = rowA + 2 * gi.lw;
-        if (e0 & 1) {
-          for (int ch = tid; ch < nchunk; ch += 256) {
-            const uint32_t *q = src + 4 * ch;
-            const uint32_t w0 = q[0], w1 = q[1], w2 = q[2], w3 = q[3], w4 = q[4];
-            *(uint4 *)(rowA + ch * 16) = make_uint4(__builtin_amdgcn_alignbyte(w1, w0, 2),
-                                                    __builtin_amdgcn_alignbyte(w2, w1, 2),
-                                                    __builtin_amdgcn_alignbyte(w3, w2, 2),
-                                                    __builtin_amdgcn_alignbyte(w4, w3, 2));
-            *(uint4 *)(rowB + ch * 16) = make_uint4(w1, w2, w3, w4);
-          }
-        } else {
-          for (int ch = tid; ch < nchunk; ch += 256) {
-            const uint32_t *q = src + 4 * ch;
-            const uint32_t w0 = q[0], w1 = q[1], w2 = q[2], w3 = q[3], w4 = q[4];
-            *(uint4 *)(rowA + ch * 16) = make_uint4(w0, w1, w2, w3);
-            *(uint4 *)(rowB + ch * 16) = make_uint4(__builtin_amdgcn_alignbyte(w1, w0, 2),
-                                                    __builtin_amdgcn_alignbyte(w2, w1, 2),
-                                                    __builtin_amdgcn_alignbyte(w3, w2, 2),
-                                                    __builtin_amdgcn_alignbyte(w4, w3, 2));
-          }
+#pragma unroll
+        for (int u = 0; u < 5; ++u) w[s][u] = src[u];
+        odd[s] = (int)(e0 & 1);
+        dstA[s] = j * 4 * gi.lw + ch * 16;
+      }
+    }
+    __syncthreads();   // the previous group's reads of LDS are done
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+      if (dstA[s] >= 0) {
+        uint32_t sh[4], A[4], B[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sh[u] = __builtin_amdgcn_alignbyte(w[s][u + 1], w[s][u], 2);
+        const bool o = odd[s] != 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          A[u] = o ? sh[u] : w[s][u];
+          B[u] = o ? w[s][u + 1] : sh[u];
         }
+        *(uint4 *)(lds + dstA[s]) = make_uint4(A[0], A[1], A[2], A[3]);
+        *(uint4 *)(lds + dstA[s] + 2 * gi.lw) = make_uint4(B[0], B[1], B[2], B[3]);
       }
     }
     __syncthreads();
@@ -259,19 +280,24 @@ k_search(SearchArgs a) {
 #pragma unroll
     for (int j = 0; j < DPW; ++j) {
       int c = 0;
+      const int jb = j * cc;
       for (; c + 4 <= cc; c += 4) {
-        int o[4];
+        const int o0 = __builtin_amdgcn_readlane(myoff, jb + c);
+        const int o1 = __builtin_amdgcn_readlane(myoff, jb + c + 1);
+        const int o2 = __builtin_amdgcn_readlane(myoff, jb + c + 2);
+        const int o3 = __builtin_amdgcn_readlane(myoff, jb + c + 3);
+        const unsigned char *p0 = lbase + o0, *p1 = lbase + o1, *p2 = lbase + o2, *p3 = lbase + o3;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) o[u] = __builtin_amdgcn_readlane(myoff, j * cc + c + u);
+        for (int r = 0; r < R2; ++r) a16[j][r] = pk_add_u16(a16[j][r], *(const uint32_t *)(p0 + 256 * r));
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const unsigned char *pp = lbase + o[u];
+        for (int r = 0; r < R2; ++r) a16[j][r] = pk_add_u16(a16[j][r], *(const uint32_t *)(p1 + 256 * r));
 #pragma unroll
-          for (int r = 0; r < R2; ++r) a16[j][r] = pk_add_u16(a16[j][r], *(const uint32_t *)(pp + 256 * r));
-        }
+        for (int r = 0; r < R2; ++r) a16[j][r] = pk_add_u16(a16[j][r], *(const uint32_t *)(p2 + 256 * r));
+#pragma unroll
+        for (int r = 0; r < R2; ++r) a16[j][r] = pk_add_u16(a16[j][r], *(const uint32_t *)(p3 + 256 * r));
       }
       for (; c < cc; ++c) {
-        const unsigned char *pp = lbase + __builtin_amdgcn_readlane(myoff, j * cc + c);
+        const unsigned char *pp = lbase + __builtin_amdgcn_readlane(myoff, jb + c);
 #pragma unroll
         for (int r = 0; r < R2; ++r) a16[j][r] = pk_add_u16(a16[j][r], *(const uint32_t *)(pp + 256 * r));
       }
@@ -289,9 +315,11 @@ k_search(SearchArgs a) {
     }
   }
 
-  // ---- boxcar search, one trial of each wave at a time
+  // ---- boxcar search, one trial of each wave at a time.  Each lane owns SP
+  // consecutive starts; per width the lane maximum goes to a per-wave LDS slot by
+  // an atomic max, so no per-width registers are held.
   __syncthreads();
-  int *Yw = (int *)lds + wave * (TY + kHalo + 4);
+  int *Yw = (int *)lds + wave * (YROW + 32);
   CandRec *part = (CandRec *)a.part;
 #pragma unroll
   for (int j = 0; j < DPW; ++j) {
@@ -301,7 +329,6 @@ k_search(SearchArgs a) {
       *(int2 *)(Yw + 2 * lane + 128 * r) = make_int2(acc[j][2 * r], acc[j][2 * r + 1]);
     if (lane < kHalo) Yw[TY + lane] = 0;
     __syncthreads();
-    // register prefix over this lane's starts and their windows
     int qv[SP + kHalo + 1];
     qv[0] = 0;
 #pragma unroll
@@ -309,47 +336,30 @@ k_search(SearchArgs a) {
     const int64_t ts = t0 + lane * SP;          // first start of this lane
     const bool owned = lane * SP < TT;
     const bool full = owned && (ts + SP - 1 + kHalo <= a.nout);
-    int mx[32];
+    // per width: the lane maximum over its starts, then the wave maximum, gathered
+    // so that lane w-1 (and lane w+31) holds the maximum for width w
+    int bmax = INT_MIN;
+    const int lane31 = lane & 31;
 #pragma unroll
-    for (int w = 0; w < 32; ++w) mx[w] = INT_MIN;
-    if (full) {
-#pragma unroll
-      for (int w = 1; w <= 32; ++w) {
-        if ((a.wmask >> (w - 1)) & 1u) {
-          int m = INT_MIN;
+    for (int w = 1; w <= 32; ++w) {
+      if ((a.wmask >> (w - 1)) & 1u) {
+        int m = INT_MIN;
+        if (full) {
 #pragma unroll
           for (int i = 0; i < SP; ++i) m = max(m, qv[i + w] - qv[i]);
-          mx[w - 1] = m;
-        }
-      }
-    } else if (owned) {
-#pragma unroll
-      for (int w = 1; w <= 32; ++w) {
-        if ((a.wmask >> (w - 1)) & 1u) {
-          int m = INT_MIN;
+        } else if (owned) {
 #pragma unroll
           for (int i = 0; i < SP; ++i)
             if (ts + i + w <= a.nout) m = max(m, qv[i + w] - qv[i]);
-          mx[w - 1] = m;
         }
+        const int wm = wave_max_i32(m);
+        bmax = (lane31 == w - 1) ? wm : bmax;
       }
     }
-    // transpose-reduce: lane l ends with the max over all lanes for W = bitrev5(l&31)+1
-#pragma unroll
-    for (int s = 0; s < 5; ++s) {
-      const int half = 16 >> s;
-      const bool hi = (lane >> s) & 1;
-#pragma unroll
-      for (int i = 0; i < half; ++i) {
-        const int send = hi ? mx[i] : mx[i + half];
-        const int keep = hi ? mx[i + half] : mx[i];
-        const int got = __shfl_xor(send, 1 << s, 64);
-        mx[i] = max(keep, got);
-      }
-    }
-    int bmax = max(mx[0], __shfl_xor(mx[0], 32, 64));
-    const int wl = bitrev5(lane & 31) + 1;
-    const int ji = a.widx[wl];
+    // lane l takes width (l mod 32) + 1
+    const int wl = (lane & 31) + 1;
+    // index of width wl in the sorted width list = number of listed widths below it
+    const int ji = ((a.wmask >> (wl - 1)) & 1u) ? __popc(a.wmask & ((1u << (wl - 1)) - 1u)) : -1;
     double snr = -INFINITY;
     if (ji >= 0 && bmax != INT_MIN && dg >= 0)
       snr = ((double)bmax - a.M[(int64_t)dg * a.nw + ji]) / a.S[(int64_t)dg * a.nw + ji];
@@ -396,6 +406,68 @@ k_search(SearchArgs a) {
     }
     __syncthreads();
   }
+}
+
+template <int DPW, int R2>
+__global__ void __launch_bounds__(256)
+k_search(SearchArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  // XCD-aware tile order: blocks b = x (mod 8) all run on XCD x; give XCD x a
+  // contiguous run of tiles in time-major order.
+  const int nb = a.ntd * a.ntt;
+  const int b = blockIdx.x;
+  const int xcd = b & 7, k = b >> 3, q = nb >> 3, rem = nb & 7;
+  const int L = xcd * q + min(xcd, rem) + k;
+  const int tt = L / a.ntd, td = L - tt * a.ntd;
+  search_tile<DPW, R2>(a, tt, td, lds);
+}
+
+// Persistent multi-beam search.  Items are (beam, tile) pairs numbered beam by beam
+// in time-major order (tile_begin[b] = first item of beam b, tile_begin[nbeam] =
+// total).  The item list is cut into 8 contiguous parts, one per XCD (blocks are
+// dealt to the XCDs round-robin, so block b runs on XCD b mod 8): a workgroup first
+// drains its own XCD's part, keeping neighbouring time tiles in that XCD's L2, then
+// helps the other parts.  Every part's counter only grows, so every workgroup
+// leaves after at most eight exhausted parts.
+template <int DPW, int R2>
+__global__ void __launch_bounds__(256)
+k_search_batch(const SearchArgs *__restrict__ beams, const int32_t *__restrict__ tile_begin,
+               int32_t nbeam, unsigned int *__restrict__ counters) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  __shared__ int s_item;
+  const int total = tile_begin[nbeam];
+  const int q = total >> 3, rem = total & 7;
+  const int home = blockIdx.x & 7;
+  for (int k = 0; k < 8; ++k) {
+    const int part = (home + k) & 7;
+    const int pbeg = part * q + min(part, rem);
+    const int plen = q + (part < rem ? 1 : 0);
+    for (;;) {
+      if (threadIdx.x == 0) s_item = (int)atomicAdd(&counters[part], 1u);
+      __syncthreads();
+      const int it = __builtin_amdgcn_readfirstlane(s_item);
+      __syncthreads();
+      if (it >= plen) break;
+      const int item = pbeg + it;
+      int lo = 0, hi = nbeam - 1;   // last beam whose first item <= item
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile_begin[mid] <= item) lo = mid; else hi = mid - 1;
+      }
+      // the argument table is read through the constant address space, so that
+      // its fields are scalar loads the compiler may repeat instead of keeping live
+      typedef const __attribute__((address_space(4))) SearchArgs CArgs;
+      CArgs &a = ((CArgs *)beams)[lo];
+      const int L = item - tile_begin[lo];
+      const int tt = L / a.ntd, td = L - tt * a.ntd;
+      search_tile<DPW, R2>(a, tt, td, lds);
+    }
+  }
+}
+
+__global__ void k_zero_u32(unsigned int *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
 }
 
 }  // namespace
@@ -484,6 +556,10 @@ static bool build_cfg(const dedisp_plan_s *p, const TiledTables &T, int ci, Tile
       }
       const int lw = ((TY + span + 2) + 7) & ~7;
       gi.lw = lw;
+      {
+        const float inv = 1.0f / (float)(lw / 8);
+        std::memcpy(&gi.inv_nchunk, &inv, sizeof(float));
+      }
       gi.c_count = ccount;
       bool flush = c >= C;
       if (!flush)
@@ -521,7 +597,7 @@ static bool build_cfg(const dedisp_plan_s *p, const TiledTables &T, int ci, Tile
   }
   out.group_begin[ntd] = (int)out.groups.size();
   out.ngroups = (int)out.groups.size();
-  out.lds_bytes = std::max(lds_max, 4 * (TY + kHalo + 4) * 4);
+  out.lds_bytes = std::max(lds_max, 4 * (TY + kHalo + 4 + 32) * 4);
   out.ok = true;
   return true;
 }
@@ -626,25 +702,30 @@ static hipError_t launch_cfg(const SearchArgs &a, int nblocks, int lds, hipStrea
 static hipError_t launch_search_kernel(int ci, const SearchArgs &a, int nblocks, int lds,
                                        hipStream_t s) {
   switch (ci) {
-    case 0: return launch_cfg<4, 8>(a, nblocks, lds, s);
-    case 1: return launch_cfg<8, 4>(a, nblocks, lds, s);
+    case 0: return launch_cfg<4, 6>(a, nblocks, lds, s);
+    case 1: return launch_cfg<4, 8>(a, nblocks, lds, s);
     case 2: return launch_cfg<2, 8>(a, nblocks, lds, s);
-    default: return launch_cfg<4, 4>(a, nblocks, lds, s);
+    case 3: return launch_cfg<8, 4>(a, nblocks, lds, s);
+    case 4: return launch_cfg<4, 4>(a, nblocks, lds, s);
+    default: return launch_cfg<3, 8>(a, nblocks, lds, s);
   }
 }
 
-dedisp_status run_search_tiled(dedisp_plan p, const uint8_t *x, int64_t nsamp, int64_t in_stride,
-                               int64_t nout, const WidthList &wl, const double *mu,
-                               const double *sigma, double *snr, int32_t *t, int32_t *w,
-                               void *work, hipStream_t s) {
-  const int ci = cfg_index(p);
+// Launches the per-block preparation of one plan (noise tables, window rows) into
+// `work` and fills the tile kernel's arguments.  Returns DEDISP_ERR_UNSUPPORTED
+// (without launching anything) when the tiled kernel cannot take this plan.
+static dedisp_status prepare_tiled(dedisp_plan p, int ci, const uint8_t *x, int64_t nsamp,
+                                   int64_t in_stride, int64_t nout, const WidthList &wl,
+                                   const double *mu, const double *sigma, void *work,
+                                   hipStream_t s, SearchArgs *out, TiledCfgTables **cfg_out,
+                                   Layout *lay_out) {
   TiledCfgTables *cfg = nullptr;
   {
     std::lock_guard<std::mutex> lk(p->mu);
     dedisp_status st = ensure_cfg(p, ci, &cfg);
     if (st != DEDISP_OK) return st;
   }
-  if (!cfg) return DEDISP_ERR_UNSUPPORTED;   // caller falls back to the general path
+  if (!cfg) return DEDISP_ERR_UNSUPPORTED;
   const TiledTables &T = *p->tiled;
   const Layout L = layout(p, ci, wl.n, nout, T.nrows);
   if (L.ntt * (int64_t)cfg->ntd > INT32_MAX / 2) return DEDISP_ERR_UNSUPPORTED;
@@ -682,13 +763,36 @@ dedisp_status run_search_tiled(dedisp_plan p, const uint8_t *x, int64_t nsamp, i
     a.widx[wl.w[i]] = (int8_t)i;
   }
   a.part = part;
+  *out = a;
+  *cfg_out = cfg;
+  *lay_out = L;
+  return DEDISP_OK;
+}
+
+static dedisp_status search_ci(dedisp_plan p, int ci, const uint8_t *x, int64_t nsamp,
+                               int64_t in_stride, int64_t nout, const WidthList &wl,
+                               const double *mu, const double *sigma, double *snr, int32_t *t,
+                               int32_t *w, void *work, hipStream_t s) {
+  SearchArgs a;
+  TiledCfgTables *cfg = nullptr;
+  Layout L;
+  dedisp_status st = prepare_tiled(p, ci, x, nsamp, in_stride, nout, wl, mu, sigma, work, s, &a,
+                                   &cfg, &L);
+  if (st != DEDISP_OK) return st;
   KernelTimer kt(p, s);
   DD_HIP(kt.begin());
   DD_HIP(launch_search_kernel(ci, a, cfg->ntd * (int)L.ntt, cfg->lds_bytes, s));
   DD_HIP(kt.end());
-  DD_HIP(launch_reduce(p->ndm, (int32_t)L.ntt, part, snr, t, w, s));
+  DD_HIP(launch_reduce(p->ndm, (int32_t)L.ntt, a.part, snr, t, w, s));
   p->last_search_tile = ci;
   return DEDISP_OK;
+}
+
+dedisp_status run_search_tiled(dedisp_plan p, const uint8_t *x, int64_t nsamp, int64_t in_stride,
+                               int64_t nout, const WidthList &wl, const double *mu,
+                               const double *sigma, double *snr, int32_t *t, int32_t *w,
+                               void *work, hipStream_t s) {
+  return search_ci(p, cfg_index(p), x, nsamp, in_stride, nout, wl, mu, sigma, snr, t, w, work, s);
 }
 
 int search_config_count() { return kNumCfgs; }
@@ -705,3 +809,416 @@ dedisp_status dedisp_set_tile(dedisp_plan p, int32_t tile) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------------------
+// Batched search over many beams: one persistent launch, optionally replayed
+// from a captured HIP graph.
+// ------------------------------------------------------------------------------
+struct dedisp_batch_s {
+  int32_t nbeam = 0, nchan = 0, ci = 0;
+  std::vector<dedisp_plan> plans;
+  std::vector<int64_t> nsamp, nout;
+  dd::WidthList wl{};
+  std::vector<size_t> off;          // workspace offset of each beam
+  std::vector<int64_t> out_off;     // first output row of each beam
+  size_t work_bytes = 0;
+  int64_t total_trials = 0, total_sums = 0;
+  std::vector<int32_t> tile_begin;
+  int32_t *d_tile_begin = nullptr;
+  dd::SearchArgs *d_args = nullptr;
+  unsigned int *d_counters = nullptr;
+  int lds = 0, grid = 0;
+  // captured graph and the pointers it was captured with
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<const void *> key;
+  hipStream_t cap = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+namespace dd {
+
+template <int DPW, int R2>
+static hipError_t launch_batch_cfg(const dedisp_batch_s *B, hipStream_t s) {
+  hipLaunchKernelGGL((k_search_batch<DPW, R2>), dim3(B->grid), dim3(256), B->lds, s, B->d_args,
+                     B->d_tile_begin, B->nbeam, B->d_counters);
+  return hipGetLastError();
+}
+
+static hipError_t launch_batch_kernel(const dedisp_batch_s *B, hipStream_t s) {
+  switch (B->ci) {
+    case 0: return launch_batch_cfg<4, 6>(B, s);
+    case 1: return launch_batch_cfg<4, 8>(B, s);
+    case 2: return launch_batch_cfg<2, 8>(B, s);
+    case 3: return launch_batch_cfg<8, 4>(B, s);
+    case 4: return launch_batch_cfg<4, 4>(B, s);
+    default: return launch_batch_cfg<3, 8>(B, s);
+  }
+}
+
+template <int DPW, int R2>
+static hipError_t occupancy_cfg(int lds, int *blocks) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_search_batch<DPW, R2>, 256, lds);
+}
+
+static hipError_t batch_occupancy(int ci, int lds, int *blocks) {
+  switch (ci) {
+    case 0: return occupancy_cfg<4, 6>(lds, blocks);
+    case 1: return occupancy_cfg<4, 8>(lds, blocks);
+    case 2: return occupancy_cfg<2, 8>(lds, blocks);
+    case 3: return occupancy_cfg<8, 4>(lds, blocks);
+    case 4: return occupancy_cfg<4, 4>(lds, blocks);
+    default: return occupancy_cfg<3, 8>(lds, blocks);
+  }
+}
+
+// The whole per-call launch sequence: per-beam tables and window rows, counter
+// reset (a fill kernel, so the sequence can be captured), the persistent search
+// and the per-beam reductions.
+// With copy_args false the argument table is not uploaded (the graph path uploads
+// it outside the capture: it depends only on the pointers the graph is keyed on).
+static dedisp_status batch_enqueue(dedisp_batch_s *B, const void *const *in, const int64_t *stride,
+                                   const double *mu, const double *sigma, double *snr, int32_t *t,
+                                   int32_t *w, void *work, hipStream_t s, bool copy_args,
+                                   std::vector<SearchArgs> &args) {
+  args.assign(B->nbeam, SearchArgs{});
+  for (int b = 0; b < B->nbeam; ++b) {
+    TiledCfgTables *cfg = nullptr;
+    Layout L;
+    dedisp_status st = prepare_tiled(B->plans[b], B->ci, (const uint8_t *)in[b], B->nsamp[b],
+                                     stride[b], B->nout[b], B->wl, mu, sigma,
+                                     (char *)work + B->off[b], s, &args[b], &cfg, &L);
+    if (st != DEDISP_OK) return st == DEDISP_ERR_UNSUPPORTED
+                                    ? fail(st, "a beam's plan cannot use the tiled search")
+                                    : st;
+  }
+  if (copy_args)
+    DD_HIP(hipMemcpyAsync(B->d_args, args.data(), sizeof(SearchArgs) * B->nbeam,
+                          hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, B->d_counters, 8);
+  DD_HIP(hipGetLastError());
+  KernelTimer kt(B->plans[0], s);
+  DD_HIP(kt.begin());
+  DD_HIP(launch_batch_kernel(B, s));
+  DD_HIP(kt.end());
+  for (int b = 0; b < B->nbeam; ++b) {
+    const int64_t o = B->out_off[b];
+    DD_HIP(launch_reduce(B->plans[b]->ndm, args[b].ntt, args[b].part, snr + o, t + o, w + o, s));
+  }
+  return DEDISP_OK;
+}
+
+}  // namespace dd
+
+extern "C" {
+
+dedisp_status dedisp_batch_create(dedisp_batch *out, int32_t nbeam, const dedisp_plan *plans,
+                                  const int64_t *nsamp, const int32_t *widths, int32_t nw) {
+  using namespace dd;
+  if (!out || nbeam < 1 || !plans || !nsamp || !widths) return fail(DEDISP_ERR_INVALID_ARG, "bad batch arguments");
+  *out = nullptr;
+  for (int b = 0; b < nbeam; ++b) {
+    if (!plans[b]) return fail(DEDISP_ERR_INVALID_ARG, "null plan in batch");
+    if (plans[b]->nchan != plans[0]->nchan) return fail(DEDISP_ERR_INVALID_ARG, "beams must share the channel count");
+    if (plans[b]->wmode != DEDISP_W_UNIT) return fail(DEDISP_ERR_UNSUPPORTED, "batched search needs unit weights");
+    if (nsamp[b] < plans[b]->max_span) return fail(DEDISP_ERR_SHAPE, "a beam is shorter than its longest run");
+  }
+  if (nw < 1 || nw > kMaxWidths) return fail(DEDISP_ERR_INVALID_ARG, "need 1..64 widths");
+  std::vector<int32_t> wv(widths, widths + nw);
+  std::sort(wv.begin(), wv.end());
+  wv.erase(std::unique(wv.begin(), wv.end()), wv.end());
+  if (wv.front() < 1 || wv.back() > 32) return fail(DEDISP_ERR_UNSUPPORTED, "batched search takes widths 1..32");
+  dedisp_batch_s *B = new (std::nothrow) dedisp_batch_s;
+  if (!B) return fail(DEDISP_ERR_OOM, "host allocation failed");
+  B->nbeam = nbeam;
+  B->nchan = plans[0]->nchan;
+  B->plans.assign(plans, plans + nbeam);
+  B->nsamp.assign(nsamp, nsamp + nbeam);
+  B->wl.n = (int32_t)wv.size();
+  for (int i = 0; i < B->wl.n; ++i) B->wl.w[i] = wv[i];
+  B->ci = cfg_index(plans[0]);
+  dedisp_status st = DEDISP_OK;
+  size_t off = 0;
+  int32_t items = 0;
+  B->tile_begin.push_back(0);
+  for (int b = 0; b < nbeam && st == DEDISP_OK; ++b) {
+    dedisp_plan p = plans[b];
+    const int64_t no = nsamp[b] - p->max_span + 1;
+    B->nout.push_back(no);
+    if (!search_supported(p, B->wl)) {
+      st = fail(DEDISP_ERR_UNSUPPORTED, "a beam's plan cannot use the tiled search");
+      break;
+    }
+    if ((st = ensure_device(p)) != DEDISP_OK) break;
+    TiledCfgTables *cfg = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(p->mu);
+      st = ensure_cfg(p, B->ci, &cfg);
+    }
+    if (st != DEDISP_OK) break;
+    if (!cfg) {
+      st = fail(DEDISP_ERR_UNSUPPORTED, "a beam's plan cannot use the tiled search");
+      break;
+    }
+    const Layout L = layout(p, B->ci, B->wl.n, no, p->tiled->nrows);
+    B->off.push_back(off);
+    off += (L.total + 255) & ~(size_t)255;
+    B->out_off.push_back(B->total_trials);
+    B->total_trials += p->ndm;
+    B->total_sums += (int64_t)p->ndm * p->nchan * no;
+    items += cfg->ntd * (int32_t)L.ntt;
+    B->tile_begin.push_back(items);
+    B->lds = std::max(B->lds, cfg->lds_bytes);
+  }
+  B->work_bytes = off;
+  if (st == DEDISP_OK) {
+    hipError_t e = upload(&B->d_tile_begin, B->tile_begin);
+    if (e == hipSuccess) e = hipMalloc((void **)&B->d_args, sizeof(SearchArgs) * nbeam);
+    if (e == hipSuccess) e = hipMalloc((void **)&B->d_counters, 8 * sizeof(unsigned int));
+    int per_cu = 0, dev = 0, ncu = 0;
+    if (e == hipSuccess) e = batch_occupancy(B->ci, B->lds, &per_cu);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) st = hip_fail(e, "batch setup");
+    B->grid = std::max(8, std::min(items, std::max(1, per_cu) * ncu));
+  }
+  if (st != DEDISP_OK) {
+    dedisp_batch_destroy(B);
+    return st;
+  }
+  *out = B;
+  return DEDISP_OK;
+}
+
+dedisp_status dedisp_batch_destroy(dedisp_batch B) {
+  if (!B) return dd::fail(DEDISP_ERR_INVALID_ARG, "null batch");
+  if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  if (B->cap) (void)hipStreamDestroy(B->cap);
+  if (B->ev_in) (void)hipEventDestroy(B->ev_in);
+  if (B->ev_out) (void)hipEventDestroy(B->ev_out);
+  (void)hipFree(B->d_tile_begin);
+  (void)hipFree(B->d_args);
+  (void)hipFree(B->d_counters);
+  delete B;
+  return DEDISP_OK;
+}
+
+dedisp_status dedisp_batch_work_bytes(dedisp_batch B, size_t *bytes) {
+  if (!B || !bytes) return dd::fail(DEDISP_ERR_INVALID_ARG, "null argument");
+  *bytes = B->work_bytes;
+  return DEDISP_OK;
+}
+
+dedisp_status dedisp_batch_info(dedisp_batch B, int64_t *total_trials, int64_t *total_sums) {
+  if (!B) return dd::fail(DEDISP_ERR_INVALID_ARG, "null batch");
+  if (total_trials) *total_trials = B->total_trials;
+  if (total_sums) *total_sums = B->total_sums;
+  return DEDISP_OK;
+}
+
+dedisp_status dedisp_batch_run(dedisp_batch B, const void *const *d_in, const int64_t *in_stride,
+                               const double *d_chan_mean, const double *d_chan_sigma,
+                               double *d_snr, int32_t *d_t, int32_t *d_w, void *d_work,
+                               size_t work_bytes, int32_t use_graph, void *stream) {
+  using namespace dd;
+  if (!B || !d_in || !in_stride || !d_chan_mean || !d_chan_sigma || !d_snr || !d_t || !d_w || !d_work)
+    return fail(DEDISP_ERR_INVALID_ARG, "null argument");
+  if (work_bytes < B->work_bytes) return fail(DEDISP_ERR_INVALID_ARG, "workspace too small");
+  for (int b = 0; b < B->nbeam; ++b)
+    if (!d_in[b] || in_stride[b] < B->nsamp[b]) return fail(DEDISP_ERR_INVALID_ARG, "bad beam input");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<SearchArgs> args;
+  if (!use_graph) {
+    dedisp_status st = batch_enqueue(B, d_in, in_stride, d_chan_mean, d_chan_sigma, d_snr, d_t, d_w,
+                                     d_work, s, true, args);
+    // the copy above reads `args` asynchronously: wait for it before it goes away
+    if (st == DEDISP_OK) DD_HIP(hipStreamSynchronize(s));
+    return st;
+  }
+  // Graph path: capture once per set of pointers on a private stream, then replay.
+  std::vector<const void *> key(d_in, d_in + B->nbeam);
+  for (int b = 0; b < B->nbeam; ++b) key.push_back((const void *)(intptr_t)in_stride[b]);
+  key.insert(key.end(), {d_chan_mean, d_chan_sigma, d_snr, d_t, d_w, d_work});
+  if (!B->cap) {
+    DD_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+    DD_HIP(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
+    DD_HIP(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
+  }
+  if (!B->gexec || key != B->key) {
+    if (B->gexec) {
+      (void)hipGraphExecDestroy(B->gexec);
+      B->gexec = nullptr;
+    }
+    if (B->graph) {
+      (void)hipGraphDestroy(B->graph);
+      B->graph = nullptr;
+    }
+    // Instrumentation events are not captured.
+    std::vector<hipEvent_t> e0, e1;
+    e0.swap(B->plans[0]->ev_start);
+    e1.swap(B->plans[0]->ev_stop);
+    DD_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+    // Anything still running from an earlier replay must not see a new table.
+    DD_HIP(hipStreamSynchronize(B->cap));
+    dedisp_status st = batch_enqueue(B, d_in, in_stride, d_chan_mean, d_chan_sigma, d_snr, d_t, d_w,
+                                     d_work, B->cap, false, args);
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(B->cap, &g);
+    e0.swap(B->plans[0]->ev_start);
+    e1.swap(B->plans[0]->ev_stop);
+    if (st != DEDISP_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+    B->graph = g;
+    DD_HIP(hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0));
+    DD_HIP(hipMemcpy(B->d_args, args.data(), sizeof(SearchArgs) * B->nbeam, hipMemcpyHostToDevice));
+    B->key = key;
+  }
+  DD_HIP(hipEventRecord(B->ev_in, s));
+  DD_HIP(hipStreamWaitEvent(B->cap, B->ev_in, 0));
+  DD_HIP(hipGraphLaunch(B->gexec, B->cap));
+  DD_HIP(hipEventRecord(B->ev_out, B->cap));
+  DD_HIP(hipStreamWaitEvent(s, B->ev_out, 0));
+  return DEDISP_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------
+// Autotuner: time every tile shape of the fused search on the caller's block and
+// keep the fastest.  Results are cached per (device architecture, plan shape,
+// table hash, block length, widths) in the text file named by DEDISP_TUNE_CACHE.
+// ------------------------------------------------------------------------------
+namespace dd {
+
+static std::string tune_key(const dedisp_plan_s *p, int64_t nsamp, const WidthList &wl) {
+  uint64_t h = 1469598103934665603ull;   // FNV-1a over the tables and widths
+  auto mix = [&](const void *data, size_t n) {
+    const unsigned char *c = (const unsigned char *)data;
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  };
+  mix(p->start.data(), p->start.size() * sizeof(int32_t));
+  mix(p->ntap.data(), p->ntap.size() * sizeof(int32_t));
+  mix(wl.w, sizeof(int32_t) * wl.n);
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    arch = prop.gcnArchName;
+  for (char &ch : arch)
+    if (ch == ' ') ch = '_';
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s:%d:%d:%d:%lld:%016llx", arch.c_str(), p->nchan, p->ndm,
+           p->max_span, (long long)nsamp, (unsigned long long)h);
+  return buf;
+}
+
+static int tune_cache_lookup(const std::string &key) {
+  const char *path = getenv("DEDISP_TUNE_CACHE");
+  if (!path) return -1;
+  FILE *f = fopen(path, "r");
+  if (!f) return -1;
+  char k[256];
+  int ci = -1, found = -1;
+  double ms;
+  while (fscanf(f, "%255s %d %lf", k, &ci, &ms) == 3)
+    if (key == k && ci >= 0 && ci < kNumCfgs) found = ci;
+  fclose(f);
+  return found;
+}
+
+static void tune_cache_store(const std::string &key, int ci, double ms) {
+  const char *path = getenv("DEDISP_TUNE_CACHE");
+  if (!path) return;
+  FILE *f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%s %d %.6f\n", key.c_str(), ci, ms);
+  fclose(f);
+}
+
+}  // namespace dd
+
+extern "C" dedisp_status dedisp_autotune(dedisp_plan p, const void *d_in, int64_t nsamp,
+                                         int64_t in_stride, const int32_t *widths, int32_t nw,
+                                         const double *d_chan_mean, const double *d_chan_sigma,
+                                         void *d_work, size_t work_bytes, void *stream,
+                                         int32_t *chosen) {
+  using namespace dd;
+  if (!p || !d_in || !widths || !d_chan_mean || !d_chan_sigma || !d_work || !chosen)
+    return fail(DEDISP_ERR_INVALID_ARG, "null argument");
+  if (p->wmode != DEDISP_W_UNIT) return fail(DEDISP_ERR_UNSUPPORTED, "the tuned kernel takes unit weights");
+  if (nsamp < p->max_span || in_stride < nsamp) return fail(DEDISP_ERR_SHAPE, "bad block length");
+  const int64_t nout = nsamp - p->max_span + 1;
+  if (nw < 1 || nw > kMaxWidths) return fail(DEDISP_ERR_INVALID_ARG, "need 1..64 widths");
+  std::vector<int32_t> wv(widths, widths + nw);
+  std::sort(wv.begin(), wv.end());
+  wv.erase(std::unique(wv.begin(), wv.end()), wv.end());
+  WidthList wl;
+  wl.n = (int32_t)wv.size();
+  for (int i = 0; i < wl.n; ++i) wl.w[i] = wv[i];
+  if (wv.front() < 1 || wv.back() > nout) return fail(DEDISP_ERR_INVALID_ARG, "bad widths");
+  if (!search_supported(p, wl)) return fail(DEDISP_ERR_UNSUPPORTED, "plan cannot use the tiled search");
+  if (work_bytes < search_work_bytes(p, wl.n, nout)) return fail(DEDISP_ERR_INVALID_ARG, "workspace too small");
+  dedisp_status st = ensure_device(p);
+  if (st != DEDISP_OK) return st;
+  const std::string key = tune_key(p, nsamp, wl);
+  const int cached = tune_cache_lookup(key);
+  if (cached >= 0) {
+    p->tile_choice = cached;
+    *chosen = cached;
+    return DEDISP_OK;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  double *snr = nullptr;
+  int32_t *tt = nullptr, *ww = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  DD_HIP(hipMalloc((void **)&snr, sizeof(double) * p->ndm));
+  DD_HIP(hipMalloc((void **)&tt, sizeof(int32_t) * p->ndm));
+  DD_HIP(hipMalloc((void **)&ww, sizeof(int32_t) * p->ndm));
+  DD_HIP(hipEventCreate(&e0));
+  DD_HIP(hipEventCreate(&e1));
+  int best = -1;
+  double best_ms = 1e30;
+  // the timed calls must not advance the instrumentation slots
+  std::vector<hipEvent_t> es, et;
+  es.swap(p->ev_start);
+  et.swap(p->ev_stop);
+  for (int ci = 0; ci < kNumCfgs && st == DEDISP_OK; ++ci) {
+    st = search_ci(p, ci, (const uint8_t *)d_in, nsamp, in_stride, nout, wl, d_chan_mean,
+                   d_chan_sigma, snr, tt, ww, d_work, s);
+    if (st == DEDISP_ERR_UNSUPPORTED) {
+      st = DEDISP_OK;
+      continue;
+    }
+    if (st != DEDISP_OK) break;
+    hipError_t e = hipEventRecord(e0, s);
+    for (int r = 0; r < 3 && e == hipSuccess && st == DEDISP_OK; ++r)
+      st = search_ci(p, ci, (const uint8_t *)d_in, nsamp, in_stride, nout, wl, d_chan_mean,
+                     d_chan_sigma, snr, tt, ww, d_work, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) st = hip_fail(e, "autotune timing");
+    if (st == DEDISP_OK && ms < best_ms) {
+      best_ms = ms;
+      best = ci;
+    }
+  }
+  es.swap(p->ev_start);
+  et.swap(p->ev_stop);
+  (void)hipFree(snr);
+  (void)hipFree(tt);
+  (void)hipFree(ww);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != DEDISP_OK) return st;
+  if (best < 0) return fail(DEDISP_ERR_UNSUPPORTED, "no tile shape fits this plan");
+  p->tile_choice = best;
+  tune_cache_store(key, best, best_ms / 3.0);
+  *chosen = best;
+  return DEDISP_OK;
+}
