@@ -46,6 +46,9 @@ static const TileCfg kCfgs[] = {{4, 6}, {4, 8}, {2, 8}, {8, 4}, {4, 4}, {3, 8}};
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 constexpr int kDefaultCfg = 0;
 constexpr int kHalo = 32;                 // boxcar widths up to 32
+// Time-tile step: TY minus a halo of at least 31 outputs, rounded so that every
+// lane (SP = 2 * r2 consecutive starts) owns either all or none of its starts.
+constexpr int tile_step(int r2) { return 128 * r2 - ((32 + 2 * r2 - 1) / (2 * r2)) * (2 * r2); }
 constexpr int kStageBudget = 32 * 1024;   // LDS bytes for one channel group's windows
 
 struct GroupInfo {
@@ -196,6 +199,8 @@ __device__ __forceinline__ int bitrev5(int v) {
 // Staging slots per thread per channel group: a group holds at most
 // kStageBudget / 32 chunks of 8 samples, spread over 256 threads.
 constexpr int kSlots = (kStageBudget / 32 + 255) / 256;
+// 8-sample chunks per lane when a wave stages one window (windows up to 1536 samples)
+constexpr int kRowChunks = 3;
 
 // One (DM tile, time tile) of the fused search: channel-group loop, then the
 // boxcar stage.  Shared by the one-plan grid kernel and the multi-beam persistent
@@ -203,8 +208,9 @@ constexpr int kSlots = (kStageBudget / 32 + 255) / 256;
 template <int DPW, int R2, typename Args>
 __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
                                             unsigned char *lds) {
-  constexpr int TY = 128 * R2, TT = TY - kHalo, DT = 4 * DPW, SP = TY / 64;
+  constexpr int TY = 128 * R2, TT = tile_step(R2), DT = 4 * DPW, SP = TY / 64;
   constexpr int YROW = TY + kHalo + 4;   // ints per wave for the boxcar stage
+  static_assert(TT % SP == 0 && TY - TT >= 31, "tile step");
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t t0 = (int64_t)tt * TT;
@@ -231,47 +237,52 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
       const int jj = lane / cc, c = lane - jj * cc;
       myoff = a.offs[(int64_t)(trial0 + jj) * a.nchan + gi.c_begin + c];
     }
-    // ---- stage the group's U windows.  Each (window, 8-sample chunk) slot becomes
-    // copy A (aligned to the window start) and copy B (one sample later).  All
-    // global loads of a thread are issued before any LDS write.
-    const int nchunk = gi.lw >> 3;
-    const int total = gi.njobs * nchunk;
-    const float inv = __int_as_float(gi.inv_nchunk);
-    uint32_t w[kSlots][5];
-    int dstA[kSlots], odd[kSlots];
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-      const int slot = tid + 256 * s;
-      dstA[s] = -1;
-      if (slot < total) {
-        int j = (int)((float)slot * inv);
-        if (j * nchunk > slot) --j;
-        else if ((j + 1) * nchunk <= slot) ++j;
-        const int ch = slot - j * nchunk;
-        const int2 jb = a.jobs[gi.job_begin + j];
-        const int64_t e0 = (int64_t)jb.x * a.tpad + jb.y + t0 + 8 * ch;
-        const uint32_t *src = (const uint32_t *)(a.U + (e0 & ~(int64_t)1));
-#pragma unroll
-        for (int u = 0; u < 5; ++u) w[s][u] = src[u];
-        odd[s] = (int)(e0 & 1);
-        dstA[s] = j * 4 * gi.lw + ch * 16;
-      }
-    }
+    // ---- stage the group's U windows: copy A (aligned to the window start) and
+    // copy B (one sample later).  Whole windows go to waves, so the window's
+    // source, destination and parity are scalar; lanes take 8-sample chunks.
     __syncthreads();   // the previous group's reads of LDS are done
+    {
+      const int nchunk = gi.lw >> 3;
+      for (int j = wave; j < gi.njobs; j += 4) {
+        const int2 jb = a.jobs[gi.job_begin + j];
+        const int64_t e0 = (int64_t)jb.x * a.tpad + jb.y + t0;
+        const uint32_t *src = (const uint32_t *)(a.U + (e0 & ~(int64_t)1));
+        unsigned char *rowA = lds + j * 4 * gi.lw;
+        unsigned char *rowB = rowA + 2 * gi.lw;
+        uint32_t w[kRowChunks][5];
 #pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-      if (dstA[s] >= 0) {
-        uint32_t sh[4], A[4], B[4];
+        for (int k = 0; k < kRowChunks; ++k) {
+          const int ch = lane + 64 * k;
+          if (ch < nchunk) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) sh[u] = __builtin_amdgcn_alignbyte(w[s][u + 1], w[s][u], 2);
-        const bool o = odd[s] != 0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          A[u] = o ? sh[u] : w[s][u];
-          B[u] = o ? w[s][u + 1] : sh[u];
+            for (int u = 0; u < 5; ++u) w[k][u] = src[4 * ch + u];
+          }
         }
-        *(uint4 *)(lds + dstA[s]) = make_uint4(A[0], A[1], A[2], A[3]);
-        *(uint4 *)(lds + dstA[s] + 2 * gi.lw) = make_uint4(B[0], B[1], B[2], B[3]);
+        if (e0 & 1) {
+#pragma unroll
+          for (int k = 0; k < kRowChunks; ++k) {
+            const int ch = lane + 64 * k;
+            if (ch < nchunk) {
+              *(uint4 *)(rowA + ch * 16) = make_uint4(__builtin_amdgcn_alignbyte(w[k][1], w[k][0], 2),
+                                                      __builtin_amdgcn_alignbyte(w[k][2], w[k][1], 2),
+                                                      __builtin_amdgcn_alignbyte(w[k][3], w[k][2], 2),
+                                                      __builtin_amdgcn_alignbyte(w[k][4], w[k][3], 2));
+              *(uint4 *)(rowB + ch * 16) = make_uint4(w[k][1], w[k][2], w[k][3], w[k][4]);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < kRowChunks; ++k) {
+            const int ch = lane + 64 * k;
+            if (ch < nchunk) {
+              *(uint4 *)(rowA + ch * 16) = make_uint4(w[k][0], w[k][1], w[k][2], w[k][3]);
+              *(uint4 *)(rowB + ch * 16) = make_uint4(__builtin_amdgcn_alignbyte(w[k][1], w[k][0], 2),
+                                                      __builtin_amdgcn_alignbyte(w[k][2], w[k][1], 2),
+                                                      __builtin_amdgcn_alignbyte(w[k][3], w[k][2], 2),
+                                                      __builtin_amdgcn_alignbyte(w[k][4], w[k][3], 2));
+            }
+          }
+        }
       }
     }
     __syncthreads();
@@ -335,7 +346,19 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
     for (int i = 0; i < SP + kHalo; ++i) qv[i + 1] = qv[i] + Yw[lane * SP + i];
     const int64_t ts = t0 + lane * SP;          // first start of this lane
     const bool owned = lane * SP < TT;
-    const bool full = owned && (ts + SP - 1 + kHalo <= a.nout);
+    // Windows of unit-weight uint8 sums are >= 0.  Entries of the prefix past the
+    // last valid output (or all of them, for lanes without starts in this tile)
+    // are pushed down so that every window that is not a valid (start, width) of
+    // this tile comes out negative: then the width loop needs no checks.
+    {
+      const int64_t room = a.nout - ts;
+      const int lim = owned ? (int)(room < SP + kHalo ? room : SP + kHalo) : -1;
+      if (lim < SP + kHalo) {
+#pragma unroll
+        for (int k = 0; k <= SP + kHalo; ++k)
+          if (k > lim) qv[k] = (INT_MIN / 4) - (k - lim);
+      }
+    }
     // per width: the lane maximum over its starts, then the wave maximum, gathered
     // so that lane w-1 (and lane w+31) holds the maximum for width w
     int bmax = INT_MIN;
@@ -343,15 +366,9 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
 #pragma unroll
     for (int w = 1; w <= 32; ++w) {
       if ((a.wmask >> (w - 1)) & 1u) {
-        int m = INT_MIN;
-        if (full) {
+        int m = qv[w] - qv[0];
 #pragma unroll
-          for (int i = 0; i < SP; ++i) m = max(m, qv[i + w] - qv[i]);
-        } else if (owned) {
-#pragma unroll
-          for (int i = 0; i < SP; ++i)
-            if (ts + i + w <= a.nout) m = max(m, qv[i + w] - qv[i]);
-        }
+        for (int i = 1; i < SP; ++i) m = max(m, qv[i + w] - qv[i]);
         const int wm = wave_max_i32(m);
         bmax = (lane31 == w - 1) ? wm : bmax;
       }
@@ -361,7 +378,7 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
     // index of width wl in the sorted width list = number of listed widths below it
     const int ji = ((a.wmask >> (wl - 1)) & 1u) ? __popc(a.wmask & ((1u << (wl - 1)) - 1u)) : -1;
     double snr = -INFINITY;
-    if (ji >= 0 && bmax != INT_MIN && dg >= 0)
+    if (ji >= 0 && bmax >= 0 && dg >= 0)
       snr = ((double)bmax - a.M[(int64_t)dg * a.nw + ji]) / a.S[(int64_t)dg * a.nw + ji];
     // wave argmax over (snr desc, W asc)
     int bw = wl, bb = bmax;
@@ -378,15 +395,15 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
     snr = __shfl(snr, 0, 64);
     bw = __shfl(bw, 0, 64);
     bb = __shfl(bb, 0, 64);
-    // earliest start of the winning width in this tile
+    // earliest start of the winning width in this tile (invalid windows are < 0 <= bb)
     int first = -1;
-    if (owned && snr != -INFINITY) {
+    if (snr != -INFINITY) {
 #pragma unroll
       for (int w = 1; w <= 32; ++w) {
         if (w == bw) {
 #pragma unroll
           for (int i = SP - 1; i >= 0; --i)
-            if (ts + i + w <= a.nout && qv[i + w] - qv[i] == bb) first = i;
+            if (qv[i + w] - qv[i] == bb) first = i;
         }
       }
     }
@@ -506,7 +523,7 @@ static bool build_cfg(const dedisp_plan_s *p, const TiledTables &T, int ci, Tile
   out = TiledCfgTables();
   out.dt = DT;
   out.ty = TY;
-  out.tt = TY - kHalo;
+  out.tt = tile_step(cf.r2);
   std::vector<int32_t> order(D);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return p->dm[a] < p->dm[b]; });
@@ -545,7 +562,8 @@ static bool build_cfg(const dedisp_plan_s *p, const TiledTables &T, int ci, Tile
         }
         const int nspan = std::max(span, smax - smin);
         const int lw = ((TY + nspan + 2) + 7) & ~7;
-        const int bytes = (nrows_g + (int)ns.size()) * 4 * lw;
+        const int bytes = lw > 64 * 8 * kRowChunks ? INT32_MAX / 2   // window too long for one wave
+                                                    : (nrows_g + (int)ns.size()) * 4 * lw;
         if (ccount == 0 && (bytes > kStageBudget || over)) return false;
         if (bytes > kStageBudget || over || ccount >= 64 / cf.dpw) break;
         span = nspan;
@@ -649,7 +667,7 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 static Layout layout(const dedisp_plan_s *p, int ci, int32_t nw, int64_t nout, int64_t nrows) {
   const TileCfg cf = kCfgs[ci];
-  const int TY = 128 * cf.r2, TT = TY - kHalo;
+  const int TY = 128 * cf.r2, TT = tile_step(cf.r2);
   Layout L;
   L.ntt = (nout + TT - 1) / TT;
   L.tpad = (((L.ntt - 1) * TT + TY + 2 * (int64_t)p->max_span + 32) + 7) & ~(int64_t)7;
@@ -687,9 +705,11 @@ bool search_supported(const dedisp_plan_s *p, const WidthList &wl) {
   if (p->wmode != DEDISP_W_UNIT) return false;
   if (wl.w[wl.n - 1] > 32) return false;
   if (p->max_ntap > 257) return false;
-  // the register prefix of the boxcar stage sums up to SP + 32 int32 outputs
+  // the register prefix of the boxcar stage sums up to SP + 32 <= 48 outputs and
+  // must stay below 2^30; invalid entries are placed near -2^29, so every
+  // difference of two entries fits in int32
   const double ymax = 255.0 * (double)p->sum_max_ntap;
-  if (ymax * (16 + 32 + 1) >= 2147483647.0) return false;
+  if (ymax * 49.0 >= 1073741824.0) return false;
   return true;
 }
 
@@ -1054,13 +1074,14 @@ dedisp_status dedisp_batch_run(dedisp_batch B, const void *const *d_in, const in
       (void)hipGraphDestroy(B->graph);
       B->graph = nullptr;
     }
-    // Instrumentation events are not captured.
+    // Anything still running from an earlier replay must not see a new table.
+    DD_HIP(hipStreamSynchronize(B->cap));
+    DD_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+    // from here on the capture is ended on every path; instrumentation events
+    // are not captured
     std::vector<hipEvent_t> e0, e1;
     e0.swap(B->plans[0]->ev_start);
     e1.swap(B->plans[0]->ev_stop);
-    DD_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
-    // Anything still running from an earlier replay must not see a new table.
-    DD_HIP(hipStreamSynchronize(B->cap));
     dedisp_status st = batch_enqueue(B, d_in, in_stride, d_chan_mean, d_chan_sigma, d_snr, d_t, d_w,
                                      d_work, B->cap, false, args);
     hipGraph_t g = nullptr;
