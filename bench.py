@@ -71,6 +71,11 @@ def main() -> int:
     ap.add_argument("--rule", default="allnonzero", choices=["allnonzero", "smear"])
     ap.add_argument("--cpu-sample-trials", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="search",
+                    choices=["search", "batch", "weighted", "autograd"],
+                    help="search: the headline fused search (default); batch: 36 beams in one "
+                         "persistent launch; weighted: 4096-channel fp32-weighted dedispersion; "
+                         "autograd: forward / adjoint timing of the 8-tap learnable profile")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (the reference kernel "
                          "for scaling HBM byte counters) and exit")
@@ -97,6 +102,8 @@ def main() -> int:
     import paper_1301_3968_amd as dd
     import workloads
 
+    if args.workload != "search":
+        return _other_workload(args, dd, workloads)
     print("generating the 336-channel workload", file=sys.stderr, flush=True)
     wl = workloads.cfg2(rule=args.rule)
     plan = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule=args.rule)
@@ -163,6 +170,116 @@ def main() -> int:
     if not args.no_cpu_baseline:
         print("timing the oracle on a sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(wl, start, ntap, args.cpu_sample_trials)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def _timed(fn, steps: int, warmup: int):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def _other_workload(args, dd, workloads) -> int:
+    """Secondary measurements (one JSON line each); not the headline metric."""
+    import math
+
+    import numpy as np
+    import torch
+    K, W = args.steps, args.warmup
+    base = {"n_gpus": 1, "steps": K, "warmup": W, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "data": "synthetic"}
+    if args.workload == "batch":
+        spec = workloads.cfg4_beams()
+        C = 336
+        f = workloads.channel_centres(1.2, 0.336, C)
+        eps = math.sqrt(0.8 ** -4 - 1.0) / 2.0       # spacing one DM error apart, 0.8 of optimal
+        plans, xs = [], []
+        print("generating 36 beams", file=sys.stderr, flush=True)
+        for b in range(len(spec["nsamp"])):
+            dms = dd.trial_dms(0.0, 1e9, eps, f, 0.001, 1e-3, cap=int(spec["ntrial"][b]))
+            x, _ = workloads.cfg4_beam_data(b, int(spec["nsamp"][b]), float(dms[0]), float(dms[-1]))
+            plans.append(dd.Plan(f, 0.001, 1e-3, dms, rule="allnonzero"))
+            xs.append(torch.from_numpy(x).cuda())
+        for p_ in plans:
+            p_.set_tile(plans[0].autotune(xs[0], list(range(1, 33)), np.full(C, 128.0), np.full(C, 16.0)))
+        widths = list(range(1, 33))
+        B = dd.Batch(plans, [int(v) for v in spec["nsamp"]], widths)
+        mu = torch.full((C,), 128.0, dtype=torch.float64, device="cuda")
+        sg = torch.full((C,), 16.0, dtype=torch.float64, device="cuda")
+        work = torch.empty(B.work_bytes, dtype=torch.uint8, device="cuda")
+        outs = tuple(torch.empty(B.total_trials, dtype=dt, device="cuda")
+                     for dt in (torch.float64, torch.int32, torch.int32))
+        t_graph = _timed(lambda: B.run(xs, mu, sg, work=work, outputs=outs, graph=True), K, W)
+        t_eager = _timed(lambda: B.run(xs, mu, sg, work=work, outputs=outs, graph=False), K, W)
+        # per-sum cost of the same beams searched one plan at a time
+        pw = [torch.empty(p_.work_bytes(x.shape[1], 32), dtype=torch.uint8, device="cuda")
+              for p_, x in zip(plans, xs)]
+        t_single = _timed(lambda: [p_.search(x, widths, mu, sg, work=w_) for p_, x, w_ in
+                                   zip(plans, xs, pw)], K, W)
+        line = dict(base, metric="DM-trial*channel*sample sums/s (36-beam batch)",
+                    value=B.total_sums / t_graph, unit="sums/s", ms_per_step=t_graph * 1e3,
+                    dtype="int32",
+                    config={"workload": "36 beams x 336 ch, lengths U{16384..131072}, "
+                                        "trial-DM grids of 300-1200 trials (0.8 of optimal)",
+                            "total_trials": B.total_trials, "total_sums": B.total_sums,
+                            "ms_eager": t_eager * 1e3, "ms_one_plan_at_a_time": t_single * 1e3})
+    elif args.workload == "weighted":
+        print("generating the 4096-channel block", file=sys.stderr, flush=True)
+        wl = workloads.cfg3()
+        p_ = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule=wl.rule, wmode="channel",
+                     weights=wl.weights)
+        x = torch.from_numpy(wl.x).cuda()
+        nout = p_.out_len(x.shape[1])
+        y = torch.empty((len(wl.dms), nout), dtype=torch.float32, device="cuda")
+        t = _timed(lambda: p_.dedisperse(x, out=y[None]), K, W)
+        sums = float(len(wl.dms)) * x.shape[0] * nout
+        line = dict(base, metric="DM-trial*channel*sample sums/s (fp32 channel weights)",
+                    value=sums / t, unit="sums/s", ms_per_step=t * 1e3, dtype="fp32",
+                    config={"workload": "4096 ch x 262144 samples uint8, 4096 trial DMs, "
+                                        "weights (f/1.35 GHz)^-1.5", "nout": nout})
+    else:
+        from paper_1301_3968_amd.autograd import matched_filter_loss
+        print("generating the 64-pulse batch", file=sys.stderr, flush=True)
+        wl = workloads.cfg5()
+        Kt = wl.extra["ktaps"]
+        p_ = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule="fixed", ktaps=Kt,
+                     wmode="tap", weights=wl.weights)
+        x = torch.from_numpy(wl.x).cuda()
+        nout = p_.out_len(x.shape[2])
+        bi = np.arange(len(wl.pulses))
+        di = np.array([q[1] for q in wl.pulses])
+        ti = np.array([min(q[2], nout - 1) for q in wl.pulses])
+        w = torch.from_numpy(wl.weights.copy()).cuda().requires_grad_(True)
+        y = torch.empty((x.shape[0], len(wl.dms), nout), dtype=torch.float32, device="cuda")
+        t_fwd = _timed(lambda: p_.dedisperse(x, weights=w.detach(), out=y), K, W)
+        g = torch.zeros_like(y)
+        g[torch.as_tensor(bi).cuda(), torch.as_tensor(di).cuda(), torch.as_tensor(ti).cuda()] = 1.0
+        t_adj_dense = _timed(lambda: p_.backward(g, x, need_x=False, need_w=True,
+                                                 weights=w.detach()), K, W)
+        val = torch.ones(len(bi), device="cuda")
+        t_adj_sparse = _timed(lambda: p_.backward_sparse(x, bi, di, ti, val), K, W)
+
+        def step():
+            w.grad = None
+            matched_filter_loss(x, w, p_, bi, di, ti, sparse=True).backward()
+        t_train = _timed(step, K, W)
+        sums = float(x.shape[0]) * len(wl.dms) * x.shape[1] * nout
+        line = dict(base, metric="DM-trial*channel*sample sums/s (8-tap fp32 forward)",
+                    value=sums / t_fwd, unit="sums/s", ms_per_step=t_fwd * 1e3, dtype="fp32",
+                    config={"workload": "64 x 336 ch x 32768 fp32, 256 trial DMs, 8 taps",
+                            "ms_forward": t_fwd * 1e3, "ms_adjoint_dense": t_adj_dense * 1e3,
+                            "ms_adjoint_sparse": t_adj_sparse * 1e3,
+                            "ms_sparse_loss_step": t_train * 1e3,
+                            "ratio_fwd_plus_dense_adjoint": (t_fwd + t_adj_dense) / t_fwd,
+                            "ratio_dense_adjoint": t_adj_dense / t_fwd,
+                            "ratio_fwd_plus_sparse_adjoint": (t_fwd + t_adj_sparse) / t_fwd})
     print(json.dumps(line), flush=True)
     return 0
 
