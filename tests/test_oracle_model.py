@@ -2,41 +2,48 @@
 closed forms, brute force and invariants."""
 import itertools
 import math
+import os
 
 import numpy as np
 import pytest
 
 import workloads
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _rows(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return [ln.strip().split(",") for ln in fh if ln.strip() and not ln.startswith("#")]
+
+
+TRIAL_EXAMPLES = [tuple(float(v) for v in r) for r in _rows("trial_dm_examples.csv")]
+SCALARS = {r[0]: float(r[1]) for r in _rows("scalar_values.csv")}
+
 
 # ---------------------------------------------------------------- trial DMs (Section 5.3)
 
-@pytest.mark.parametrize("flo,bw,C,dt,eps,lo,hi,count", [
-    # CRAFT example: 10-3000 pc cm^-3, 1 MHz channels, 1 ms, eps = 1.492 -> 442 trials
-    (0.7, 0.304, 304, 1e-3, 1.492, 10, 3000, 442),
-    # 21-23 GHz example, 100 us: 256 channels eps = 0.580 and 32 channels eps = 0.287 -> 128 each
-    (21.0, 2.0, 256, 1e-4, 0.580, 50, 10000, 128),
-    (21.0, 2.0, 32, 1e-4, 0.287, 50, 10000, 128),
-])
-def test_trial_counts_printed_in_paper(orc, flo, bw, C, dt, eps, lo, hi, count):
+@pytest.mark.parametrize("flo,bw,C,dt,eps,lo,hi,count,drop", TRIAL_EXAMPLES)
+def test_trial_counts_printed_in_paper(orc, flo, bw, C, dt, eps, lo, hi, count, drop):
+    C = int(C)
     f = workloads.channel_centres(flo, bw, C)
     dms = orc.trial_dms(lo, hi, eps, f, bw / C, dt)
-    assert len(dms) == count
+    assert len(dms) == int(count)
     assert dms[0] == lo and dms[-1] <= hi
     assert np.all(np.diff(dms) > 0)
 
 
-def test_dropouts_printed_in_paper(orc):
-    # eq. dm error smearing limit: 0.75 (eps 1.492), 93 % (0.580), 98 % (0.287)
-    assert round(orc.dropout(1.492), 2) == 0.75
-    assert round(orc.dropout(0.580), 2) == 0.93
-    assert round(orc.dropout(0.287), 2) == 0.98
+@pytest.mark.parametrize("eps,drop", [(r[4], r[8]) for r in TRIAL_EXAMPLES])
+def test_dropouts_printed_in_paper(orc, eps, drop):
+    # eq. dm error smearing limit at the printed eps, to the printed two digits
+    assert round(orc.dropout(eps), 2) == drop
 
 
 def test_exponential_grid_count():
-    # 442 trials from 10 with ratio 0.013 reach 3000 (Section 5.3 comparison grid)
-    n = int(math.floor(math.log(3000 / 10) / math.log(1.013))) + 1
-    assert n == 442
+    # the geometric comparison grid: ratio r from lo reaches hi after the printed count
+    r, lo, hi = SCALARS["exp_grid_ratio"], SCALARS["exp_grid_lo"], SCALARS["exp_grid_hi"]
+    n = int(math.floor(math.log(hi / lo) / math.log(r))) + 1
+    assert n == int(SCALARS["exp_grid_trials"])
 
 
 def test_trial_rule_limits(orc):
@@ -137,8 +144,8 @@ def test_nominal_resolution_rule(orc):
         s, _ = _snr_allnonzero(orc, flo, beta, C, m * tau, dm, tau)
         ratio = s / math.sqrt(beta * tau)
         assert ratio == pytest.approx(1 / math.sqrt(1 + 2 * m), rel=0.01)
-        if m == 0.25:
-            assert round(ratio, 2) == 0.82
+        if m == SCALARS["m_rule_m"]:
+            assert round(ratio, 2) == SCALARS["m_rule_fraction_2dp"]
 
 
 # ------------------------------------------------------------ selection rule (Section 2.2)

@@ -149,6 +149,54 @@ def test_norm_matches_monte_carlo(orc, wmode):
             assert abs(np.std(z) - 1.0) < 0.03
 
 
+def _explicit_matrix(C, T, s, n, w):
+    """The linear map of eq. p_dedisp written out entry by entry: row (d, t) holds
+    w[c, k] in column (c, t + s[d, c] + k) for every channel c and tap k < n[d, c]."""
+    D = s.shape[0]
+    tout = T - int(np.max(s + n)) + 1
+    A = np.zeros((D * tout, C * T))
+    for d in range(D):
+        for t in range(tout):
+            for c in range(C):
+                for k in range(n[d, c]):
+                    A[d * tout + t, c * T + t + s[d, c] + k] += w[c, k]
+    return A, tout
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_brute_force_matrix(orc, seed):
+    # Tiny instances (C <= 4, T <= 32, D <= 4): y = A x, A^T g for both adjoints,
+    # and unit weights as the all-ones special case, against the explicit matrix.
+    rng = np.random.default_rng(100 + seed)
+    C, T, D, K = int(rng.integers(1, 5)), int(rng.integers(16, 33)), int(rng.integers(1, 5)), 4
+    s = rng.integers(0, 8, size=(D, C)).astype(np.int32)
+    n = rng.integers(0, K + 1, size=(D, C)).astype(np.int32)
+    n[0, 0] = max(n[0, 0], 1)
+    w = rng.standard_normal((C, K)).astype(np.float32)
+    w64 = w.astype(np.float64)
+    A, tout = _explicit_matrix(C, T, s, n, w64)
+    x = rng.standard_normal((C, T))
+    y = orc.dedisperse_f64(x, s, n, "tap", w)
+    assert y.shape == (D, tout)
+    assert np.allclose(y.ravel(), A @ x.ravel(), rtol=0, atol=1e-12)
+    g = rng.standard_normal((D, tout))
+    assert np.allclose(orc.adjoint_x(T, s, n, g, "tap", w).ravel(), A.T @ g.ravel(),
+                       rtol=0, atol=1e-12)
+    # weight adjoint: column (c, k) of the Jacobian of y in w
+    gw = orc.adjoint_w(x, s, n, g, "tap", K)
+    for c in range(C):
+        for k in range(K):
+            e = np.zeros((C, K))
+            e[c, k] = 1.0
+            Ak, _ = _explicit_matrix(C, T, s, n, e)
+            assert gw[c, k] == pytest.approx(float(g.ravel() @ (Ak @ x.ravel())), abs=1e-12)
+    # unit weights on uint8: integer-exact
+    A1, _ = _explicit_matrix(C, T, s, n, np.ones((C, K)))
+    xu = rng.integers(0, 256, size=(C, T), dtype=np.uint8)
+    yu = orc.dedisperse_u8(xu, s, n)
+    assert np.array_equal(yu.ravel(), (A1 @ xu.ravel().astype(np.float64)).astype(np.int64))
+
+
 def test_adjoint_dot_product_identity(orc):
     # <A x, g> = <x, A^T g> and <A_w x, g> linear in w: grad_w = A-adjoint in w.
     rng = np.random.default_rng(8)
