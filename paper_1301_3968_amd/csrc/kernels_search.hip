@@ -49,7 +49,10 @@ constexpr int kHalo = 32;                 // boxcar widths up to 32
 // Time-tile step: TY minus a halo of at least 31 outputs, rounded so that every
 // lane (SP = 2 * r2 consecutive starts) owns either all or none of its starts.
 constexpr int tile_step(int r2) { return 128 * r2 - ((32 + 2 * r2 - 1) / (2 * r2)) * (2 * r2); }
-constexpr int kStageBudget = 32 * 1024;   // LDS bytes for one channel group's windows
+// LDS bytes for one channel group's windows, smallest first: two such buffers per
+// workgroup (double buffering) let four, three or two workgroups share a CU's
+// 160 KiB.  A plan takes the smallest budget that holds every channel's windows.
+constexpr int kStageBudgets[3] = {19968, 26624, 39936};
 
 struct GroupInfo {
   int32_t job_begin, njobs, lw, c_begin;   // lw: window length in samples (multiple of 8)
@@ -58,7 +61,7 @@ struct GroupInfo {
 
 struct TiledCfgTables {
   bool ok = false;
-  int dt = 0, ty = 0, tt = 0, ntd = 0, ngroups = 0, lds_bytes = 0;
+  int dt = 0, ty = 0, tt = 0, ntd = 0, ngroups = 0, lds_bytes = 0, bufbytes = 0;
   std::vector<int32_t> offs;          // [ntd*dt][nchan] LDS byte offsets
   std::vector<GroupInfo> groups;      // flat
   std::vector<int32_t> group_begin;   // [ntd+1]
@@ -110,20 +113,23 @@ __device__ __forceinline__ uint32_t pk_add_u16(uint32_t a, uint32_t b) {
   return __builtin_bit_cast(uint32_t, va + vb);
 }
 
-// U_{c,n}[tau] for tau in [0, tpad), n in [nmin_c, nmax_c]; each thread makes 8
-// consecutive tau of every row of its channel from bytes staged in LDS.
+// U_{c,n}[tau] for tau in [0, tpad), n in [nmin_c, nmax_c], and the same rows one
+// sample later, U1_{c,n}[tau] = U_{c,n}[tau + 1], so that a window starting at
+// either parity can be copied to LDS from a dword-aligned source.  Each thread
+// makes 8 consecutive tau of every row of its channel from bytes staged in LDS.
 constexpr int kRowThreads = 256;
 constexpr int kRowSpan = kRowThreads * 8;   // tau per block
 __global__ void __launch_bounds__(kRowThreads)
 k_window_rows(const uint8_t *__restrict__ x, int64_t in_stride, int64_t nsamp, int64_t tpad,
               const int32_t *__restrict__ nmin, const int32_t *__restrict__ nmaxv,
-              const int64_t *__restrict__ rowidx, uint16_t *__restrict__ U) {
+              const int64_t *__restrict__ rowidx, uint16_t *__restrict__ U,
+              uint16_t *__restrict__ U1) {
   extern __shared__ unsigned char sx[];
   const int c = blockIdx.y, tid = threadIdx.x;
   const int64_t blk0 = (int64_t)blockIdx.x * kRowSpan;
   const int n0 = nmin[c], n1 = nmaxv[c];
   const uint8_t *row = x + (int64_t)c * in_stride;
-  const int nbytes = kRowSpan + n1;
+  const int nbytes = kRowSpan + 1 + n1;
   for (int i = tid; i < nbytes; i += kRowThreads) {
     const int64_t g = blk0 + i;
     sx[i] = g < nsamp ? row[g] : 0;
@@ -131,35 +137,36 @@ k_window_rows(const uint8_t *__restrict__ x, int64_t in_stride, int64_t nsamp, i
   __syncthreads();
   const int64_t tau0 = blk0 + tid * 8;
   if (tau0 >= tpad) return;
-  uint32_t s[8];
+  uint32_t s[9];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) s[i] = 0;
+  for (int i = 0; i < 9; ++i) s[i] = 0;
   const unsigned char *b = sx + tid * 8;
   for (int n = 1; n <= n1; ++n) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) s[i] += b[i + n - 1];
+    for (int i = 0; i < 9; ++i) s[i] += b[i + n - 1];
     if (n >= n0) {
-      uint16_t *dst = U + (rowidx[c] + (n - n0)) * tpad + tau0;
-      uint32_t w[4];
+      // windows running past the end of the block are zero
+      uint32_t v[9];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        // windows running past the end of the block are zero
-        const uint32_t lo = (tau0 + 2 * i + n <= nsamp) ? s[2 * i] : 0u;
-        const uint32_t hi = (tau0 + 2 * i + 1 + n <= nsamp) ? s[2 * i + 1] : 0u;
-        w[i] = lo | (hi << 16);
-      }
-      *(uint4 *)dst = make_uint4(w[0], w[1], w[2], w[3]);
+      for (int i = 0; i < 9; ++i) v[i] = (tau0 + i + n <= nsamp) ? s[i] : 0u;
+      const int64_t r = (rowidx[c] + (n - n0)) * tpad + tau0;
+      *(uint4 *)(U + r) = make_uint4(v[0] | (v[1] << 16), v[2] | (v[3] << 16),
+                                     v[4] | (v[5] << 16), v[6] | (v[7] << 16));
+      *(uint4 *)(U1 + r) = make_uint4(v[1] | (v[2] << 16), v[3] | (v[4] << 16),
+                                      v[5] | (v[6] << 16), v[7] | (v[8] << 16));
     }
   }
   if (n0 == 0) {
-    uint16_t *dst = U + rowidx[c] * tpad + tau0;
-    *(uint4 *)dst = make_uint4(0, 0, 0, 0);
+    const int64_t r = rowidx[c] * tpad + tau0;
+    *(uint4 *)(U + r) = make_uint4(0, 0, 0, 0);
+    *(uint4 *)(U1 + r) = make_uint4(0, 0, 0, 0);
   }
 }
 
 struct SearchArgs {
-  const uint16_t *U;
+  const uint16_t *U, *U1;   // window rows and the same rows one sample later
   int64_t tpad;
+  int32_t bufbytes;         // LDS bytes of one of the two window buffers
   const int32_t *offs;
   const GroupInfo *groups;
   const int32_t *group_begin;
@@ -196,11 +203,76 @@ __device__ __forceinline__ int bitrev5(int v) {
   return ((v & 1) << 4) | ((v & 2) << 2) | (v & 4) | ((v & 8) >> 2) | ((v & 16) >> 4);
 }
 
-// Staging slots per thread per channel group: a group holds at most
-// kStageBudget / 32 chunks of 8 samples, spread over 256 threads.
-constexpr int kSlots = (kStageBudget / 32 + 255) / 256;
 // 8-sample chunks per lane when a wave stages one window (windows up to 1536 samples)
 constexpr int kRowChunks = 3;
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Read-only tables read through the constant address space: their fields become
+// scalar loads, which do not share the vector memory counter with the direct
+// global-to-LDS copies (the compiler cannot prove on its own that those copies
+// leave the tables untouched).
+__device__ __forceinline__ int32_t ldc(const int32_t *p, int64_t i) {
+  return ((const __attribute__((address_space(4))) int32_t *)p)[i];
+}
+
+__device__ __forceinline__ GroupInfo load_group(const GroupInfo *groups, int g) {
+  static_assert(sizeof(GroupInfo) == 8 * sizeof(int32_t), "GroupInfo layout");
+  const int32_t *q = (const int32_t *)(groups + g);
+  GroupInfo gi;
+  gi.job_begin = ldc(q, 0);
+  gi.njobs = ldc(q, 1);
+  gi.lw = ldc(q, 2);
+  gi.c_begin = ldc(q, 3);
+  gi.c_count = ldc(q, 4);
+  gi.flush = ldc(q, 5);
+  gi.inv_nchunk = ldc(q, 6);
+  gi.pad1 = 0;
+  return gi;
+}
+
+// Starts the copy of group gi's windows into one LDS buffer: copy A of a window
+// (aligned to its first sample) and copy B (one sample later), each from the row
+// parity whose start is dword-aligned.  Whole windows go to waves; lanes move
+// 16-byte chunks with direct global-to-LDS loads, which complete asynchronously
+// (the caller waits on the vector memory counter before its barrier).
+template <typename Args>
+__device__ __forceinline__ void stage_group(Args &a, const GroupInfo &gi, int64_t t0, int wave,
+                                            int lane, unsigned char *buf) {
+  const int nchunk = gi.lw >> 3;
+  for (int j = wave; j < gi.njobs; j += 4) {
+    const int32_t *jp = (const int32_t *)(a.jobs + gi.job_begin + j);
+    const int jrow = ldc(jp, 0), jstart = ldc(jp, 1);
+    const int64_t e0 = (int64_t)jstart + t0;
+    const int64_t base = (int64_t)jrow * a.tpad + (e0 & ~(int64_t)1);
+    const bool odd = (e0 & 1) != 0;
+    const uint16_t *srcA = (odd ? a.U1 : a.U) + base;        // U[e0 ...]
+    const uint16_t *srcB = odd ? a.U + base + 2 : a.U1 + base;  // U[e0 + 1 ...]
+    unsigned char *rowA = buf + j * 4 * gi.lw;
+    unsigned char *rowB = rowA + 2 * gi.lw;
+#pragma unroll
+    for (int k = 0; k < kRowChunks; ++k) {
+      const int ch = lane + 64 * k;
+      if (ch < nchunk) {
+        __builtin_amdgcn_global_load_lds(srcA + 8 * ch, (lds_void *)(rowA + 1024 * k), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(srcB + 8 * ch, (lds_void *)(rowB + 1024 * k), 16, 0, 0);
+      }
+    }
+  }
+}
+
+// LDS read offset of (trial trial0 + lane / cc, channel c_begin + lane % cc) for the
+// first DPW * cc lanes; broadcast later with v_readlane.
+template <int DPW, typename Args>
+__device__ __forceinline__ int group_offsets(Args &a, const GroupInfo &gi, int trial0, int lane) {
+  const int cc = gi.c_count;
+  int o = 0;
+  if (lane < DPW * cc) {
+    const int jj = lane / cc, c = lane - jj * cc;
+    o = a.offs[(int64_t)(trial0 + jj) * a.nchan + gi.c_begin + c];
+  }
+  return o;
+}
 
 // One (DM tile, time tile) of the fused search: channel-group loop, then the
 // boxcar stage.  Shared by the one-plan grid kernel and the multi-beam persistent
@@ -225,69 +297,31 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
     for (int r = 0; r < R2; ++r) a16[j][r] = 0;
   }
 
-  const int gb = a.group_begin[td], ge = a.group_begin[td + 1];
+  const int gb = ldc(a.group_begin, td), ge = ldc(a.group_begin, td + 1);
   const int trial0 = td * DT + wave * DPW;
-  for (int g = gb; g < ge; ++g) {
-    const GroupInfo gi = a.groups[g];
-    // LDS read offsets of this wave's (trial, channel) pairs, one per lane;
-    // broadcast later with v_readlane (no memory latency in the inner loop).
-    const int cc = gi.c_count;
-    int myoff = 0;
-    if (lane < DPW * cc) {
-      const int jj = lane / cc, c = lane - jj * cc;
-      myoff = a.offs[(int64_t)(trial0 + jj) * a.nchan + gi.c_begin + c];
-    }
-    // ---- stage the group's U windows: copy A (aligned to the window start) and
-    // copy B (one sample later).  Whole windows go to waves, so the window's
-    // source, destination and parity are scalar; lanes take 8-sample chunks.
-    __syncthreads();   // the previous group's reads of LDS are done
-    {
-      const int nchunk = gi.lw >> 3;
-      for (int j = wave; j < gi.njobs; j += 4) {
-        const int2 jb = a.jobs[gi.job_begin + j];
-        const int64_t e0 = (int64_t)jb.x * a.tpad + jb.y + t0;
-        const uint32_t *src = (const uint32_t *)(a.U + (e0 & ~(int64_t)1));
-        unsigned char *rowA = lds + j * 4 * gi.lw;
-        unsigned char *rowB = rowA + 2 * gi.lw;
-        uint32_t w[kRowChunks][5];
-#pragma unroll
-        for (int k = 0; k < kRowChunks; ++k) {
-          const int ch = lane + 64 * k;
-          if (ch < nchunk) {
-#pragma unroll
-            for (int u = 0; u < 5; ++u) w[k][u] = src[4 * ch + u];
-          }
-        }
-        if (e0 & 1) {
-#pragma unroll
-          for (int k = 0; k < kRowChunks; ++k) {
-            const int ch = lane + 64 * k;
-            if (ch < nchunk) {
-              *(uint4 *)(rowA + ch * 16) = make_uint4(__builtin_amdgcn_alignbyte(w[k][1], w[k][0], 2),
-                                                      __builtin_amdgcn_alignbyte(w[k][2], w[k][1], 2),
-                                                      __builtin_amdgcn_alignbyte(w[k][3], w[k][2], 2),
-                                                      __builtin_amdgcn_alignbyte(w[k][4], w[k][3], 2));
-              *(uint4 *)(rowB + ch * 16) = make_uint4(w[k][1], w[k][2], w[k][3], w[k][4]);
-            }
-          }
-        } else {
-#pragma unroll
-          for (int k = 0; k < kRowChunks; ++k) {
-            const int ch = lane + 64 * k;
-            if (ch < nchunk) {
-              *(uint4 *)(rowA + ch * 16) = make_uint4(w[k][0], w[k][1], w[k][2], w[k][3]);
-              *(uint4 *)(rowB + ch * 16) = make_uint4(__builtin_amdgcn_alignbyte(w[k][1], w[k][0], 2),
-                                                      __builtin_amdgcn_alignbyte(w[k][2], w[k][1], 2),
-                                                      __builtin_amdgcn_alignbyte(w[k][3], w[k][2], 2),
-                                                      __builtin_amdgcn_alignbyte(w[k][4], w[k][3], 2));
-            }
-          }
-        }
-      }
-    }
+  // Software pipeline over channel groups: while the waves accumulate group g from
+  // one LDS buffer, the windows of group g + 1 stream into the other.
+  int myoff;
+  {
+    const GroupInfo g0 = load_group(a.groups, gb);
+    myoff = group_offsets<DPW>(a, g0, trial0, lane);
+    stage_group(a, g0, t0, wave, lane, lds);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    asm volatile("" ::"v"(myoff));
     __syncthreads();
+  }
+  for (int g = gb; g < ge; ++g) {
+    const GroupInfo gi = load_group(a.groups, g);
+    const int cc = gi.c_count;
+    const int par = (g - gb) & 1;
+    int nextoff = 0;
+    if (g + 1 < ge) {
+      const GroupInfo gn = load_group(a.groups, g + 1);
+      nextoff = group_offsets<DPW>(a, gn, trial0, lane);
+      stage_group(a, gn, t0, wave, lane, lds + (par ^ 1) * a.bufbytes);
+    }
     // ---- accumulate: per trial, per channel, R2 aligned dword reads
-    const unsigned char *lbase = lds + lane * 4;
+    const unsigned char *lbase = lds + par * a.bufbytes + lane * 4;
 #pragma unroll
     for (int j = 0; j < DPW; ++j) {
       int c = 0;
@@ -324,6 +358,11 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
         }
       }
     }
+    // the next group's windows and offsets have landed; this group's reads are done
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    asm volatile("" ::"v"(nextoff));
+    __syncthreads();
+    myoff = nextoff;
   }
 
   // ---- boxcar search, one trial of each wave at a time.  Each lane owns SP
@@ -516,7 +555,17 @@ static void build_rows(const dedisp_plan_s *p, TiledTables *T) {
 // Groups of channels per DM tile, their LDS window layout and the per-(trial,
 // channel) LDS read offsets.  Returns false if some channel's windows alone exceed
 // the LDS budget or a single run could wrap a uint16 lane.
+static bool build_cfg_budget(const dedisp_plan_s *p, const TiledTables &T, int ci, int budget,
+                             TiledCfgTables &out);
+
 static bool build_cfg(const dedisp_plan_s *p, const TiledTables &T, int ci, TiledCfgTables &out) {
+  for (int budget : kStageBudgets)
+    if (build_cfg_budget(p, T, ci, budget, out)) return true;
+  return false;
+}
+
+static bool build_cfg_budget(const dedisp_plan_s *p, const TiledTables &T, int ci, int budget,
+                             TiledCfgTables &out) {
   const TileCfg cf = kCfgs[ci];
   const int C = p->nchan, D = p->ndm;
   const int DT = 4 * cf.dpw, TY = 128 * cf.r2;
@@ -564,8 +613,8 @@ static bool build_cfg(const dedisp_plan_s *p, const TiledTables &T, int ci, Tile
         const int lw = ((TY + nspan + 2) + 7) & ~7;
         const int bytes = lw > 64 * 8 * kRowChunks ? INT32_MAX / 2   // window too long for one wave
                                                     : (nrows_g + (int)ns.size()) * 4 * lw;
-        if (ccount == 0 && (bytes > kStageBudget || over)) return false;
-        if (bytes > kStageBudget || over || ccount >= 64 / cf.dpw) break;
+        if (ccount == 0 && (bytes > budget || over)) return false;
+        if (bytes > budget || over || ccount >= 64 / cf.dpw) break;
         span = nspan;
         nrows_g += (int)ns.size();
         for (int j = 0; j < DT; ++j) run[j] += 255LL * p->ntap[(size_t)tr[j] * C + c];
@@ -615,7 +664,8 @@ static bool build_cfg(const dedisp_plan_s *p, const TiledTables &T, int ci, Tile
   }
   out.group_begin[ntd] = (int)out.groups.size();
   out.ngroups = (int)out.groups.size();
-  out.lds_bytes = std::max(lds_max, 4 * (TY + kHalo + 4 + 32) * 4);
+  out.bufbytes = (lds_max + 15) & ~15;
+  out.lds_bytes = std::max(2 * out.bufbytes, 4 * (TY + kHalo + 4 + 32) * 4);
   out.ok = true;
   return true;
 }
@@ -675,7 +725,7 @@ static Layout layout(const dedisp_plan_s *p, int ci, int32_t nw, int64_t nout, i
   const size_t tables = align256(2 * sizeof(double) * (size_t)p->ndm * nw);
   L.off_part = tables;
   L.off_u = L.off_part + align256(sizeof(CandRec) * (size_t)p->ndm * L.ntt);
-  L.total = L.off_u + align256(sizeof(uint16_t) * (size_t)nrows * L.tpad);
+  L.total = L.off_u + align256(2 * sizeof(uint16_t) * (size_t)nrows * L.tpad);
   return L;
 }
 
@@ -758,12 +808,14 @@ static dedisp_status prepare_tiled(dedisp_plan p, int ci, const uint8_t *x, int6
     const dim3 g((unsigned)((L.tpad + kRowSpan - 1) / kRowSpan), (unsigned)p->nchan);
     const int shm = kRowSpan + T.nmax_all + 16;
     hipLaunchKernelGGL(k_window_rows, g, dim3(kRowThreads), shm, s, x, in_stride, nsamp, L.tpad,
-                       T.d_nmin, T.d_nmax, T.d_rowidx, U);
+                       T.d_nmin, T.d_nmax, T.d_rowidx, U, U + (size_t)T.nrows * L.tpad);
     DD_HIP(hipGetLastError());
   }
   SearchArgs a{};
   a.U = U;
+  a.U1 = U + (size_t)T.nrows * L.tpad;
   a.tpad = L.tpad;
+  a.bufbytes = cfg->bufbytes;
   a.offs = cfg->d_offs;
   a.groups = cfg->d_groups;
   a.group_begin = cfg->d_group_begin;
