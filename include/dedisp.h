@@ -207,7 +207,7 @@ dedisp_status dedisp_trial_dms(double dm0, double dm_max, double eps, int32_t nc
                                double *out, int32_t *n_out);
 
 /* Batched search over many beams, each with its own plan (own DM grid) and
- * block length, as one persistent launch.  plans[nbeam] must share nchan and
+ * block length, as one launch over every beam's tiles.  plans[nbeam] must share nchan and
  * use UNIT weights with uint8 input.  widths host [nw]. */
 dedisp_status dedisp_batch_create(dedisp_batch *out, int32_t nbeam, const dedisp_plan *plans,
                                   const int64_t *nsamp, const int32_t *widths, int32_t nw);

@@ -298,7 +298,7 @@ Plan.autotune = _autotune
 
 class Batch:
     """Many beams (each with its own plan and block length) searched by one
-    persistent launch; `run(..., graph=True)` replays a captured HIP graph."""
+    launch over every beam's tiles; `run(..., graph=True)` replays a captured HIP graph."""
 
     def __init__(self, plans: Sequence[Plan], nsamp: Sequence[int], widths: Sequence[int]):
         self.plans = list(plans)

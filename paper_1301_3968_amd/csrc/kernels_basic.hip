@@ -180,40 +180,100 @@ __device__ __forceinline__ void norm_terms(int wmode, int K, const float *__rest
   }
 }
 
-// One block per trial: channel terms summed by the block for every width.
+// Noise statistics of every (trial, width).  One workgroup per kNormTrials trials;
+// per trial, 32 width lanes (each taking widths j and j + 32) times kNormSplit
+// channel residues.  The trials' tap counts and the channel statistics are staged
+// in LDS a chunk of channels at a time; the kNormSplit partial sums of a (trial,
+// width) are added in a fixed order, so results do not vary between runs.
+constexpr int kNormTrials = 2, kNormSplit = 4, kNormChunk = 512;
+static_assert(kThreads == kNormTrials * 32 * kNormSplit, "thread layout of k_norm");
+
+// Sum and sum of squares of the n-box convolved with the W-box: a trapezoid
+// 1, 2, .., L, .., L, .., 2, 1 with L = min(n, W) (exact integers).
+__device__ __forceinline__ void trapezoid(int n, int W, double &s1, double &s2) {
+  const int L = min(n, W), H = max(n, W);
+  s1 = (double)n * (double)W;
+  if (L < 1024) {
+    s2 = (double)((L - 1) * L * (2 * L - 1) / 3) + (double)(H - L + 1) * (double)L * (double)L;
+  } else {
+    const double ld = L;
+    s2 = (ld - 1.0) * ld * (2.0 * ld - 1.0) / 3.0 + (double)(H - L + 1) * ld * ld;
+  }
+}
+
 __global__ void __launch_bounds__(kThreads)
 k_norm(const int32_t *__restrict__ ntap, int32_t nchan, int32_t ndm, int32_t wmode, int32_t K,
        const float *__restrict__ w, const double *__restrict__ mu,
        const double *__restrict__ sigma, WidthList wl, double *__restrict__ M,
        double *__restrict__ S) {
-  const int d = blockIdx.x, tid = threadIdx.x;
-  __shared__ double rm[kThreads], rv[kThreads];
-  for (int j = 0; j < wl.n; ++j) {
-    const int W = wl.w[j];
-    double m = 0.0, v = 0.0;
-    for (int c = tid; c < nchan; c += kThreads) {
-      const int n = ntap[(int64_t)d * nchan + c];
-      if (n == 0) continue;
-      double s1, s2;
-      norm_terms(wmode, K, w, c, n, W, s1, s2);
-      m += mu[c] * s1;
-      v += sigma[c] * sigma[c] * s2;
-    }
-    rm[tid] = m;
-    rv[tid] = v;
+  __shared__ int32_t sn[kNormTrials][kNormChunk];
+  __shared__ double smu[kNormChunk], svar[kNormChunk];
+  __shared__ double part[kNormTrials][2][64][kNormSplit];
+  const int tid = threadIdx.x, d0 = blockIdx.x * kNormTrials;
+  const int tj = tid / (32 * kNormSplit), rest = tid % (32 * kNormSplit);
+  const int split = rest / 32, jlane = rest % 32;
+  const int d = d0 + tj;
+  int Wh[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) Wh[h] = (jlane + 32 * h < wl.n) ? wl.w[jlane + 32 * h] : 0;
+  double m[2] = {0.0, 0.0}, v[2] = {0.0, 0.0};
+  for (int c0 = 0; c0 < nchan; c0 += kNormChunk) {
+    const int cn = min(kNormChunk, nchan - c0);
     __syncthreads();
-    for (int off = kThreads / 2; off > 0; off >>= 1) {
-      if (tid < off) {
-        rm[tid] += rm[tid + off];
-        rv[tid] += rv[tid + off];
+    for (int i = tid; i < kNormTrials * kNormChunk; i += kThreads) {
+      const int t = i / kNormChunk, c = i - t * kNormChunk;
+      sn[t][c] = (c < cn && d0 + t < ndm) ? ntap[(int64_t)(d0 + t) * nchan + c0 + c] : 0;
+    }
+    for (int c = tid; c < cn; c += kThreads) {
+      smu[c] = mu[c0 + c];
+      svar[c] = sigma[c0 + c] * sigma[c0 + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int W = Wh[h];
+      if (W == 0) continue;
+      double mm = m[h], vv = v[h];
+      for (int c = split; c < cn; c += kNormSplit) {
+        const int n = sn[tj][c];
+        if (n == 0) continue;
+        double s1, s2;
+        if (wmode == DEDISP_W_TAP) {
+          norm_terms(wmode, K, w, c0 + c, n, W, s1, s2);
+        } else {
+          trapezoid(n, W, s1, s2);
+          if (wmode == DEDISP_W_CHANNEL) {
+            const double wc = (double)w[c0 + c];
+            s1 *= wc;
+            s2 *= wc * wc;
+          }
+        }
+        mm += smu[c] * s1;
+        vv += svar[c] * s2;
       }
-      __syncthreads();
+      m[h] = mm;
+      v[h] = vv;
     }
-    if (tid == 0) {
-      M[(int64_t)d * wl.n + j] = rm[0];
-      S[(int64_t)d * wl.n + j] = sqrt(rv[0]);
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    part[tj][0][jlane + 32 * h][split] = m[h];
+    part[tj][1][jlane + 32 * h][split] = v[h];
+  }
+  __syncthreads();
+  if (split != 0 || d >= ndm) return;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int j = jlane + 32 * h;
+    if (j >= wl.n) continue;
+    double mm = 0.0, vv = 0.0;
+#pragma unroll
+    for (int q = 0; q < kNormSplit; ++q) {
+      mm += part[tj][0][j][q];
+      vv += part[tj][1][j][q];
     }
-    __syncthreads();
+    M[(int64_t)d * wl.n + j] = mm;
+    S[(int64_t)d * wl.n + j] = sqrt(vv);
   }
 }
 
@@ -576,7 +636,7 @@ hipError_t launch_dedisp_1tap_f32(const dedisp_plan_s *p, const float *z, int64_
 
 hipError_t launch_norm(const dedisp_plan_s *p, const WidthList &wl, const double *mu,
                        const double *sigma, double *M, double *S, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm, dim3((unsigned)p->ndm), dim3(kThreads), 0, s,
+  hipLaunchKernelGGL(k_norm, dim3((unsigned)((p->ndm + kNormTrials - 1) / kNormTrials)), dim3(kThreads), 0, s,
                      p->dev.ntap, p->nchan, p->ndm, p->wmode, p->ktaps, weights_of(p), mu, sigma,
                      wl, M, S);
   return hipGetLastError();

@@ -42,7 +42,7 @@ struct TileCfg {
   int dpw;   // trials per wave (4 waves per workgroup)
   int r2;    // packed output pairs per lane per row: outputs per tile row = 128 * r2
 };
-static const TileCfg kCfgs[] = {{4, 6}, {4, 8}, {2, 8}, {8, 4}, {4, 4}, {3, 8}};
+static const TileCfg kCfgs[] = {{4, 6}, {4, 8}, {2, 8}, {6, 4}, {4, 4}, {3, 8}};
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 constexpr int kDefaultCfg = 0;
 constexpr int kHalo = 32;                 // boxcar widths up to 32
@@ -275,8 +275,7 @@ __device__ __forceinline__ int group_offsets(Args &a, const GroupInfo &gi, int t
 }
 
 // One (DM tile, time tile) of the fused search: channel-group loop, then the
-// boxcar stage.  Shared by the one-plan grid kernel and the multi-beam persistent
-// kernel.
+// boxcar stage.  Shared by the one-plan kernel and the multi-beam kernel.
 template <int DPW, int R2, typename Args>
 __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
                                             unsigned char *lds) {
@@ -320,7 +319,9 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
       nextoff = group_offsets<DPW>(a, gn, trial0, lane);
       stage_group(a, gn, t0, wave, lane, lds + (par ^ 1) * a.bufbytes);
     }
-    // ---- accumulate: per trial, per channel, R2 aligned dword reads
+    // ---- accumulate: per trial, per channel, R2 aligned dword reads (pairs of
+    // them 256 bytes apart are merged into one two-address read, so one LDS
+    // instruction moves 512 bytes per wave)
     const unsigned char *lbase = lds + par * a.bufbytes + lane * 4;
 #pragma unroll
     for (int j = 0; j < DPW; ++j) {
@@ -366,11 +367,17 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
   }
 
   // ---- boxcar search, one trial of each wave at a time.  Each lane owns SP
-  // consecutive starts; per width the lane maximum goes to a per-wave LDS slot by
-  // an atomic max, so no per-width registers are held.
-  __syncthreads();
+  // consecutive starts of the tile.  Every wave transposes its series through its
+  // own LDS rows, so no workgroup barrier is needed until the stage ends (the
+  // group loop ended with one, so the window buffers are free).
   int *Yw = (int *)lds + wave * (YROW + 32);
   CandRec *part = (CandRec *)a.part;
+  // Only the tile holding the end of the series sees outputs past the last valid
+  // one.  Elsewhere every prefix entry is a real output, except the zero halo past
+  // TY: windows of lanes whose starts belong to the next tile may run into it and
+  // come out short, never larger than the same window in the tile that owns the
+  // start, which finds it exactly; so they cannot win falsely.
+  const bool tail = t0 + TY + kHalo > a.nout;
 #pragma unroll
   for (int j = 0; j < DPW; ++j) {
     const int dg = a.perm[td * DT + wave * DPW + j];
@@ -378,72 +385,107 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
     for (int r = 0; r < R2; ++r)
       *(int2 *)(Yw + 2 * lane + 128 * r) = make_int2(acc[j][2 * r], acc[j][2 * r + 1]);
     if (lane < kHalo) Yw[TY + lane] = 0;
-    __syncthreads();
+    // LDS operations of one wave complete in order: the reads below see the writes
+    __builtin_amdgcn_wave_barrier();
+    // Window sums come from the running prefix qv[k] = y[0] + .. + y[k-1] of this
+    // lane's SP + 32 outputs.  In the tail tile, prefix entries past the last
+    // valid output (all of them for lanes without starts in this tile) are pushed
+    // down so that every window that is not a valid (start, width) comes out
+    // negative; windows of unit-weight uint8 sums are otherwise >= 0.
+    const int *yl = Yw + lane * SP;
+    int lim = SP + kHalo;
+    if (tail) {
+      const int64_t room = a.nout - (t0 + lane * SP);
+      lim = (lane * SP < TT) ? (int)(room < SP + kHalo ? room : SP + kHalo) : -1;
+    }
     int qv[SP + kHalo + 1];
     qv[0] = 0;
 #pragma unroll
-    for (int i = 0; i < SP + kHalo; ++i) qv[i + 1] = qv[i] + Yw[lane * SP + i];
-    const int64_t ts = t0 + lane * SP;          // first start of this lane
-    const bool owned = lane * SP < TT;
-    // Windows of unit-weight uint8 sums are >= 0.  Entries of the prefix past the
-    // last valid output (or all of them, for lanes without starts in this tile)
-    // are pushed down so that every window that is not a valid (start, width) of
-    // this tile comes out negative: then the width loop needs no checks.
-    {
-      const int64_t room = a.nout - ts;
-      const int lim = owned ? (int)(room < SP + kHalo ? room : SP + kHalo) : -1;
-      if (lim < SP + kHalo) {
+    for (int k = 0; k < SP + kHalo; ++k) qv[k + 1] = qv[k] + yl[k];
+    __builtin_amdgcn_wave_barrier();
+    if (tail) {
 #pragma unroll
-        for (int k = 0; k <= SP + kHalo; ++k)
-          if (k > lim) qv[k] = (INT_MIN / 4) - (k - lim);
-      }
+      for (int k = 0; k <= SP + kHalo; ++k)
+        if (k > lim) qv[k] = (INT_MIN / 4) - (k - lim);
     }
-    // per width: the lane maximum over its starts, then the wave maximum, gathered
-    // so that lane w-1 (and lane w+31) holds the maximum for width w
-    int bmax = INT_MIN;
-    const int lane31 = lane & 31;
+    // Per width: the lane maximum over its starts (made for all 32 widths; the
+    // widths not searched are dropped at the S/N step), reduced across the wave
+    // by a transposed butterfly: each level
+    // halves the registers and doubles the lanes each register is reduced over.
+    // Widths are taken in ascending pairs (2r + 1, 2r + 2), so each prefix entry
+    // is needed only for a short run of widths, and the first level (lanes l,
+    // l ^ 32: the lower half keeps width 2r + 1, the upper half 2r + 2) runs as
+    // the maxima are made.
+    int mw[16];
 #pragma unroll
-    for (int w = 1; w <= 32; ++w) {
-      if ((a.wmask >> (w - 1)) & 1u) {
+    for (int r = 0; r < 16; ++r) {
+      int m2[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int w = 2 * r + h + 1;
         int m = qv[w] - qv[0];
 #pragma unroll
         for (int i = 1; i < SP; ++i) m = max(m, qv[i + w] - qv[i]);
-        const int wm = wave_max_i32(m);
-        bmax = (lane31 == w - 1) ? wm : bmax;
+        m2[h] = m;
       }
+      const auto p = __builtin_amdgcn_permlane32_swap(m2[0], m2[1], false, false);
+      mw[r] = max((int)p[0], (int)p[1]);
     }
-    // lane l takes width (l mod 32) + 1
-    const int wl = (lane & 31) + 1;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {    // lanes l, l ^ 16: rows 0, 2 keep r, rows 1, 3 r + 8
+      const auto p = __builtin_amdgcn_permlane16_swap(mw[r], mw[r + 8], false, false);
+      mw[r] = max((int)p[0], (int)p[1]);
+    }
+    const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {    // lanes l, l ^ 8 (rotate by 8 within a row)
+      int t = __builtin_amdgcn_update_dpp(0, mw[r + 4], 0x128, 0xf, 0xc, false);
+      t = __builtin_amdgcn_update_dpp(t, mw[r], 0x128, 0xf, 0x3, false);
+      mw[r] = max(b3 ? mw[r + 4] : mw[r], t);
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {    // lanes l, l ^ 4 (a row rotation by n moves lane i - n to i)
+      int t = __builtin_amdgcn_update_dpp(0, mw[r + 2], 0x124, 0xf, 0xa, false);
+      t = __builtin_amdgcn_update_dpp(t, mw[r], 0x12c, 0xf, 0x5, false);
+      mw[r] = max(b2 ? mw[r + 2] : mw[r], t);
+    }
+    {                                // lanes l, l ^ 2 (quad permutation 2, 3, 0, 1)
+      const int send = b1 ? mw[0] : mw[1];
+      const int t = __builtin_amdgcn_update_dpp(0, send, 0x4e, 0xf, 0xf, false);
+      mw[0] = max(b1 ? mw[1] : mw[0], t);
+    }
+    // lanes l, l ^ 1 (quad permutation 1, 0, 3, 2)
+    const int bmax = max(mw[0], __builtin_amdgcn_update_dpp(0, mw[0], 0xb1, 0xf, 0xf, false));
+    // the width this lane speaks for: register index from lane bits 1-4, pair
+    // member from bit 5 (lanes l and l ^ 1 agree)
+    const int wl = 2 * ((lane >> 1) & 15) + (lane >> 5) + 1;
     // index of width wl in the sorted width list = number of listed widths below it
     const int ji = ((a.wmask >> (wl - 1)) & 1u) ? __popc(a.wmask & ((1u << (wl - 1)) - 1u)) : -1;
     double snr = -INFINITY;
     if (ji >= 0 && bmax >= 0 && dg >= 0)
       snr = ((double)bmax - a.M[(int64_t)dg * a.nw + ji]) / a.S[(int64_t)dg * a.nw + ji];
-    // wave argmax over (snr desc, W asc)
+    // wave argmax over (snr desc, W asc); every lane ends with the result
     int bw = wl, bb = bmax;
 #pragma unroll
-    for (int s = 1; s < 32; s <<= 1) {
-      const double os = __shfl_xor(snr, s, 64);
-      const int ow = __shfl_xor(bw, s, 64), ob = __shfl_xor(bb, s, 64);
+    for (int sh = 2; sh < 64; sh <<= 1) {
+      const double os = __shfl_xor(snr, sh, 64);
+      const int ow = __shfl_xor(bw, sh, 64), ob = __shfl_xor(bb, sh, 64);
       if (os > snr || (os == snr && ow < bw)) {
         snr = os;
         bw = ow;
         bb = ob;
       }
     }
-    snr = __shfl(snr, 0, 64);
-    bw = __shfl(bw, 0, 64);
-    bb = __shfl(bb, 0, 64);
-    // earliest start of the winning width in this tile (invalid windows are < 0 <= bb)
+    // earliest start of the winning width in this tile: a sliding window of width
+    // bw over this lane's outputs (only valid windows, i + bw <= lim, can match)
     int first = -1;
     if (snr != -INFINITY) {
+      int B = 0;
+      for (int k = 0; k < bw; ++k) B += yl[k];
 #pragma unroll
-      for (int w = 1; w <= 32; ++w) {
-        if (w == bw) {
-#pragma unroll
-          for (int i = SP - 1; i >= 0; --i)
-            if (qv[i + w] - qv[i] == bb) first = i;
-        }
+      for (int i = 0; i < SP; ++i) {
+        if (first < 0 && B == bb && i + bw <= lim) first = i;
+        B += yl[i + bw] - yl[i];
       }
     }
     const unsigned long long hit = __ballot(first >= 0);
@@ -460,8 +502,8 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
       rec.w = (hit != 0ull) ? bw : 0;
       part[(int64_t)dg * a.ntt + tt] = rec;
     }
-    __syncthreads();
   }
+  __syncthreads();   // LDS may be reused by whatever runs next in this workgroup
 }
 
 template <int DPW, int R2>
@@ -478,53 +520,37 @@ k_search(SearchArgs a) {
   search_tile<DPW, R2>(a, tt, td, lds);
 }
 
-// Persistent multi-beam search.  Items are (beam, tile) pairs numbered beam by beam
-// in time-major order (tile_begin[b] = first item of beam b, tile_begin[nbeam] =
-// total).  The item list is cut into 8 contiguous parts, one per XCD (blocks are
-// dealt to the XCDs round-robin, so block b runs on XCD b mod 8): a workgroup first
-// drains its own XCD's part, keeping neighbouring time tiles in that XCD's L2, then
-// helps the other parts.  Every part's counter only grows, so every workgroup
-// leaves after at most eight exhausted parts.
+// Multi-beam search: one workgroup per (beam, tile).  Beam b owns the blocks
+// [base[b], base[b] + nb_b rounded up to 8), base[b] a multiple of 8, so that
+// block i of a beam runs on XCD i mod 8 (blocks are dealt to the 8 XCDs
+// round-robin) and the beam's tiles take the single-plan kernel's XCD-aware order:
+// all XCDs work through one beam at a time, each on a contiguous run of its time
+// tiles.  Blocks past a beam's tile count exit at once.
 template <int DPW, int R2>
 __global__ void __launch_bounds__(256)
-k_search_batch(const SearchArgs *__restrict__ beams, const int32_t *__restrict__ tile_begin,
-               int32_t nbeam, unsigned int *__restrict__ counters) {
+k_search_batch(const SearchArgs *__restrict__ beams, const int32_t *__restrict__ base,
+               int32_t nbeam) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  __shared__ int s_item;
-  const int total = tile_begin[nbeam];
-  const int q = total >> 3, rem = total & 7;
-  const int home = blockIdx.x & 7;
-  for (int k = 0; k < 8; ++k) {
-    const int part = (home + k) & 7;
-    const int pbeg = part * q + min(part, rem);
-    const int plen = q + (part < rem ? 1 : 0);
-    for (;;) {
-      if (threadIdx.x == 0) s_item = (int)atomicAdd(&counters[part], 1u);
-      __syncthreads();
-      const int it = __builtin_amdgcn_readfirstlane(s_item);
-      __syncthreads();
-      if (it >= plen) break;
-      const int item = pbeg + it;
-      int lo = 0, hi = nbeam - 1;   // last beam whose first item <= item
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tile_begin[mid] <= item) lo = mid; else hi = mid - 1;
-      }
-      // the argument table is read through the constant address space, so that
-      // its fields are scalar loads the compiler may repeat instead of keeping live
-      typedef const __attribute__((address_space(4))) SearchArgs CArgs;
-      CArgs &a = ((CArgs *)beams)[lo];
-      const int L = item - tile_begin[lo];
-      const int tt = L / a.ntd, td = L - tt * a.ntd;
-      search_tile<DPW, R2>(a, tt, td, lds);
-    }
+  const int bi = blockIdx.x;
+  int lo = 0, hi = nbeam - 1;   // last beam whose first block <= bi
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ldc(base, mid) <= bi) lo = mid; else hi = mid - 1;
   }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  // the argument table is read through the constant address space, so that its
+  // fields are scalar loads
+  typedef const __attribute__((address_space(4))) SearchArgs CArgs;
+  CArgs &a = ((CArgs *)beams)[lo];
+  const int nb = a.ntd * a.ntt;
+  const int kl = bi - ldc(base, lo);
+  const int xcd = kl & 7, k = kl >> 3, q = nb >> 3, rem = nb & 7;
+  if (k >= q + (xcd < rem ? 1 : 0)) return;
+  const int L = xcd * q + min(xcd, rem) + k;
+  const int tt = L / a.ntd, td = L - tt * a.ntd;
+  search_tile<DPW, R2>(a, tt, td, lds);
 }
 
-__global__ void k_zero_u32(unsigned int *p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
-}
 
 }  // namespace
 
@@ -775,7 +801,7 @@ static hipError_t launch_search_kernel(int ci, const SearchArgs &a, int nblocks,
     case 0: return launch_cfg<4, 6>(a, nblocks, lds, s);
     case 1: return launch_cfg<4, 8>(a, nblocks, lds, s);
     case 2: return launch_cfg<2, 8>(a, nblocks, lds, s);
-    case 3: return launch_cfg<8, 4>(a, nblocks, lds, s);
+    case 3: return launch_cfg<6, 4>(a, nblocks, lds, s);
     case 4: return launch_cfg<4, 4>(a, nblocks, lds, s);
     default: return launch_cfg<3, 8>(a, nblocks, lds, s);
   }
@@ -883,8 +909,8 @@ dedisp_status dedisp_set_tile(dedisp_plan p, int32_t tile) {
 }  // extern "C"
 
 // ------------------------------------------------------------------------------
-// Batched search over many beams: one persistent launch, optionally replayed
-// from a captured HIP graph.
+// Batched search over many beams: one launch over every beam's tiles, optionally
+// replayed from a captured HIP graph.
 // ------------------------------------------------------------------------------
 struct dedisp_batch_s {
   int32_t nbeam = 0, nchan = 0, ci = 0;
@@ -898,7 +924,6 @@ struct dedisp_batch_s {
   std::vector<int32_t> tile_begin;
   int32_t *d_tile_begin = nullptr;
   dd::SearchArgs *d_args = nullptr;
-  unsigned int *d_counters = nullptr;
   int lds = 0, grid = 0;
   // captured graph and the pointers it was captured with
   hipGraph_t graph = nullptr;
@@ -913,7 +938,7 @@ namespace dd {
 template <int DPW, int R2>
 static hipError_t launch_batch_cfg(const dedisp_batch_s *B, hipStream_t s) {
   hipLaunchKernelGGL((k_search_batch<DPW, R2>), dim3(B->grid), dim3(256), B->lds, s, B->d_args,
-                     B->d_tile_begin, B->nbeam, B->d_counters);
+                     B->d_tile_begin, B->nbeam);
   return hipGetLastError();
 }
 
@@ -922,31 +947,14 @@ static hipError_t launch_batch_kernel(const dedisp_batch_s *B, hipStream_t s) {
     case 0: return launch_batch_cfg<4, 6>(B, s);
     case 1: return launch_batch_cfg<4, 8>(B, s);
     case 2: return launch_batch_cfg<2, 8>(B, s);
-    case 3: return launch_batch_cfg<8, 4>(B, s);
+    case 3: return launch_batch_cfg<6, 4>(B, s);
     case 4: return launch_batch_cfg<4, 4>(B, s);
     default: return launch_batch_cfg<3, 8>(B, s);
   }
 }
 
-template <int DPW, int R2>
-static hipError_t occupancy_cfg(int lds, int *blocks) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_search_batch<DPW, R2>, 256, lds);
-}
-
-static hipError_t batch_occupancy(int ci, int lds, int *blocks) {
-  switch (ci) {
-    case 0: return occupancy_cfg<4, 6>(lds, blocks);
-    case 1: return occupancy_cfg<4, 8>(lds, blocks);
-    case 2: return occupancy_cfg<2, 8>(lds, blocks);
-    case 3: return occupancy_cfg<8, 4>(lds, blocks);
-    case 4: return occupancy_cfg<4, 4>(lds, blocks);
-    default: return occupancy_cfg<3, 8>(lds, blocks);
-  }
-}
-
-// The whole per-call launch sequence: per-beam tables and window rows, counter
-// reset (a fill kernel, so the sequence can be captured), the persistent search
-// and the per-beam reductions.
+// The whole per-call launch sequence: per-beam tables and window rows, the
+// multi-beam search and the per-beam reductions.
 // With copy_args false the argument table is not uploaded (the graph path uploads
 // it outside the capture: it depends only on the pointers the graph is keyed on).
 static dedisp_status batch_enqueue(dedisp_batch_s *B, const void *const *in, const int64_t *stride,
@@ -967,8 +975,6 @@ static dedisp_status batch_enqueue(dedisp_batch_s *B, const void *const *in, con
   if (copy_args)
     DD_HIP(hipMemcpyAsync(B->d_args, args.data(), sizeof(SearchArgs) * B->nbeam,
                           hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, B->d_counters, 8);
-  DD_HIP(hipGetLastError());
   KernelTimer kt(B->plans[0], s);
   DD_HIP(kt.begin());
   DD_HIP(launch_batch_kernel(B, s));
@@ -1038,7 +1044,12 @@ dedisp_status dedisp_batch_create(dedisp_batch *out, int32_t nbeam, const dedisp
     B->out_off.push_back(B->total_trials);
     B->total_trials += p->ndm;
     B->total_sums += (int64_t)p->ndm * p->nchan * no;
-    items += cfg->ntd * (int32_t)L.ntt;
+    const int64_t nit = ((int64_t)cfg->ntd * L.ntt + 7) & ~(int64_t)7;   // blocks of this beam
+    if ((int64_t)items + nit > INT32_MAX / 2) {
+      st = fail(DEDISP_ERR_UNSUPPORTED, "too many tiles in one batch");
+      break;
+    }
+    items += (int32_t)nit;
     B->tile_begin.push_back(items);
     B->lds = std::max(B->lds, cfg->lds_bytes);
   }
@@ -1046,13 +1057,8 @@ dedisp_status dedisp_batch_create(dedisp_batch *out, int32_t nbeam, const dedisp
   if (st == DEDISP_OK) {
     hipError_t e = upload(&B->d_tile_begin, B->tile_begin);
     if (e == hipSuccess) e = hipMalloc((void **)&B->d_args, sizeof(SearchArgs) * nbeam);
-    if (e == hipSuccess) e = hipMalloc((void **)&B->d_counters, 8 * sizeof(unsigned int));
-    int per_cu = 0, dev = 0, ncu = 0;
-    if (e == hipSuccess) e = batch_occupancy(B->ci, B->lds, &per_cu);
-    if (e == hipSuccess) e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) st = hip_fail(e, "batch setup");
-    B->grid = std::max(8, std::min(items, std::max(1, per_cu) * ncu));
+    B->grid = items;
   }
   if (st != DEDISP_OK) {
     dedisp_batch_destroy(B);
@@ -1071,7 +1077,6 @@ dedisp_status dedisp_batch_destroy(dedisp_batch B) {
   if (B->ev_out) (void)hipEventDestroy(B->ev_out);
   (void)hipFree(B->d_tile_begin);
   (void)hipFree(B->d_args);
-  (void)hipFree(B->d_counters);
   delete B;
   return DEDISP_OK;
 }
