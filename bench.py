@@ -22,8 +22,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9   # int32 vector lane-ops/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+PACKED_PEAK_OPS = 2 * VALU_PEAK_OPS    # two 16-bit adds per lane-op (packed uint16 adds)
 KERNEL_SRC = os.path.join(ROOT, "paper_1301_3968_amd", "csrc", "kernels_search.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_search_cfg2.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_search_336ch_65536s_1024dm.json")
 
 
 def _src_sha() -> str:
@@ -31,9 +32,11 @@ def _src_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic(launches_per_step: int):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if they were
-    taken on the current kernel source; otherwise None."""
+def _traffic(tile: int):
+    """HBM bytes per launch of the search kernel in tile shape `tile`, from the
+    committed rocprofv3 counter runs (FETCH_SIZE + WRITE_SIZE, each scaled by what
+    the counter reads for a plain copy of known size), if they were taken on the
+    current kernel source; otherwise None."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -41,7 +44,7 @@ def _traffic(launches_per_step: int):
         return None
     if t.get("kernel_src_sha") != _src_sha():
         return None
-    return t.get("hbm_bytes_per_launch")
+    return t.get("per_tile", {}).get(str(tile), {}).get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(wl, start, ntap, ndm_sample: int):
@@ -74,7 +77,7 @@ def main() -> int:
     ap.add_argument("--workload", default="search",
                     choices=["search", "batch", "weighted", "autograd"],
                     help="search: the headline fused search (default); batch: 36 beams in one "
-                         "persistent launch; weighted: 4096-channel fp32-weighted dedispersion; "
+                         "launch; weighted: 4096-channel fp32-weighted dedispersion; "
                          "autograd: forward / adjoint timing of the 8-tap learnable profile")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (the reference kernel "
@@ -154,8 +157,11 @@ def main() -> int:
     ops = sums + (2.0 * D * nout * nw if fused else 0.0)
     achieved = ops / (kern_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                "unit": "Tops/s", "frac": achieved / VALU_PEAK_OPS, "traffic": _traffic(1),
-                "kernel_ms": kern_ms, "ops_per_launch": ops}
+                "unit": "Tops/s", "frac": achieved / VALU_PEAK_OPS,
+                "traffic": _traffic(tile) if fused else None,
+                "kernel_ms": kern_ms, "ops_per_launch": ops,
+                "peak_packed_u16": PACKED_PEAK_OPS / 1e12,
+                "frac_packed_u16": achieved / PACKED_PEAK_OPS}
     line = {
         "metric": "DM-trial*channel*sample sums/s", "value": value, "unit": "sums/s",
         "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": ms_step,
