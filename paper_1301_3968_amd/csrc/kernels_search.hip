@@ -38,21 +38,37 @@ namespace dd {
 // ------------------------------------------------------------------------------
 // Tile configurations (candidates for the autotuner)
 // ------------------------------------------------------------------------------
+// (trials per wave, packed output pairs per lane per row, waves per workgroup):
+// a tile covers NW * DPW trials and 128 * R2 outputs; the NW waves share the
+// staged windows, so more waves stage fewer bytes per sum.
+#define DD_TILE_CONFIGS(X) \
+  X(0, 4, 6, 4)            \
+  X(1, 4, 8, 4)            \
+  X(2, 6, 4, 4)            \
+  X(3, 4, 4, 8)            \
+  X(4, 4, 6, 8)            \
+  X(5, 4, 8, 8)            \
+  X(6, 4, 4, 16)           \
+  X(7, 4, 6, 16)
 struct TileCfg {
-  int dpw;   // trials per wave (4 waves per workgroup)
+  int dpw;   // trials per wave
   int r2;    // packed output pairs per lane per row: outputs per tile row = 128 * r2
+  int nw;    // waves per workgroup
 };
-static const TileCfg kCfgs[] = {{4, 6}, {4, 8}, {2, 8}, {6, 4}, {4, 4}, {3, 8}};
+#define DD_CFG_ENTRY(i, d, r, w) {d, r, w},
+static const TileCfg kCfgs[] = {DD_TILE_CONFIGS(DD_CFG_ENTRY)};
+#undef DD_CFG_ENTRY
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 constexpr int kDefaultCfg = 0;
 constexpr int kHalo = 32;                 // boxcar widths up to 32
 // Time-tile step: TY minus a halo of at least 31 outputs, rounded so that every
 // lane (SP = 2 * r2 consecutive starts) owns either all or none of its starts.
 constexpr int tile_step(int r2) { return 128 * r2 - ((32 + 2 * r2 - 1) / (2 * r2)) * (2 * r2); }
-// LDS bytes for one channel group's windows, smallest first: two such buffers per
-// workgroup (double buffering) let four, three or two workgroups share a CU's
+// LDS bytes for one channel group's windows per 4 waves, smallest first: two such
+// buffers per workgroup (double buffering) let 16, 12 or 8 waves share a CU's
 // 160 KiB.  A plan takes the smallest budget that holds every channel's windows.
 constexpr int kStageBudgets[3] = {19968, 26624, 39936};
+constexpr int kMaxLds = 160 * 1024;
 
 struct GroupInfo {
   int32_t job_begin, njobs, lw, c_begin;   // lw: window length in samples (multiple of 8)
@@ -203,9 +219,6 @@ __device__ __forceinline__ int bitrev5(int v) {
   return ((v & 1) << 4) | ((v & 2) << 2) | (v & 4) | ((v & 8) >> 2) | ((v & 16) >> 4);
 }
 
-// 8-sample chunks per lane when a wave stages one window (windows up to 1536 samples)
-constexpr int kRowChunks = 3;
-
 typedef __attribute__((address_space(3))) void lds_void;
 
 // Read-only tables read through the constant address space: their fields become
@@ -236,11 +249,11 @@ __device__ __forceinline__ GroupInfo load_group(const GroupInfo *groups, int g) 
 // parity whose start is dword-aligned.  Whole windows go to waves; lanes move
 // 16-byte chunks with direct global-to-LDS loads, which complete asynchronously
 // (the caller waits on the vector memory counter before its barrier).
-template <typename Args>
+template <int NW, typename Args>
 __device__ __forceinline__ void stage_group(Args &a, const GroupInfo &gi, int64_t t0, int wave,
                                             int lane, unsigned char *buf) {
   const int nchunk = gi.lw >> 3;
-  for (int j = wave; j < gi.njobs; j += 4) {
+  for (int j = wave; j < gi.njobs; j += NW) {
     const int32_t *jp = (const int32_t *)(a.jobs + gi.job_begin + j);
     const int jrow = ldc(jp, 0), jstart = ldc(jp, 1);
     const int64_t e0 = (int64_t)jstart + t0;
@@ -250,8 +263,7 @@ __device__ __forceinline__ void stage_group(Args &a, const GroupInfo &gi, int64_
     const uint16_t *srcB = odd ? a.U + base + 2 : a.U1 + base;  // U[e0 + 1 ...]
     unsigned char *rowA = buf + j * 4 * gi.lw;
     unsigned char *rowB = rowA + 2 * gi.lw;
-#pragma unroll
-    for (int k = 0; k < kRowChunks; ++k) {
+    for (int k = 0; 64 * k < nchunk; ++k) {
       const int ch = lane + 64 * k;
       if (ch < nchunk) {
         __builtin_amdgcn_global_load_lds(srcA + 8 * ch, (lds_void *)(rowA + 1024 * k), 16, 0, 0);
@@ -276,10 +288,10 @@ __device__ __forceinline__ int group_offsets(Args &a, const GroupInfo &gi, int t
 
 // One (DM tile, time tile) of the fused search: channel-group loop, then the
 // boxcar stage.  Shared by the one-plan kernel and the multi-beam kernel.
-template <int DPW, int R2, typename Args>
+template <int DPW, int R2, int NW, typename Args>
 __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
                                             unsigned char *lds) {
-  constexpr int TY = 128 * R2, TT = tile_step(R2), DT = 4 * DPW, SP = TY / 64;
+  constexpr int TY = 128 * R2, TT = tile_step(R2), DT = NW * DPW, SP = TY / 64;
   constexpr int YROW = TY + kHalo + 4;   // ints per wave for the boxcar stage
   static_assert(TT % SP == 0 && TY - TT >= 31, "tile step");
   const int tid = threadIdx.x, lane = tid & 63;
@@ -304,7 +316,7 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
   {
     const GroupInfo g0 = load_group(a.groups, gb);
     myoff = group_offsets<DPW>(a, g0, trial0, lane);
-    stage_group(a, g0, t0, wave, lane, lds);
+    stage_group<NW>(a, g0, t0, wave, lane, lds);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     asm volatile("" ::"v"(myoff));
     __syncthreads();
@@ -317,7 +329,7 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
     if (g + 1 < ge) {
       const GroupInfo gn = load_group(a.groups, g + 1);
       nextoff = group_offsets<DPW>(a, gn, trial0, lane);
-      stage_group(a, gn, t0, wave, lane, lds + (par ^ 1) * a.bufbytes);
+      stage_group<NW>(a, gn, t0, wave, lane, lds + (par ^ 1) * a.bufbytes);
     }
     // ---- accumulate: per trial, per channel, R2 aligned dword reads (pairs of
     // them 256 bytes apart are merged into one two-address read, so one LDS
@@ -506,8 +518,8 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
   __syncthreads();   // LDS may be reused by whatever runs next in this workgroup
 }
 
-template <int DPW, int R2>
-__global__ void __launch_bounds__(256)
+template <int DPW, int R2, int NW>
+__global__ void __launch_bounds__(64 * NW)
 k_search(SearchArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   // XCD-aware tile order: blocks b = x (mod 8) all run on XCD x; give XCD x a
@@ -517,7 +529,7 @@ k_search(SearchArgs a) {
   const int xcd = b & 7, k = b >> 3, q = nb >> 3, rem = nb & 7;
   const int L = xcd * q + min(xcd, rem) + k;
   const int tt = L / a.ntd, td = L - tt * a.ntd;
-  search_tile<DPW, R2>(a, tt, td, lds);
+  search_tile<DPW, R2, NW>(a, tt, td, lds);
 }
 
 // Multi-beam search: one workgroup per (beam, tile).  Beam b owns the blocks
@@ -526,8 +538,8 @@ k_search(SearchArgs a) {
 // round-robin) and the beam's tiles take the single-plan kernel's XCD-aware order:
 // all XCDs work through one beam at a time, each on a contiguous run of its time
 // tiles.  Blocks past a beam's tile count exit at once.
-template <int DPW, int R2>
-__global__ void __launch_bounds__(256)
+template <int DPW, int R2, int NW>
+__global__ void __launch_bounds__(64 * NW)
 k_search_batch(const SearchArgs *__restrict__ beams, const int32_t *__restrict__ base,
                int32_t nbeam) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -548,7 +560,7 @@ k_search_batch(const SearchArgs *__restrict__ beams, const int32_t *__restrict__
   if (k >= q + (xcd < rem ? 1 : 0)) return;
   const int L = xcd * q + min(xcd, rem) + k;
   const int tt = L / a.ntd, td = L - tt * a.ntd;
-  search_tile<DPW, R2>(a, tt, td, lds);
+  search_tile<DPW, R2, NW>(a, tt, td, lds);
 }
 
 
@@ -585,8 +597,11 @@ static bool build_cfg_budget(const dedisp_plan_s *p, const TiledTables &T, int c
                              TiledCfgTables &out);
 
 static bool build_cfg(const dedisp_plan_s *p, const TiledTables &T, int ci, TiledCfgTables &out) {
-  for (int budget : kStageBudgets)
+  for (int budget : kStageBudgets) {
+    budget = budget * kCfgs[ci].nw / 4;
+    if (2 * budget > kMaxLds) break;
     if (build_cfg_budget(p, T, ci, budget, out)) return true;
+  }
   return false;
 }
 
@@ -594,7 +609,7 @@ static bool build_cfg_budget(const dedisp_plan_s *p, const TiledTables &T, int c
                              TiledCfgTables &out) {
   const TileCfg cf = kCfgs[ci];
   const int C = p->nchan, D = p->ndm;
-  const int DT = 4 * cf.dpw, TY = 128 * cf.r2;
+  const int DT = cf.nw * cf.dpw, TY = 128 * cf.r2;
   out = TiledCfgTables();
   out.dt = DT;
   out.ty = TY;
@@ -637,8 +652,7 @@ static bool build_cfg_budget(const dedisp_plan_s *p, const TiledTables &T, int c
         }
         const int nspan = std::max(span, smax - smin);
         const int lw = ((TY + nspan + 2) + 7) & ~7;
-        const int bytes = lw > 64 * 8 * kRowChunks ? INT32_MAX / 2   // window too long for one wave
-                                                    : (nrows_g + (int)ns.size()) * 4 * lw;
+        const int bytes = (nrows_g + (int)ns.size()) * 4 * lw;
         if (ccount == 0 && (bytes > budget || over)) return false;
         if (bytes > budget || over || ccount >= 64 / cf.dpw) break;
         span = nspan;
@@ -691,7 +705,7 @@ static bool build_cfg_budget(const dedisp_plan_s *p, const TiledTables &T, int c
   out.group_begin[ntd] = (int)out.groups.size();
   out.ngroups = (int)out.groups.size();
   out.bufbytes = (lds_max + 15) & ~15;
-  out.lds_bytes = std::max(2 * out.bufbytes, 4 * (TY + kHalo + 4 + 32) * 4);
+  out.lds_bytes = std::max(2 * out.bufbytes, cf.nw * (TY + kHalo + 4 + 32) * 4);
   out.ok = true;
   return true;
 }
@@ -789,21 +803,38 @@ bool search_supported(const dedisp_plan_s *p, const WidthList &wl) {
   return true;
 }
 
-template <int DPW, int R2>
+// Workgroups may take more than the default 64 KiB of LDS: raise each kernel's
+// limit once per device.
+static hipError_t allow_lds(const void *fn, bool *done, std::mutex *mu) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= 64) return e;
+  std::lock_guard<std::mutex> lk(*mu);
+  if (!done[dev]) {
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    if (e == hipSuccess) done[dev] = true;
+  }
+  return e;
+}
+
+template <int DPW, int R2, int NW>
 static hipError_t launch_cfg(const SearchArgs &a, int nblocks, int lds, hipStream_t s) {
-  hipLaunchKernelGGL((k_search<DPW, R2>), dim3(nblocks), dim3(256), lds, s, a);
+  static bool done[64] = {};
+  static std::mutex mu;
+  hipError_t e = allow_lds((const void *)k_search<DPW, R2, NW>, done, &mu);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_search<DPW, R2, NW>), dim3(nblocks), dim3(64 * NW), lds, s, a);
   return hipGetLastError();
 }
 
 static hipError_t launch_search_kernel(int ci, const SearchArgs &a, int nblocks, int lds,
                                        hipStream_t s) {
   switch (ci) {
-    case 0: return launch_cfg<4, 6>(a, nblocks, lds, s);
-    case 1: return launch_cfg<4, 8>(a, nblocks, lds, s);
-    case 2: return launch_cfg<2, 8>(a, nblocks, lds, s);
-    case 3: return launch_cfg<6, 4>(a, nblocks, lds, s);
-    case 4: return launch_cfg<4, 4>(a, nblocks, lds, s);
-    default: return launch_cfg<3, 8>(a, nblocks, lds, s);
+#define DD_CFG_CASE(i, d, r, w) \
+  case i: return launch_cfg<d, r, w>(a, nblocks, lds, s);
+    DD_TILE_CONFIGS(DD_CFG_CASE)
+#undef DD_CFG_CASE
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -935,21 +966,24 @@ struct dedisp_batch_s {
 
 namespace dd {
 
-template <int DPW, int R2>
+template <int DPW, int R2, int NW>
 static hipError_t launch_batch_cfg(const dedisp_batch_s *B, hipStream_t s) {
-  hipLaunchKernelGGL((k_search_batch<DPW, R2>), dim3(B->grid), dim3(256), B->lds, s, B->d_args,
-                     B->d_tile_begin, B->nbeam);
+  static bool done[64] = {};
+  static std::mutex mu;
+  hipError_t e = allow_lds((const void *)k_search_batch<DPW, R2, NW>, done, &mu);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_search_batch<DPW, R2, NW>), dim3(B->grid), dim3(64 * NW), B->lds, s,
+                     B->d_args, B->d_tile_begin, B->nbeam);
   return hipGetLastError();
 }
 
 static hipError_t launch_batch_kernel(const dedisp_batch_s *B, hipStream_t s) {
   switch (B->ci) {
-    case 0: return launch_batch_cfg<4, 6>(B, s);
-    case 1: return launch_batch_cfg<4, 8>(B, s);
-    case 2: return launch_batch_cfg<2, 8>(B, s);
-    case 3: return launch_batch_cfg<6, 4>(B, s);
-    case 4: return launch_batch_cfg<4, 4>(B, s);
-    default: return launch_batch_cfg<3, 8>(B, s);
+#define DD_CFG_CASE(i, d, r, w) \
+  case i: return launch_batch_cfg<d, r, w>(B, s);
+    DD_TILE_CONFIGS(DD_CFG_CASE)
+#undef DD_CFG_CASE
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -214,7 +214,7 @@ def cfg2_mid(orc):
     return wl, n, yo
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, -2])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7, -2])
 def test_fused_search_every_tile_config(dd, orc, cfg2_mid, tile):
     # Ragged in both DM (100 trials) and time (6755 outputs) for every tile shape.
     wl, n, yo = cfg2_mid
