@@ -221,6 +221,12 @@ __device__ __forceinline__ int bitrev5(int v) {
 
 typedef __attribute__((address_space(3))) void lds_void;
 
+// s_waitcnt immediate (gfx9 layout: vmcnt in bits 3:0 and 15:14, expcnt in 6:4,
+// lgkmcnt in 11:8) waiting for all vector memory operations, the direct-to-LDS
+// copies included.  Issued through the builtin, not inline asm, so that the
+// compiler's own wait insertion knows the counter is zero afterwards.
+constexpr unsigned kWaitVm0 = 0x0f70;
+
 // Read-only tables read through the constant address space: their fields become
 // scalar loads, which do not share the vector memory counter with the direct
 // global-to-LDS copies (the compiler cannot prove on its own that those copies
@@ -229,26 +235,35 @@ __device__ __forceinline__ int32_t ldc(const int32_t *p, int64_t i) {
   return ((const __attribute__((address_space(4))) int32_t *)p)[i];
 }
 
+// The descriptor is read with one scalar load, so that using any field waits for
+// all of them (a field read later would otherwise leave a scalar load in flight,
+// forcing every LDS wait in between to wait for all outstanding reads).
 __device__ __forceinline__ GroupInfo load_group(const GroupInfo *groups, int g) {
   static_assert(sizeof(GroupInfo) == 8 * sizeof(int32_t), "GroupInfo layout");
-  const int32_t *q = (const int32_t *)(groups + g);
+  typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
+  const i32x8 v = *(const __attribute__((address_space(4))) i32x8 *)(groups + g);
   GroupInfo gi;
-  gi.job_begin = ldc(q, 0);
-  gi.njobs = ldc(q, 1);
-  gi.lw = ldc(q, 2);
-  gi.c_begin = ldc(q, 3);
-  gi.c_count = ldc(q, 4);
-  gi.flush = ldc(q, 5);
-  gi.inv_nchunk = ldc(q, 6);
+  gi.job_begin = v[0];
+  gi.njobs = v[1];
+  gi.lw = v[2];
+  gi.c_begin = v[3];
+  gi.c_count = v[4];
+  gi.flush = v[5];
+  gi.inv_nchunk = v[6];
   gi.pad1 = 0;
   return gi;
 }
 
+// Buffer descriptor word 3 for raw (unformatted, unswizzled) 32-bit buffers.
+constexpr int kBufWord3 = 0x00020000;
+
 // Starts the copy of group gi's windows into one LDS buffer: copy A of a window
 // (aligned to its first sample) and copy B (one sample later), each from the row
 // parity whose start is dword-aligned.  Whole windows go to waves; lanes move
-// 16-byte chunks with direct global-to-LDS loads, which complete asynchronously
-// (the caller waits on the vector memory counter before its barrier).
+// 16-byte chunks with direct buffer-to-LDS loads, which complete asynchronously
+// (the caller waits on the vector memory counter before its barrier).  Each
+// window copy gets its own buffer descriptor covering exactly that copy, so a
+// read past it returns zeros instead of touching other memory.
 template <int NW, typename Args>
 __device__ __forceinline__ void stage_group(Args &a, const GroupInfo &gi, int64_t t0, int wave,
                                             int lane, unsigned char *buf) {
@@ -261,13 +276,15 @@ __device__ __forceinline__ void stage_group(Args &a, const GroupInfo &gi, int64_
     const bool odd = (e0 & 1) != 0;
     const uint16_t *srcA = (odd ? a.U1 : a.U) + base;        // U[e0 ...]
     const uint16_t *srcB = odd ? a.U + base + 2 : a.U1 + base;  // U[e0 + 1 ...]
+    const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc((void *)srcA, (short)0, 2 * gi.lw, kBufWord3);
+    const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc((void *)srcB, (short)0, 2 * gi.lw, kBufWord3);
     unsigned char *rowA = buf + j * 4 * gi.lw;
     unsigned char *rowB = rowA + 2 * gi.lw;
     for (int k = 0; 64 * k < nchunk; ++k) {
       const int ch = lane + 64 * k;
       if (ch < nchunk) {
-        __builtin_amdgcn_global_load_lds(srcA + 8 * ch, (lds_void *)(rowA + 1024 * k), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds(srcB + 8 * ch, (lds_void *)(rowB + 1024 * k), 16, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rA, (lds_void *)(rowA + 1024 * k), 16, 16 * ch, 0, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rB, (lds_void *)(rowB + 1024 * k), 16, 16 * ch, 0, 0, 0);
       }
     }
   }
@@ -317,8 +334,7 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
     const GroupInfo g0 = load_group(a.groups, gb);
     myoff = group_offsets<DPW>(a, g0, trial0, lane);
     stage_group<NW>(a, g0, t0, wave, lane, lds);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    asm volatile("" ::"v"(myoff));
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
   }
   for (int g = gb; g < ge; ++g) {
@@ -333,26 +349,25 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
     }
     // ---- accumulate: per trial, per channel, R2 aligned dword reads (pairs of
     // them 256 bytes apart are merged into one two-address read, so one LDS
-    // instruction moves 512 bytes per wave)
+    // instruction moves 512 bytes per wave).  Channels go in chunks of CH, so that
+    // a chunk keeps 12 reads in flight: the LDS counter holds at most 15, and the
+    // adds can then wait for the reads one at a time.
+    constexpr int CH = 24 / R2;
+    static_assert(CH * R2 == 24, "chunk of 12 two-address reads");
     const unsigned char *lbase = lds + par * a.bufbytes + lane * 4;
 #pragma unroll
     for (int j = 0; j < DPW; ++j) {
       int c = 0;
       const int jb = j * cc;
-      for (; c + 4 <= cc; c += 4) {
-        const int o0 = __builtin_amdgcn_readlane(myoff, jb + c);
-        const int o1 = __builtin_amdgcn_readlane(myoff, jb + c + 1);
-        const int o2 = __builtin_amdgcn_readlane(myoff, jb + c + 2);
-        const int o3 = __builtin_amdgcn_readlane(myoff, jb + c + 3);
-        const unsigned char *p0 = lbase + o0, *p1 = lbase + o1, *p2 = lbase + o2, *p3 = lbase + o3;
+      for (; c + CH <= cc; c += CH) {
+        const unsigned char *pc[CH];
 #pragma unroll
-        for (int r = 0; r < R2; ++r) a16[j][r] = pk_add_u16(a16[j][r], *(const uint32_t *)(p0 + 256 * r));
+        for (int q = 0; q < CH; ++q) pc[q] = lbase + __builtin_amdgcn_readlane(myoff, jb + c + q);
 #pragma unroll
-        for (int r = 0; r < R2; ++r) a16[j][r] = pk_add_u16(a16[j][r], *(const uint32_t *)(p1 + 256 * r));
+        for (int q = 0; q < CH; ++q)
 #pragma unroll
-        for (int r = 0; r < R2; ++r) a16[j][r] = pk_add_u16(a16[j][r], *(const uint32_t *)(p2 + 256 * r));
-#pragma unroll
-        for (int r = 0; r < R2; ++r) a16[j][r] = pk_add_u16(a16[j][r], *(const uint32_t *)(p3 + 256 * r));
+          for (int r = 0; r < R2; ++r)
+            a16[j][r] = pk_add_u16(a16[j][r], *(const uint32_t *)(pc[q] + 256 * r));
       }
       for (; c < cc; ++c) {
         const unsigned char *pp = lbase + __builtin_amdgcn_readlane(myoff, jb + c);
@@ -372,8 +387,7 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
       }
     }
     // the next group's windows and offsets have landed; this group's reads are done
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    asm volatile("" ::"v"(nextoff));
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
     myoff = nextoff;
   }
