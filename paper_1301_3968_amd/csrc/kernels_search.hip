@@ -69,6 +69,9 @@ constexpr int tile_step(int r2) { return 128 * r2 - ((32 + 2 * r2 - 1) / (2 * r2
 // 160 KiB.  A plan takes the smallest budget that holds every channel's windows.
 constexpr int kStageBudgets[3] = {19968, 26624, 39936};
 constexpr int kMaxLds = 160 * 1024;
+// Window-row bytes per chunk of a multi-beam search: rows written just before the
+// chunk's search should still sit in the 256 MiB last-level cache when read.
+constexpr size_t kBatchChunkRows = 192u << 20;
 
 struct GroupInfo {
   int32_t job_begin, njobs, lw, c_begin;   // lw: window length in samples (multiple of 8)
@@ -852,14 +855,12 @@ static hipError_t launch_search_kernel(int ci, const SearchArgs &a, int nblocks,
   }
 }
 
-// Launches the per-block preparation of one plan (noise tables, window rows) into
-// `work` and fills the tile kernel's arguments.  Returns DEDISP_ERR_UNSUPPORTED
-// (without launching anything) when the tiled kernel cannot take this plan.
-static dedisp_status prepare_tiled(dedisp_plan p, int ci, const uint8_t *x, int64_t nsamp,
-                                   int64_t in_stride, int64_t nout, const WidthList &wl,
-                                   const double *mu, const double *sigma, void *work,
-                                   hipStream_t s, SearchArgs *out, TiledCfgTables **cfg_out,
-                                   Layout *lay_out) {
+// The tile kernel's arguments for one plan and one block (pointers into `work`,
+// or the window rows at u_rows when given), without launching anything.  Returns
+// DEDISP_ERR_UNSUPPORTED when the tiled kernel cannot take this plan.
+static dedisp_status describe_tiled(dedisp_plan p, int ci, int64_t nout, const WidthList &wl,
+                                    void *work, uint16_t *u_rows, SearchArgs *out,
+                                    TiledCfgTables **cfg_out = nullptr, Layout *lay_out = nullptr) {
   TiledCfgTables *cfg = nullptr;
   {
     std::lock_guard<std::mutex> lk(p->mu);
@@ -871,17 +872,7 @@ static dedisp_status prepare_tiled(dedisp_plan p, int ci, const uint8_t *x, int6
   const Layout L = layout(p, ci, wl.n, nout, T.nrows);
   if (L.ntt * (int64_t)cfg->ntd > INT32_MAX / 2) return DEDISP_ERR_UNSUPPORTED;
   double *M = (double *)work;
-  double *S = M + (size_t)p->ndm * wl.n;
-  void *part = (char *)work + L.off_part;
-  uint16_t *U = (uint16_t *)((char *)work + L.off_u);
-  DD_HIP(launch_norm(p, wl, mu, sigma, M, S, s));
-  {
-    const dim3 g((unsigned)((L.tpad + kRowSpan - 1) / kRowSpan), (unsigned)p->nchan);
-    const int shm = kRowSpan + T.nmax_all + 16;
-    hipLaunchKernelGGL(k_window_rows, g, dim3(kRowThreads), shm, s, x, in_stride, nsamp, L.tpad,
-                       T.d_nmin, T.d_nmax, T.d_rowidx, U, U + (size_t)T.nrows * L.tpad);
-    DD_HIP(hipGetLastError());
-  }
+  uint16_t *U = u_rows ? u_rows : (uint16_t *)((char *)work + L.off_u);
   SearchArgs a{};
   a.U = U;
   a.U1 = U + (size_t)T.nrows * L.tpad;
@@ -897,7 +888,7 @@ static dedisp_status prepare_tiled(dedisp_plan p, int ci, const uint8_t *x, int6
   a.nchan = p->nchan;
   a.nout = nout;
   a.M = M;
-  a.S = S;
+  a.S = M + (size_t)p->ndm * wl.n;
   a.nw = wl.n;
   a.wmask = 0;
   for (int i = 0; i <= 32; ++i) a.widx[i] = -1;
@@ -905,7 +896,36 @@ static dedisp_status prepare_tiled(dedisp_plan p, int ci, const uint8_t *x, int6
     a.wmask |= 1u << (wl.w[i] - 1);
     a.widx[wl.w[i]] = (int8_t)i;
   }
-  a.part = part;
+  a.part = (char *)work + L.off_part;
+  *out = a;
+  if (cfg_out) *cfg_out = cfg;
+  if (lay_out) *lay_out = L;
+  return DEDISP_OK;
+}
+
+// Launches the per-block preparation of one plan (noise tables, window rows) into
+// `work` (rows at u_rows when given) and fills the tile kernel's arguments.
+// Returns DEDISP_ERR_UNSUPPORTED (without launching anything) when the tiled
+// kernel cannot take this plan.
+static dedisp_status prepare_tiled(dedisp_plan p, int ci, const uint8_t *x, int64_t nsamp,
+                                   int64_t in_stride, int64_t nout, const WidthList &wl,
+                                   const double *mu, const double *sigma, void *work,
+                                   hipStream_t s, SearchArgs *out, TiledCfgTables **cfg_out,
+                                   Layout *lay_out, uint16_t *u_rows = nullptr) {
+  SearchArgs a;
+  TiledCfgTables *cfg = nullptr;
+  Layout L;
+  dedisp_status st = describe_tiled(p, ci, nout, wl, work, u_rows, &a, &cfg, &L);
+  if (st != DEDISP_OK) return st;
+  const TiledTables &T = *p->tiled;
+  DD_HIP(launch_norm(p, wl, mu, sigma, (double *)a.M, (double *)a.S, s));
+  {
+    const dim3 g((unsigned)((L.tpad + kRowSpan - 1) / kRowSpan), (unsigned)p->nchan);
+    const int shm = kRowSpan + T.nmax_all + 16;
+    hipLaunchKernelGGL(k_window_rows, g, dim3(kRowThreads), shm, s, x, in_stride, nsamp, L.tpad,
+                       T.d_nmin, T.d_nmax, T.d_rowidx, (uint16_t *)a.U, (uint16_t *)a.U1);
+    DD_HIP(hipGetLastError());
+  }
   *out = a;
   *cfg_out = cfg;
   *lay_out = L;
@@ -966,10 +986,16 @@ struct dedisp_batch_s {
   std::vector<int64_t> out_off;     // first output row of each beam
   size_t work_bytes = 0;
   int64_t total_trials = 0, total_sums = 0;
-  std::vector<int32_t> tile_begin;
+  // Beams are searched in chunks whose window rows fit kBatchChunkRows bytes (so
+  // that rows written by the preparation are still cached when the search reads
+  // them); chunk k covers beams [chunk_beam[k], chunk_beam[k + 1]), its block
+  // bases start at tile_begin[chunk_tb[k]] = 0, and all chunks share one rows
+  // region at u_off of the workspace.
+  std::vector<int32_t> tile_begin, chunk_beam, chunk_tb, chunk_grid, chunk_lds;
+  std::vector<size_t> u_rel;          // rows offset of each beam inside the shared region
+  size_t u_off = 0;
   int32_t *d_tile_begin = nullptr;
   dd::SearchArgs *d_args = nullptr;
-  int lds = 0, grid = 0;
   // captured graph and the pointers it was captured with
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -981,20 +1007,21 @@ struct dedisp_batch_s {
 namespace dd {
 
 template <int DPW, int R2, int NW>
-static hipError_t launch_batch_cfg(const dedisp_batch_s *B, hipStream_t s) {
+static hipError_t launch_batch_cfg(const dedisp_batch_s *B, int k, hipStream_t s) {
   static bool done[64] = {};
   static std::mutex mu;
   hipError_t e = allow_lds((const void *)k_search_batch<DPW, R2, NW>, done, &mu);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_search_batch<DPW, R2, NW>), dim3(B->grid), dim3(64 * NW), B->lds, s,
-                     B->d_args, B->d_tile_begin, B->nbeam);
+  const int b0 = B->chunk_beam[k], b1 = B->chunk_beam[k + 1];
+  hipLaunchKernelGGL((k_search_batch<DPW, R2, NW>), dim3(B->chunk_grid[k]), dim3(64 * NW),
+                     B->chunk_lds[k], s, B->d_args + b0, B->d_tile_begin + B->chunk_tb[k], b1 - b0);
   return hipGetLastError();
 }
 
-static hipError_t launch_batch_kernel(const dedisp_batch_s *B, hipStream_t s) {
+static hipError_t launch_batch_kernel(const dedisp_batch_s *B, int k, hipStream_t s) {
   switch (B->ci) {
 #define DD_CFG_CASE(i, d, r, w) \
-  case i: return launch_batch_cfg<d, r, w>(B, s);
+  case i: return launch_batch_cfg<d, r, w>(B, k, s);
     DD_TILE_CONFIGS(DD_CFG_CASE)
 #undef DD_CFG_CASE
     default: return hipErrorInvalidValue;
@@ -1010,12 +1037,11 @@ static dedisp_status batch_enqueue(dedisp_batch_s *B, const void *const *in, con
                                    int32_t *w, void *work, hipStream_t s, bool copy_args,
                                    std::vector<SearchArgs> &args) {
   args.assign(B->nbeam, SearchArgs{});
+  uint16_t *urows = (uint16_t *)((char *)work + B->u_off);
   for (int b = 0; b < B->nbeam; ++b) {
-    TiledCfgTables *cfg = nullptr;
-    Layout L;
-    dedisp_status st = prepare_tiled(B->plans[b], B->ci, (const uint8_t *)in[b], B->nsamp[b],
-                                     stride[b], B->nout[b], B->wl, mu, sigma,
-                                     (char *)work + B->off[b], s, &args[b], &cfg, &L);
+    dedisp_status st = describe_tiled(B->plans[b], B->ci, B->nout[b], B->wl,
+                                      (char *)work + B->off[b],
+                                      (uint16_t *)((char *)urows + B->u_rel[b]), &args[b]);
     if (st != DEDISP_OK) return st == DEDISP_ERR_UNSUPPORTED
                                     ? fail(st, "a beam's plan cannot use the tiled search")
                                     : st;
@@ -1023,9 +1049,25 @@ static dedisp_status batch_enqueue(dedisp_batch_s *B, const void *const *in, con
   if (copy_args)
     DD_HIP(hipMemcpyAsync(B->d_args, args.data(), sizeof(SearchArgs) * B->nbeam,
                           hipMemcpyHostToDevice, s));
+  // chunk by chunk: the beams' noise tables and window rows (the rows region is
+  // shared by all chunks: stream order keeps a chunk's search ahead of the next
+  // chunk's rows), then one search launch over the chunk's tiles
+  const int nchunk = (int)B->chunk_beam.size() - 1;
   KernelTimer kt(B->plans[0], s);
-  DD_HIP(kt.begin());
-  DD_HIP(launch_batch_kernel(B, s));
+  for (int k = 0; k < nchunk; ++k) {
+    for (int b = B->chunk_beam[k]; b < B->chunk_beam[k + 1]; ++b) {
+      TiledCfgTables *cfg = nullptr;
+      Layout L;
+      SearchArgs a;
+      dedisp_status st = prepare_tiled(B->plans[b], B->ci, (const uint8_t *)in[b], B->nsamp[b],
+                                       stride[b], B->nout[b], B->wl, mu, sigma,
+                                       (char *)work + B->off[b], s, &a, &cfg, &L,
+                                       (uint16_t *)((char *)urows + B->u_rel[b]));
+      if (st != DEDISP_OK) return st;
+    }
+    if (k == 0) DD_HIP(kt.begin());
+    DD_HIP(launch_batch_kernel(B, k, s));
+  }
   DD_HIP(kt.end());
   for (int b = 0; b < B->nbeam; ++b) {
     const int64_t o = B->out_off[b];
@@ -1065,8 +1107,9 @@ dedisp_status dedisp_batch_create(dedisp_batch *out, int32_t nbeam, const dedisp
   B->ci = cfg_index(plans[0]);
   dedisp_status st = DEDISP_OK;
   size_t off = 0;
-  int32_t items = 0;
-  B->tile_begin.push_back(0);
+  std::vector<size_t> rows;      // window-row bytes of each beam
+  std::vector<int64_t> blocks;   // workgroups of each beam (a multiple of 8)
+  std::vector<int> lds;          // LDS bytes per workgroup of each beam
   for (int b = 0; b < nbeam && st == DEDISP_OK; ++b) {
     dedisp_plan p = plans[b];
     const int64_t no = nsamp[b] - p->max_span + 1;
@@ -1088,25 +1131,57 @@ dedisp_status dedisp_batch_create(dedisp_batch *out, int32_t nbeam, const dedisp
     }
     const Layout L = layout(p, B->ci, B->wl.n, no, p->tiled->nrows);
     B->off.push_back(off);
-    off += (L.total + 255) & ~(size_t)255;
+    off += (L.off_u + 255) & ~(size_t)255;   // noise tables and partial results
+    rows.push_back((L.total - L.off_u + 255) & ~(size_t)255);
     B->out_off.push_back(B->total_trials);
     B->total_trials += p->ndm;
     B->total_sums += (int64_t)p->ndm * p->nchan * no;
     const int64_t nit = ((int64_t)cfg->ntd * L.ntt + 7) & ~(int64_t)7;   // blocks of this beam
-    if ((int64_t)items + nit > INT32_MAX / 2) {
-      st = fail(DEDISP_ERR_UNSUPPORTED, "too many tiles in one batch");
+    if (nit > INT32_MAX / 2) {
+      st = fail(DEDISP_ERR_UNSUPPORTED, "too many tiles in one beam");
       break;
     }
-    items += (int32_t)nit;
-    B->tile_begin.push_back(items);
-    B->lds = std::max(B->lds, cfg->lds_bytes);
+    blocks.push_back(nit);
+    lds.push_back(cfg->lds_bytes);
+  }
+  if (st == DEDISP_OK) {
+    // chunks of consecutive beams whose rows fit kBatchChunkRows (at least one beam)
+    size_t rows_max = 0, rows_in = 0;
+    int64_t items = 0;
+    int lds_in = 0;
+    B->chunk_beam.push_back(0);
+    B->chunk_tb.push_back(0);
+    B->tile_begin.push_back(0);
+    for (int b = 0; b < nbeam; ++b) {
+      if (b > B->chunk_beam.back() &&
+          (rows_in + rows[b] > kBatchChunkRows || items + blocks[b] > INT32_MAX / 2)) {
+        B->chunk_grid.push_back((int32_t)items);
+        B->chunk_lds.push_back(lds_in);
+        B->chunk_beam.push_back(b);
+        B->chunk_tb.push_back((int32_t)B->tile_begin.size());
+        B->tile_begin.push_back(0);
+        rows_in = 0;
+        items = 0;
+        lds_in = 0;
+      }
+      lds_in = std::max(lds_in, lds[b]);
+      B->u_rel.push_back(rows_in);
+      rows_in += rows[b];
+      rows_max = std::max(rows_max, rows_in);
+      items += blocks[b];
+      B->tile_begin.push_back((int32_t)items);
+    }
+    B->chunk_grid.push_back((int32_t)items);
+    B->chunk_lds.push_back(lds_in);
+    B->chunk_beam.push_back(nbeam);
+    B->u_off = off;
+    off += rows_max;
   }
   B->work_bytes = off;
   if (st == DEDISP_OK) {
     hipError_t e = upload(&B->d_tile_begin, B->tile_begin);
     if (e == hipSuccess) e = hipMalloc((void **)&B->d_args, sizeof(SearchArgs) * nbeam);
     if (e != hipSuccess) st = hip_fail(e, "batch setup");
-    B->grid = items;
   }
   if (st != DEDISP_OK) {
     dedisp_batch_destroy(B);
