@@ -55,6 +55,14 @@ static dedisp_status run_dedisperse(dedisp_plan p, const void *in, int32_t in_dt
                                     void *out, int32_t out_dtype, int64_t out_stride,
                                     int64_t out_bstride, int64_t nout, hipStream_t s,
                                     KernelTimer *kt = nullptr) {
+  // fp32 output: the tiled kernel (weights folded into window rows) when the plan
+  // fits it; the tile setting -2 keeps the general kernels below
+  if (out_dtype == DEDISP_F32 && p->tile_choice != -2) {
+    dedisp_status st = run_dedisperse_f32_tiled(p, in, in_dtype, nsamp, in_stride, in_bstride,
+                                                nbatch, (float *)out, out_stride, out_bstride,
+                                                nout, s, kt);
+    if (st != DEDISP_ERR_UNSUPPORTED) return st;
+  }
   if (in_dtype == DEDISP_U8 && (p->wmode == DEDISP_W_UNIT || p->wmode == DEDISP_W_CHANNEL)) {
     if (p->wmode == DEDISP_W_CHANNEL && out_dtype != DEDISP_F32)
       return fail(DEDISP_ERR_UNSUPPORTED, "channel weights produce F32 output");

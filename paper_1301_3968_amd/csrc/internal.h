@@ -31,8 +31,10 @@ struct WidthList {
   int32_t w[kMaxWidths];
 };
 
-// Per-(DM tile, channel group) descriptors of the tiled search kernel.
+// Per-(DM tile, channel group) descriptors of the tiled search kernel and of the
+// tiled fp32 dedispersion.
 struct TiledTables;
+struct F32Tables;
 
 struct DevTables {
   int32_t *start = nullptr;   // [ndm][nchan]
@@ -64,6 +66,7 @@ struct dedisp_plan_s {
   int device = -1;
   dd::DevTables dev;
   dd::TiledTables *tiled = nullptr;     // optimised-search tables (built lazily)
+  dd::F32Tables *f32 = nullptr;         // tiled fp32 dedispersion tables (built lazily)
 
   // Instrumentation events around the dominant kernel (dedisp_set_kernel_events).
   std::vector<hipEvent_t> ev_start, ev_stop;
@@ -102,6 +105,7 @@ inline const float *weights_of(const dedisp_plan_s *p) {
   return tl_weights ? tl_weights : p->dev.weights;
 }
 void free_tiled(TiledTables *t);
+void free_f32(F32Tables *t);
 
 // Launchers (kernels_*.hip).  All enqueue on `stream` and return hipError_t.
 hipError_t launch_prefix_u8(const uint8_t *x, int64_t in_stride, int64_t in_bstride, int32_t nchan,
@@ -156,6 +160,15 @@ dedisp_status run_search_tiled(dedisp_plan p, const uint8_t *x, int64_t nsamp, i
                                int64_t nout, const WidthList &wl, const double *mu,
                                const double *sigma, double *snr, int32_t *t, int32_t *w,
                                void *work, hipStream_t s);
+
+// Tiled fp32 dedispersion for weighted profiles (kernels_f32.hip): uint8 or fp32
+// input, fp32 output.  Returns DEDISP_ERR_UNSUPPORTED (launching nothing) when the
+// plan does not fit the tiled kernel.
+dedisp_status run_dedisperse_f32_tiled(dedisp_plan p, const void *in, int32_t in_dtype,
+                                       int64_t nsamp, int64_t in_stride, int64_t in_bstride,
+                                       int32_t nbatch, float *out, int64_t out_stride,
+                                       int64_t out_bstride, int64_t nout, hipStream_t s,
+                                       KernelTimer *kt);
 
 // Size of one per-chunk detection candidate record in the workspace.
 constexpr size_t kCandBytes = 16;

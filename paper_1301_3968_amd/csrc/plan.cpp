@@ -378,6 +378,7 @@ dedisp_status dedisp_plan_destroy(dedisp_plan p) {
     if (p->dev.weights) (void)hipFree(p->dev.weights);
   }
   if (p->tiled) dd::free_tiled(p->tiled);
+  if (p->f32) dd::free_f32(p->f32);
   delete p;
   return DEDISP_OK;
 }
