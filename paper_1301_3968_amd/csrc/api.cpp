@@ -236,7 +236,16 @@ dedisp_status dedisp_dedisperse_backward(dedisp_plan p, const float *d_grad_y, i
     const int64_t nz = nsamp - p->ktaps + 1;
     float *z = nullptr;
     DD_HIP(hipMallocAsync((void **)&z, sizeof(float) * (size_t)nz * p->nchan * nbatch, s));
-    hipError_t e = dd::launch_adjoint_z(p, d_grad_y, nout, gy_stride, gy_bstride, nbatch, nz, z, s);
+    hipError_t e = hipSuccess;
+    st = p->tile_choice == -2 ? DEDISP_ERR_UNSUPPORTED
+                              : dd::run_adjoint_z_tiled(p, d_grad_y, nout, gy_stride, gy_bstride,
+                                                        nbatch, nz, z, s);
+    if (st == DEDISP_ERR_UNSUPPORTED)
+      e = dd::launch_adjoint_z(p, d_grad_y, nout, gy_stride, gy_bstride, nbatch, nz, z, s);
+    else if (st != DEDISP_OK) {
+      (void)hipFreeAsync(z, s);
+      return st;
+    }
     if (e == hipSuccess && d_grad_w)
       e = dd::launch_grad_w_tap(p, z, nz, d_in, in_dtype, in_stride, in_bstride, nbatch, d_grad_w, s);
     if (e == hipSuccess && d_grad_in)

@@ -67,6 +67,7 @@ struct dedisp_plan_s {
   dd::DevTables dev;
   dd::TiledTables *tiled = nullptr;     // optimised-search tables (built lazily)
   dd::F32Tables *f32 = nullptr;         // tiled fp32 dedispersion tables (built lazily)
+  dd::F32Tables *f32_adj = nullptr;     // tables of the transposed (adjoint) gather
 
   // Instrumentation events around the dominant kernel (dedisp_set_kernel_events).
   std::vector<hipEvent_t> ev_start, ev_stop;
@@ -169,6 +170,11 @@ dedisp_status run_dedisperse_f32_tiled(dedisp_plan p, const void *in, int32_t in
                                        int32_t nbatch, float *out, int64_t out_stride,
                                        int64_t out_bstride, int64_t nout, hipStream_t s,
                                        KernelTimer *kt);
+// zbar[b][c][tau] = sum_d g[b][d][tau - start[d][c]] for tau in [0, nz) on the same
+// tiled kernel; DEDISP_ERR_UNSUPPORTED (launching nothing) when it does not fit.
+dedisp_status run_adjoint_z_tiled(dedisp_plan p, const float *g, int64_t nout, int64_t gstride,
+                                  int64_t gbstride, int32_t nbatch, int64_t nz, float *z,
+                                  hipStream_t s);
 
 // Size of one per-chunk detection candidate record in the workspace.
 constexpr size_t kCandBytes = 16;

@@ -400,33 +400,65 @@ k_adjoint_z(const float *__restrict__ g, int64_t nout, int64_t gstride, int64_t 
   z[((int64_t)b * nchan + c) * nz + i] = (float)acc;
 }
 
-// gw[c][k] = sum_b sum_i zbar[b][c][i] x[b][c][i+k], fp64, one block per channel.
+// gw[c][k] = sum_b sum_i zbar[b][c][i] x[b][c][i+k] with fp64 products and sums, in
+// two passes.  Pass 1: one workgroup per (chunk of kGwChunk samples, channel, batch
+// element) stages x of its chunk in LDS, keeps its zbar samples in registers and
+// writes its K partial sums; pass 2 adds the partials of each (c, k) in a fixed
+// order, so the result does not depend on the schedule.
+constexpr int kGwChunk = 4096, kGwPerThread = kGwChunk / kThreads, kGwMaxK = 64;
+
 template <typename XT>
 __global__ void __launch_bounds__(kThreads)
-k_grad_w_tap(const float *__restrict__ z, int64_t nz, const XT *__restrict__ x, int64_t in_stride,
-             int64_t in_bstride, int32_t nbatch, int32_t nchan, int32_t K, double *__restrict__ gw) {
-  const int c = blockIdx.x, tid = threadIdx.x;
-  double acc[64];
-  for (int k = 0; k < K; ++k) acc[k] = 0.0;
-  for (int b = 0; b < nbatch; ++b) {
-    const float *zr = z + ((int64_t)b * nchan + c) * nz;
-    const XT *xr = x + (int64_t)b * in_bstride + (int64_t)c * in_stride;
-    for (int64_t i = tid; i < nz; i += kThreads) {
-      const double zv = (double)zr[i];
-      for (int k = 0; k < K; ++k) acc[k] += zv * (double)xr[i + k];
-    }
+k_grad_w_tap_part(const float *__restrict__ z, int64_t nz, const XT *__restrict__ x,
+                  int64_t in_stride, int64_t in_bstride, int32_t nchan, int32_t K,
+                  double *__restrict__ part) {
+  __shared__ float xs[kGwChunk + kGwMaxK];
+  __shared__ double red[kGwMaxK][kThreads / 64];
+  const int sidx = blockIdx.x, c = blockIdx.y, b = blockIdx.z, tid = threadIdx.x;
+  const int64_t i0 = (int64_t)sidx * kGwChunk;
+  const int n = (int)min((int64_t)kGwChunk, nz - i0);
+  const XT *xr = x + (int64_t)b * in_bstride + (int64_t)c * in_stride + i0;
+  const float *zr = z + ((int64_t)b * nchan + c) * nz + i0;
+  // x[i0 + i] for i < n + K - 1: the last is x[nz + K - 2] = x[nsamp - 1]
+  for (int i = tid; i < n + K - 1; i += kThreads) xs[i] = (float)xr[i];
+  float zv[kGwPerThread];
+#pragma unroll
+  for (int j = 0; j < kGwPerThread; ++j) {
+    const int i = tid + kThreads * j;
+    zv[j] = i < n ? zr[i] : 0.0f;
   }
-  __shared__ double red[kThreads];
+  __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6;
   for (int k = 0; k < K; ++k) {
-    red[tid] = acc[k];
-    __syncthreads();
-    for (int off = kThreads / 2; off > 0; off >>= 1) {
-      if (tid < off) red[tid] += red[tid + off];
-      __syncthreads();
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < kGwPerThread; ++j) {
+      const int i = tid + kThreads * j;
+      if (i < n) acc += (double)zv[j] * (double)xs[i + k];
     }
-    if (tid == 0) gw[(int64_t)c * K + k] = red[0];
-    __syncthreads();
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) red[k][wave] = acc;
   }
+  __syncthreads();
+  if (tid < K) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) t += red[tid][w];
+    part[(((int64_t)c * gridDim.z + b) * gridDim.x + sidx) * K + tid] = t;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_grad_w_tap_sum(const double *__restrict__ part, int32_t nparts, int32_t nchan, int32_t K,
+                 double *__restrict__ gw) {
+  const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= (int64_t)nchan * K) return;
+  const int64_t c = idx / K, k = idx - c * K;
+  const double *pp = part + c * nparts * K + k;
+  double t = 0.0;
+  for (int j = 0; j < nparts; ++j) t += pp[(int64_t)j * K];
+  gw[idx] = t;
 }
 
 // gx[b][c][i] = sum_k w[c][k] zbar[b][c][i-k].
@@ -673,13 +705,32 @@ hipError_t launch_adjoint_z(const dedisp_plan_s *p, const float *g, int64_t nout
 hipError_t launch_grad_w_tap(const dedisp_plan_s *p, const float *z, int64_t nz, const void *x,
                              int32_t in_dtype, int64_t in_stride, int64_t in_bstride,
                              int32_t nbatch, double *gw, hipStream_t s) {
+  const int K = p->ktaps;
+  if (K < 1 || K > kGwMaxK || nz < 1) return hipErrorInvalidValue;
+  const int64_t nsplit = (nz + kGwChunk - 1) / kGwChunk;
+  const int64_t nparts = nsplit * nbatch;
+  if (nsplit > INT32_MAX || nparts > INT32_MAX || p->nchan > 65535 || nbatch > 65535)
+    return hipErrorInvalidValue;
+  double *part = nullptr;
+  hipError_t e =
+      hipMallocAsync((void **)&part, sizeof(double) * (size_t)p->nchan * nparts * K, s);
+  if (e != hipSuccess) return e;
+  const dim3 g((unsigned)nsplit, (unsigned)p->nchan, (unsigned)nbatch);
   if (in_dtype == DEDISP_F32)
-    hipLaunchKernelGGL(k_grad_w_tap<float>, dim3(p->nchan), dim3(kThreads), 0, s, z, nz,
-                       (const float *)x, in_stride, in_bstride, nbatch, p->nchan, p->ktaps, gw);
+    hipLaunchKernelGGL(k_grad_w_tap_part<float>, g, dim3(kThreads), 0, s, z, nz,
+                       (const float *)x, in_stride, in_bstride, p->nchan, K, part);
   else
-    hipLaunchKernelGGL(k_grad_w_tap<uint8_t>, dim3(p->nchan), dim3(kThreads), 0, s, z, nz,
-                       (const uint8_t *)x, in_stride, in_bstride, nbatch, p->nchan, p->ktaps, gw);
-  return hipGetLastError();
+    hipLaunchKernelGGL(k_grad_w_tap_part<uint8_t>, g, dim3(kThreads), 0, s, z, nz,
+                       (const uint8_t *)x, in_stride, in_bstride, p->nchan, K, part);
+  e = hipGetLastError();
+  if (e == hipSuccess) {
+    const int64_t n = (int64_t)p->nchan * K;
+    hipLaunchKernelGGL(k_grad_w_tap_sum, dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, part, (int32_t)nparts, p->nchan, K, gw);
+    e = hipGetLastError();
+  }
+  hipError_t e2 = hipFreeAsync(part, s);
+  return e != hipSuccess ? e : e2;
 }
 
 hipError_t launch_grad_x_tap(const dedisp_plan_s *p, const float *z, int64_t nz, int64_t nsamp,

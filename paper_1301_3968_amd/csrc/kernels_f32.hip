@@ -17,6 +17,10 @@
 //      group (at most 32 channels) run in fp32; group sums are added in fp64, so the
 //      result is within a few fp32 roundings of the exact sum.
 // Long blocks are processed in time segments so that the rows stay within 4 GiB.
+//
+// The same two kernels compute the transpose of the one-sample-per-channel sum (the
+// adjoint needed for per-tap weights): with trials as row channels, channels as
+// outputs and the trial gradients as rows, it is again a sum of shifted rows.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -67,6 +71,7 @@ struct F32Tables {
   int32_t nmax_all = 0;
   int32_t *d_nmin = nullptr, *d_nmax = nullptr;
   int64_t *d_rowidx = nullptr;
+  int32_t lead = 0;            // zeros in front of each row (transposed gathers)
   F32CfgTables cfg[kNumF32Cfgs];
   bool tried[kNumF32Cfgs] = {};
 };
@@ -102,7 +107,7 @@ constexpr int kRowThreads = 256, kRowTau = 4 * kRowThreads;   // 4 tau per threa
 template <typename XT>
 __global__ void __launch_bounds__(kRowThreads)
 k_rows_f32(const XT *__restrict__ x, int64_t in_stride, int64_t in_bstride, int64_t nsamp,
-           int64_t seg0, int64_t tpad, const int32_t *__restrict__ nmin,
+           int64_t lead, int64_t seg0, int64_t tpad, const int32_t *__restrict__ nmin,
            const int32_t *__restrict__ nmaxv, const int64_t *__restrict__ rowidx, int64_t nrows,
            int32_t wmode, int32_t K, const float *__restrict__ w, float *__restrict__ R) {
   extern __shared__ float sxf[];
@@ -112,8 +117,8 @@ k_rows_f32(const XT *__restrict__ x, int64_t in_stride, int64_t in_bstride, int6
   const XT *row = x + (int64_t)b * in_bstride + (int64_t)c * in_stride;
   const int nval = kRowTau + n1;
   for (int i = tid; i < nval; i += kRowThreads) {
-    const int64_t g = seg0 + blk0 + i;
-    sxf[i] = g < nsamp ? (float)row[g] : 0.0f;
+    const int64_t g = seg0 + blk0 + i - lead;   // rows start `lead` zeros before the input
+    sxf[i] = (g >= 0 && g < nsamp) ? (float)row[g] : 0.0f;
   }
   __syncthreads();
   const int64_t tau0 = blk0 + 4 * tid;
@@ -131,7 +136,7 @@ k_rows_f32(const XT *__restrict__ x, int64_t in_stride, int64_t in_bstride, int6
       float v[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i)   // windows running past the end of the block are zero
-        v[i] = (seg0 + tau0 + i + n <= nsamp) ? s[i] * wc : 0.0f;
+        v[i] = (seg0 + tau0 + i + n <= nsamp + lead) ? s[i] * wc : 0.0f;
       *(float4 *)(base + (int64_t)(n - n0) * tpad) = make_float4(v[0], v[1], v[2], v[3]);
     }
   }
@@ -295,13 +300,22 @@ static hipError_t upload(T **dst, const std::vector<T> &v) {
   return hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
 }
 
-static void build_rows_f32(const dedisp_plan_s *p, F32Tables *T) {
-  const int C = p->nchan, D = p->ndm;
+// What the tiled kernel sums: out[o][t] = sum_r row_{r, ntap[o][r]}[t + start[o][r]]
+// for `nout_rows` outputs o (the forward's trials) over `nrow_ch` row channels r (the
+// forward's channels); outputs are tiled in the order of `key`.
+struct GatherSpec {
+  int32_t nout_rows = 0, nrow_ch = 0;
+  const int32_t *start = nullptr, *ntap = nullptr;   // [nout_rows][nrow_ch], host
+  const double *key = nullptr;                       // [nout_rows]
+};
+
+static void build_rows_f32(const GatherSpec &gs, F32Tables *T) {
+  const int C = gs.nrow_ch, D = gs.nout_rows;
   T->nmin.assign(C, INT32_MAX);
   T->nmax.assign(C, 0);
   for (int d = 0; d < D; ++d)
     for (int c = 0; c < C; ++c) {
-      const int n = p->ntap[(size_t)d * C + c];
+      const int n = gs.ntap[(size_t)d * C + c];
       T->nmin[c] = std::min(T->nmin[c], n);
       T->nmax[c] = std::max(T->nmax[c], n);
     }
@@ -316,19 +330,20 @@ static void build_rows_f32(const dedisp_plan_s *p, F32Tables *T) {
   T->nrows = r;
 }
 
-// Channel groups per DM tile (LDS budget per buffer), window jobs and the per-
-// (trial, channel) LDS byte offsets.  Returns false if one channel alone does not fit.
-static bool build_f32_cfg(const dedisp_plan_s *p, const F32Tables &T, int ci, int budget,
+// Row-channel groups per output tile (LDS budget per buffer), window jobs and the
+// per-(output, row channel) LDS byte offsets.  Returns false if one row channel alone
+// does not fit.
+static bool build_f32_cfg(const GatherSpec &gs, const F32Tables &T, int ci, int budget,
                           F32CfgTables &out) {
   const F32Cfg cf = kF32Cfgs[ci];
-  const int C = p->nchan, D = p->ndm;
+  const int C = gs.nrow_ch, D = gs.nout_rows;
   const int DT = cf.nw * cf.dpw, TY = 64 * cf.r;
   out = F32CfgTables();
   out.dt = DT;
   out.ty = TY;
   std::vector<int32_t> order(D);
   std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return p->dm[a] < p->dm[b]; });
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return gs.key[a] < gs.key[b]; });
   const int ntd = (D + DT - 1) / DT;
   out.ntd = ntd;
   out.perm.assign((size_t)ntd * DT, -1);
@@ -353,7 +368,7 @@ static bool build_f32_cfg(const dedisp_plan_s *p, const F32Tables &T, int ci, in
         int smin = INT32_MAX, smax = INT32_MIN;
         std::vector<int> ns;
         for (int j = 0; j < DT; ++j) {
-          const int s = p->start[(size_t)tr[j] * C + c], n = p->ntap[(size_t)tr[j] * C + c];
+          const int s = gs.start[(size_t)tr[j] * C + c], n = gs.ntap[(size_t)tr[j] * C + c];
           smin = std::min(smin, s);
           smax = std::max(smax, s);
           if (std::find(ns.begin(), ns.end(), n) == ns.end()) ns.push_back(n);
@@ -376,8 +391,8 @@ static bool build_f32_cfg(const dedisp_plan_s *p, const F32Tables &T, int ci, in
         int smin = INT32_MAX;
         std::vector<int> ns;
         for (int j = 0; j < DT; ++j) {
-          smin = std::min(smin, p->start[(size_t)tr[j] * C + cc]);
-          const int n = p->ntap[(size_t)tr[j] * C + cc];
+          smin = std::min(smin, gs.start[(size_t)tr[j] * C + cc]);
+          const int n = gs.ntap[(size_t)tr[j] * C + cc];
           if (std::find(ns.begin(), ns.end(), n) == ns.end()) ns.push_back(n);
         }
         for (size_t k = 0; k < ns.size(); ++k) {
@@ -385,7 +400,7 @@ static bool build_f32_cfg(const dedisp_plan_s *p, const F32Tables &T, int ci, in
           out.jobs.push_back(smin);
         }
         for (int j = 0; j < DT; ++j) {
-          const int s = p->start[(size_t)tr[j] * C + cc], n = p->ntap[(size_t)tr[j] * C + cc];
+          const int s = gs.start[(size_t)tr[j] * C + cc], n = gs.ntap[(size_t)tr[j] * C + cc];
           const int k = (int)(std::find(ns.begin(), ns.end(), n) - ns.begin());
           out.offs[((size_t)td * DT + j) * C + cc] = (ri + k) * 4 * lw + 4 * (s - smin);
         }
@@ -403,24 +418,26 @@ static bool build_f32_cfg(const dedisp_plan_s *p, const F32Tables &T, int ci, in
   return true;
 }
 
-static dedisp_status ensure_f32(dedisp_plan p, int ci, F32CfgTables **out) {
+// Builds (once) the row tables in *slot and the tables of configuration ci.  Caller
+// holds the plan's mutex.
+static dedisp_status ensure_gather(const GatherSpec &gs, F32Tables **slot, int ci,
+                                   F32CfgTables **out) {
   *out = nullptr;
-  std::lock_guard<std::mutex> lk(p->mu);
-  if (!p->f32) {
-    p->f32 = new (std::nothrow) F32Tables;
-    if (!p->f32) return fail(DEDISP_ERR_OOM, "host allocation failed");
-    build_rows_f32(p, p->f32);
-    DD_HIP(upload(&p->f32->d_nmin, p->f32->nmin));
-    DD_HIP(upload(&p->f32->d_nmax, p->f32->nmax));
-    DD_HIP(upload(&p->f32->d_rowidx, p->f32->rowidx));
+  if (!*slot) {
+    *slot = new (std::nothrow) F32Tables;
+    if (!*slot) return fail(DEDISP_ERR_OOM, "host allocation failed");
+    build_rows_f32(gs, *slot);
+    DD_HIP(upload(&(*slot)->d_nmin, (*slot)->nmin));
+    DD_HIP(upload(&(*slot)->d_nmax, (*slot)->nmax));
+    DD_HIP(upload(&(*slot)->d_rowidx, (*slot)->rowidx));
   }
-  F32Tables &T = *p->f32;
+  F32Tables &T = **slot;
   F32CfgTables &c = T.cfg[ci];
   if (!T.tried[ci]) {
     T.tried[ci] = true;
     // two buffers per workgroup, 16 waves per CU, a little LDS left over
     const int budget = 79872 * kF32Cfgs[ci].nw / 16;
-    if (build_f32_cfg(p, T, ci, budget, c)) {
+    if (build_f32_cfg(gs, T, ci, budget, c)) {
       DD_HIP(upload(&c.d_offs, c.offs));
       DD_HIP(upload(&c.d_groups, c.groups));
       DD_HIP(upload(&c.d_group_begin, c.group_begin));
@@ -465,6 +482,70 @@ static hipError_t launch_f32(int ci, const F32Args &a, int nbatch, int lds, hipS
   }
 }
 
+// Rows from the input (`lead` zeros in front of it and zeros past its nsamp
+// samples), then the tiled sum into `nout` outputs per output row, segment by segment.
+static dedisp_status run_gather_f32(const F32Tables &T, const F32CfgTables &cfg, int ci,
+                                    const void *in, int32_t in_dtype, int64_t nsamp,
+                                    int64_t in_stride, int64_t in_bstride, int32_t nbatch,
+                                    int32_t nrow_ch, int32_t wmode, int32_t K, const float *w,
+                                    int32_t max_span, float *out, int64_t out_stride,
+                                    int64_t out_bstride, int64_t nout, hipStream_t s,
+                                    KernelTimer *kt) {
+  const int TY = cfg.ty;
+  const int64_t halo = 2 * (int64_t)max_span + 32;
+  // time segment: as many tiles as keep the rows of all batch elements within
+  // kF32RowBytesMax (at least one tile)
+  const double row_bytes = 4.0 * (double)T.nrows * nbatch;
+  int64_t seg = (int64_t)((double)kF32RowBytesMax / row_bytes) - halo;
+  seg = std::max<int64_t>(TY, seg / TY * TY);
+  seg = std::min<int64_t>(seg, (nout + TY - 1) / TY * TY);
+  const int64_t ntt = seg / TY;
+  if (ntt * (int64_t)cfg.ntd > INT32_MAX / 2) return DEDISP_ERR_UNSUPPORTED;
+  const int64_t tpad = (seg + halo + 3) & ~(int64_t)3;
+  float *Rrows = nullptr;
+  DD_HIP(hipMallocAsync((void **)&Rrows, sizeof(float) * (size_t)T.nrows * tpad * nbatch, s));
+  hipError_t e = hipSuccess;
+  for (int64_t o0 = 0; o0 < nout && e == hipSuccess; o0 += seg) {
+    const int64_t nseg = std::min(seg, nout - o0);
+    const dim3 g((unsigned)((tpad + kRowTau - 1) / kRowTau), (unsigned)nrow_ch, (unsigned)nbatch);
+    const int shm = (kRowTau + T.nmax_all + 4) * (int)sizeof(float);
+    if (in_dtype == DEDISP_U8)
+      hipLaunchKernelGGL(k_rows_f32<uint8_t>, g, dim3(kRowThreads), shm, s, (const uint8_t *)in,
+                         in_stride, in_bstride, nsamp, (int64_t)T.lead, o0, tpad, T.d_nmin,
+                         T.d_nmax, T.d_rowidx, T.nrows, wmode, K, w, Rrows);
+    else
+      hipLaunchKernelGGL(k_rows_f32<float>, g, dim3(kRowThreads), shm, s, (const float *)in,
+                         in_stride, in_bstride, nsamp, (int64_t)T.lead, o0, tpad, T.d_nmin,
+                         T.d_nmax, T.d_rowidx, T.nrows, wmode, K, w, Rrows);
+    e = hipGetLastError();
+    if (e != hipSuccess) break;
+    F32Args a{};
+    a.R = Rrows;
+    a.rbstride = T.nrows * tpad;
+    a.tpad = tpad;
+    a.bufbytes = cfg.bufbytes;
+    a.ntd = cfg.ntd;
+    a.ntt = (int32_t)((nseg + TY - 1) / TY);
+    a.nchan = nrow_ch;
+    a.offs = cfg.d_offs;
+    a.groups = cfg.d_groups;
+    a.group_begin = cfg.d_group_begin;
+    a.jobs = cfg.d_jobs;
+    a.perm = cfg.d_perm;
+    a.nout = nseg;
+    a.out = out + o0;
+    a.out_stride = out_stride;
+    a.out_bstride = out_bstride;
+    if (kt && o0 == 0) e = kt->begin();
+    if (e == hipSuccess) e = launch_f32(ci, a, nbatch, cfg.lds_bytes, s);
+    if (e == hipSuccess && kt && o0 + seg >= nout) e = kt->end();
+  }
+  hipError_t e2 = hipFreeAsync(Rrows, s);
+  if (e != hipSuccess) return hip_fail(e, "tiled fp32 gather");
+  if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+  return DEDISP_OK;
+}
+
 dedisp_status run_dedisperse_f32_tiled(dedisp_plan p, const void *in, int32_t in_dtype,
                                        int64_t nsamp, int64_t in_stride, int64_t in_bstride,
                                        int32_t nbatch, float *out, int64_t out_stride,
@@ -474,64 +555,66 @@ dedisp_status run_dedisperse_f32_tiled(dedisp_plan p, const void *in, int32_t in
   if (p->max_ntap > kF32MaxTaps) return DEDISP_ERR_UNSUPPORTED;
   const int ci = p->ndm >= 256 ? 0 : 1;
   F32CfgTables *cfg = nullptr;
-  dedisp_status st = ensure_f32(p, ci, &cfg);
-  if (st != DEDISP_OK) return st;
-  if (!cfg) return DEDISP_ERR_UNSUPPORTED;
-  const F32Tables &T = *p->f32;
-  const int TY = cfg->ty;
-  const int64_t halo = 2 * (int64_t)p->max_span + 32;
-  // time segment: as many tiles as keep the rows of all batch elements within
-  // kF32RowBytesMax (at least one tile)
-  const double row_bytes = 4.0 * (double)T.nrows * nbatch;
-  int64_t seg = (int64_t)((double)kF32RowBytesMax / row_bytes) - halo;
-  seg = std::max<int64_t>(TY, seg / TY * TY);
-  seg = std::min<int64_t>(seg, (nout + TY - 1) / TY * TY);
-  const int64_t ntt = seg / TY;
-  if (ntt * (int64_t)cfg->ntd > INT32_MAX / 2) return DEDISP_ERR_UNSUPPORTED;
-  const int64_t tpad = (seg + halo + 3) & ~(int64_t)3;
-  float *Rrows = nullptr;
-  DD_HIP(hipMallocAsync((void **)&Rrows, sizeof(float) * (size_t)T.nrows * tpad * nbatch, s));
-  const float *w = weights_of(p);
-  hipError_t e = hipSuccess;
-  for (int64_t o0 = 0; o0 < nout && e == hipSuccess; o0 += seg) {
-    const int64_t nseg = std::min(seg, nout - o0);
-    const dim3 g((unsigned)((tpad + kRowTau - 1) / kRowTau), (unsigned)p->nchan, (unsigned)nbatch);
-    const int shm = (kRowTau + T.nmax_all + 4) * (int)sizeof(float);
-    if (in_dtype == DEDISP_U8)
-      hipLaunchKernelGGL(k_rows_f32<uint8_t>, g, dim3(kRowThreads), shm, s, (const uint8_t *)in,
-                         in_stride, in_bstride, nsamp, o0, tpad, T.d_nmin, T.d_nmax, T.d_rowidx,
-                         T.nrows, p->wmode, p->ktaps, w, Rrows);
-    else
-      hipLaunchKernelGGL(k_rows_f32<float>, g, dim3(kRowThreads), shm, s, (const float *)in,
-                         in_stride, in_bstride, nsamp, o0, tpad, T.d_nmin, T.d_nmax, T.d_rowidx,
-                         T.nrows, p->wmode, p->ktaps, w, Rrows);
-    e = hipGetLastError();
-    if (e != hipSuccess) break;
-    F32Args a{};
-    a.R = Rrows;
-    a.rbstride = T.nrows * tpad;
-    a.tpad = tpad;
-    a.bufbytes = cfg->bufbytes;
-    a.ntd = cfg->ntd;
-    a.ntt = (int32_t)((nseg + TY - 1) / TY);
-    a.nchan = p->nchan;
-    a.offs = cfg->d_offs;
-    a.groups = cfg->d_groups;
-    a.group_begin = cfg->d_group_begin;
-    a.jobs = cfg->d_jobs;
-    a.perm = cfg->d_perm;
-    a.nout = nseg;
-    a.out = out + o0;
-    a.out_stride = out_stride;
-    a.out_bstride = out_bstride;
-    if (kt && o0 == 0) e = kt->begin();
-    if (e == hipSuccess) e = launch_f32(ci, a, nbatch, cfg->lds_bytes, s);
-    if (e == hipSuccess && kt && o0 + seg >= nout) e = kt->end();
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    GatherSpec gs;
+    gs.nout_rows = p->ndm;
+    gs.nrow_ch = p->nchan;
+    gs.start = p->start.data();
+    gs.ntap = p->ntap.data();
+    gs.key = p->dm.data();
+    dedisp_status st = ensure_gather(gs, &p->f32, ci, &cfg);
+    if (st != DEDISP_OK) return st;
   }
-  hipError_t e2 = hipFreeAsync(Rrows, s);
-  if (e != hipSuccess) return hip_fail(e, "tiled fp32 dedisperse");
-  if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
-  return DEDISP_OK;
+  if (!cfg) return DEDISP_ERR_UNSUPPORTED;
+  return run_gather_f32(*p->f32, *cfg, ci, in, in_dtype, nsamp, in_stride, in_bstride, nbatch,
+                        p->nchan, p->wmode, p->ktaps, weights_of(p), p->max_span, out, out_stride,
+                        out_bstride, nout, s, kt);
+}
+
+// zbar[b][c][tau] = sum_d g[b][d][tau - start[d][c]] (terms with the index outside
+// [0, nout) are zero) for tau in [0, nz): the transpose of the one-sample-per-channel
+// sum.  It is the same tiled gather with the roles swapped: outputs are channels,
+// row channels are trials, rows are g with smax = max start zeros in front, and the
+// start of (c, d) is smax - start[d][c].
+dedisp_status run_adjoint_z_tiled(dedisp_plan p, const float *g, int64_t nout, int64_t gstride,
+                                  int64_t gbstride, int32_t nbatch, int64_t nz, float *z,
+                                  hipStream_t s) {
+  const int C = p->nchan, D = p->ndm;
+  const int ci = C >= 256 ? 0 : 1;
+  F32CfgTables *cfg = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!p->f32_adj || !p->f32_adj->tried[ci]) {
+      int32_t smax = 0;
+      for (int32_t v : p->start) smax = std::max(smax, v);
+      std::vector<int32_t> st((size_t)C * D), nt((size_t)C * D, 1);
+      std::vector<double> key(C, 0.0);   // channels with similar delays share tiles
+      for (int c = 0; c < C; ++c)
+        for (int d = 0; d < D; ++d) {
+          st[(size_t)c * D + d] = smax - p->start[(size_t)d * C + c];
+          key[c] += (double)p->start[(size_t)d * C + c];
+        }
+      GatherSpec gs;
+      gs.nout_rows = C;
+      gs.nrow_ch = D;
+      gs.start = st.data();
+      gs.ntap = nt.data();
+      gs.key = key.data();
+      const bool fresh = !p->f32_adj;
+      dedisp_status e = ensure_gather(gs, &p->f32_adj, ci, &cfg);
+      if (fresh && p->f32_adj) p->f32_adj->lead = smax;
+      if (e != DEDISP_OK) return e;
+    } else {
+      F32CfgTables &c = p->f32_adj->cfg[ci];
+      cfg = c.ok ? &c : nullptr;
+    }
+  }
+  if (!cfg) return DEDISP_ERR_UNSUPPORTED;
+  const F32Tables &T = *p->f32_adj;
+  return run_gather_f32(T, *cfg, ci, g, DEDISP_F32, nout, gstride, gbstride, nbatch, D,
+                        DEDISP_W_UNIT, 1, nullptr, T.lead + 1, z, nz, (int64_t)C * nz, nz, s,
+                        nullptr);
 }
 
 }  // namespace dd
