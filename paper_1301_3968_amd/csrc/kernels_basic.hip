@@ -401,64 +401,107 @@ k_adjoint_z(const float *__restrict__ g, int64_t nout, int64_t gstride, int64_t 
 }
 
 // gw[c][k] = sum_b sum_i zbar[b][c][i] x[b][c][i+k] with fp64 products and sums, in
-// two passes.  Pass 1: one workgroup per (chunk of kGwChunk samples, channel, batch
-// element) stages x of its chunk in LDS, keeps its zbar samples in registers and
-// writes its K partial sums; pass 2 adds the partials of each (c, k) in a fixed
-// order, so the result does not depend on the schedule.
-constexpr int kGwChunk = 4096, kGwPerThread = kGwChunk / kThreads, kGwMaxK = 64;
+// two passes.  Pass 1: one workgroup per (chunk of kGwChunk samples, slice of at most
+// KB taps, channel, batch element).  Piece by piece (kGwPiece samples) the workgroup
+// copies zbar and the x it meets into LDS with coalesced loads; a thread then takes
+// kGwRun consecutive samples and the x window they meet into registers and keeps one
+// fp64 accumulator per tap of the slice.  The workgroup reduces them and writes its
+// partial sums.  Pass 2 adds the partials of each (c, k) in a fixed order, so the
+// result does not depend on the schedule.
+constexpr int kGwRun = 8, kGwPiece = kThreads * kGwRun, kGwIter = 4;
+constexpr int kGwChunk = kGwPiece * kGwIter, kGwMaxK = 64;
 
-template <typename XT>
+template <typename XT, int KB>
 __global__ void __launch_bounds__(kThreads)
 k_grad_w_tap_part(const float *__restrict__ z, int64_t nz, const XT *__restrict__ x,
                   int64_t in_stride, int64_t in_bstride, int32_t nchan, int32_t K,
-                  double *__restrict__ part) {
-  __shared__ float xs[kGwChunk + kGwMaxK];
-  __shared__ double red[kGwMaxK][kThreads / 64];
-  const int sidx = blockIdx.x, c = blockIdx.y, b = blockIdx.z, tid = threadIdx.x;
-  const int64_t i0 = (int64_t)sidx * kGwChunk;
-  const int n = (int)min((int64_t)kGwChunk, nz - i0);
-  const XT *xr = x + (int64_t)b * in_bstride + (int64_t)c * in_stride + i0;
-  const float *zr = z + ((int64_t)b * nchan + c) * nz + i0;
-  // x[i0 + i] for i < n + K - 1: the last is x[nz + K - 2] = x[nsamp - 1]
-  for (int i = tid; i < n + K - 1; i += kThreads) xs[i] = (float)xr[i];
-  float zv[kGwPerThread];
+                  int32_t nslice, double *__restrict__ part) {
+  constexpr int XW = (kGwRun + KB - 1 + 3) / 4 * 4;   // x window of a run, whole float4s
+  static_assert(KB <= 16 && kGwRun % 4 == 0, "window within the 16-sample pad");
+  __shared__ __attribute__((aligned(16))) float zs[kGwPiece];
+  __shared__ __attribute__((aligned(16))) float xs[kGwPiece + 16];
+  __shared__ double red[KB][kThreads / 64];
+  const int sidx = blockIdx.x / nslice, k0 = (blockIdx.x - sidx * nslice) * KB;
+  const int c = blockIdx.y, b = blockIdx.z, tid = threadIdx.x;
+  const int kl = min(KB, K - k0);   // taps k0 .. k0 + kl - 1
+  const int nsplit = gridDim.x / nslice;
+  const XT *xr = x + (int64_t)b * in_bstride + (int64_t)c * in_stride + k0;
+  const float *zr = z + ((int64_t)b * nchan + c) * nz;
+  const int64_t nx = nz + K - 1 - k0;   // samples of the input row from k0 on
+  double acc[KB];
 #pragma unroll
-  for (int j = 0; j < kGwPerThread; ++j) {
-    const int i = tid + kThreads * j;
-    zv[j] = i < n ? zr[i] : 0.0f;
-  }
-  __syncthreads();
-  const int lane = tid & 63, wave = tid >> 6;
-  for (int k = 0; k < K; ++k) {
-    double acc = 0.0;
+  for (int k = 0; k < KB; ++k) acc[k] = 0.0;
+  // the next piece is loaded into registers while the current one is summed
+  float zn[kGwRun], xn[kGwRun], xt = 0.0f;
+  auto load_piece = [&](int64_t p0) {
+    // zbar[p0 + i] (zero past nz) and x[p0 + k0 + i] (zero past the row)
 #pragma unroll
-    for (int j = 0; j < kGwPerThread; ++j) {
+    for (int j = 0; j < kGwRun; ++j) {
       const int i = tid + kThreads * j;
-      if (i < n) acc += (double)zv[j] * (double)xs[i + k];
+      zn[j] = p0 + i < nz ? zr[p0 + i] : 0.0f;
+      xn[j] = p0 + i < nx ? (float)xr[p0 + i] : 0.0f;
     }
+    if (tid < 16) xt = p0 + kGwPiece + tid < nx ? (float)xr[p0 + kGwPiece + tid] : 0.0f;
+  };
+  const int64_t c0 = (int64_t)sidx * kGwChunk;
+  load_piece(c0);
+  for (int it = 0; it < kGwIter; ++it) {
+    const int64_t p0 = c0 + (int64_t)it * kGwPiece;
+    if (p0 >= nz) break;   // uniform over the workgroup
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0) red[k][wave] = acc;
+    for (int j = 0; j < kGwRun; ++j) {
+      zs[tid + kThreads * j] = zn[j];
+      xs[tid + kThreads * j] = xn[j];
+    }
+    if (tid < 16) xs[kGwPiece + tid] = xt;
+    __syncthreads();
+    if (it + 1 < kGwIter && p0 + kGwPiece < nz) load_piece(p0 + kGwPiece);
+    const float4 *zp = (const float4 *)(zs + kGwRun * tid);
+    const float4 *xp = (const float4 *)(xs + kGwRun * tid);
+    float zv[kGwRun], xv[XW];
+#pragma unroll
+    for (int q = 0; q < kGwRun / 4; ++q) *(float4 *)&zv[4 * q] = zp[q];
+#pragma unroll
+    for (int q = 0; q < XW / 4; ++q) *(float4 *)&xv[4 * q] = xp[q];
+#pragma unroll
+    for (int q = 0; q < kGwRun; ++q) {
+      const double zq = (double)zv[q];
+#pragma unroll
+      for (int k = 0; k < KB; ++k) acc[k] += zq * (double)xv[q + k];   // k >= kl: never stored
+    }
+    __syncthreads();
+  }
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    double v = acc[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[k][wave] = v;
   }
   __syncthreads();
-  if (tid < K) {
+  if (tid < kl) {
     double t = 0.0;
 #pragma unroll
     for (int w = 0; w < kThreads / 64; ++w) t += red[tid][w];
-    part[(((int64_t)c * gridDim.z + b) * gridDim.x + sidx) * K + tid] = t;
+    part[(((int64_t)c * gridDim.z + b) * nsplit + sidx) * K + k0 + tid] = t;
   }
 }
 
+// One wave per (c, k): lane l adds partials l, l + 64, ..., then a fixed tree.
 __global__ void __launch_bounds__(kThreads)
 k_grad_w_tap_sum(const double *__restrict__ part, int32_t nparts, int32_t nchan, int32_t K,
                  double *__restrict__ gw) {
-  const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (idx >= (int64_t)nchan * K) return;
+  const int64_t idx = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (idx >= (int64_t)nchan * K) return;   // whole waves leave together
   const int64_t c = idx / K, k = idx - c * K;
   const double *pp = part + c * nparts * K + k;
   double t = 0.0;
-  for (int j = 0; j < nparts; ++j) t += pp[(int64_t)j * K];
-  gw[idx] = t;
+  for (int j = lane; j < nparts; j += 64) t += pp[(int64_t)j * K];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+  if (lane == 0) gw[idx] = t;
 }
 
 // gx[b][c][i] = sum_k w[c][k] zbar[b][c][i-k].
@@ -709,23 +752,31 @@ hipError_t launch_grad_w_tap(const dedisp_plan_s *p, const float *z, int64_t nz,
   if (K < 1 || K > kGwMaxK || nz < 1) return hipErrorInvalidValue;
   const int64_t nsplit = (nz + kGwChunk - 1) / kGwChunk;
   const int64_t nparts = nsplit * nbatch;
-  if (nsplit > INT32_MAX || nparts > INT32_MAX || p->nchan > 65535 || nbatch > 65535)
+  const int kb = K <= 8 ? 8 : 16;
+  const int nslice = (K + kb - 1) / kb;
+  if (nsplit * nslice > INT32_MAX || nparts > INT32_MAX || p->nchan > 65535 || nbatch > 65535)
     return hipErrorInvalidValue;
   double *part = nullptr;
   hipError_t e =
       hipMallocAsync((void **)&part, sizeof(double) * (size_t)p->nchan * nparts * K, s);
   if (e != hipSuccess) return e;
-  const dim3 g((unsigned)nsplit, (unsigned)p->nchan, (unsigned)nbatch);
-  if (in_dtype == DEDISP_F32)
-    hipLaunchKernelGGL(k_grad_w_tap_part<float>, g, dim3(kThreads), 0, s, z, nz,
-                       (const float *)x, in_stride, in_bstride, p->nchan, K, part);
-  else
-    hipLaunchKernelGGL(k_grad_w_tap_part<uint8_t>, g, dim3(kThreads), 0, s, z, nz,
-                       (const uint8_t *)x, in_stride, in_bstride, p->nchan, K, part);
+  const dim3 g((unsigned)(nsplit * nslice), (unsigned)p->nchan, (unsigned)nbatch);
+#define DD_GW_LAUNCH(XT, KB)                                                     \
+  hipLaunchKernelGGL((k_grad_w_tap_part<XT, KB>), g, dim3(kThreads), 0, s, z, nz, \
+                     (const XT *)x, in_stride, in_bstride, p->nchan, K, nslice, part)
+  if (in_dtype == DEDISP_F32) {
+    if (kb == 8) DD_GW_LAUNCH(float, 8);
+    else DD_GW_LAUNCH(float, 16);
+  } else {
+    if (kb == 8) DD_GW_LAUNCH(uint8_t, 8);
+    else DD_GW_LAUNCH(uint8_t, 16);
+  }
+#undef DD_GW_LAUNCH
   e = hipGetLastError();
   if (e == hipSuccess) {
-    const int64_t n = (int64_t)p->nchan * K;
-    hipLaunchKernelGGL(k_grad_w_tap_sum, dim3((unsigned)((n + kThreads - 1) / kThreads)),
+    const int64_t n = (int64_t)p->nchan * K;   // one wave each
+    constexpr int kWaves = kThreads / 64;
+    hipLaunchKernelGGL(k_grad_w_tap_sum, dim3((unsigned)((n + kWaves - 1) / kWaves)),
                        dim3(kThreads), 0, s, part, (int32_t)nparts, p->nchan, K, gw);
     e = hipGetLastError();
   }

@@ -102,7 +102,9 @@ __device__ __forceinline__ int32_t ldc(const int32_t *p, int64_t i) {
 }
 
 // ---- rows ----------------------------------------------------------------------
-constexpr int kRowThreads = 256, kRowTau = 4 * kRowThreads;   // 4 tau per thread
+// Each thread builds 4 consecutive tau in each of kRowHalves runs of 4 * kRowThreads.
+constexpr int kRowThreads = 256, kRowHalves = 2, kRowTau = 4 * kRowThreads * kRowHalves;
+constexpr int kRowLoads = kRowTau / kRowThreads;   // block samples loaded per thread
 
 template <typename XT>
 __global__ void __launch_bounds__(kRowThreads)
@@ -115,29 +117,51 @@ k_rows_f32(const XT *__restrict__ x, int64_t in_stride, int64_t in_bstride, int6
   const int64_t blk0 = (int64_t)blockIdx.x * kRowTau;
   const int n0 = nmin[c], n1 = nmaxv[c];
   const XT *row = x + (int64_t)b * in_bstride + (int64_t)c * in_stride;
-  const int nval = kRowTau + n1;
-  for (int i = tid; i < nval; i += kRowThreads) {
-    const int64_t g = seg0 + blk0 + i - lead;   // rows start `lead` zeros before the input
+  // input samples blk0 .. blk0 + kRowTau + n1 of the row (rows start `lead` zeros
+  // before the input); the fixed part is loaded with every load in flight at once
+  const int64_t g0 = seg0 + blk0 - lead;
+  float v0[kRowLoads];
+#pragma unroll
+  for (int j = 0; j < kRowLoads; ++j) {
+    const int64_t g = g0 + tid + kRowThreads * j;
+    v0[j] = (g >= 0 && g < nsamp) ? (float)row[g] : 0.0f;
+  }
+#pragma unroll
+  for (int j = 0; j < kRowLoads; ++j) sxf[tid + kRowThreads * j] = v0[j];
+  for (int i = kRowTau + tid; i < kRowTau + n1; i += kRowThreads) {
+    const int64_t g = g0 + i;
     sxf[i] = (g >= 0 && g < nsamp) ? (float)row[g] : 0.0f;
   }
   __syncthreads();
-  const int64_t tau0 = blk0 + 4 * tid;
-  if (tau0 >= tpad) return;
   const float wc = wmode == DEDISP_W_CHANNEL ? w[c] : 1.0f;
-  float s[4] = {0.f, 0.f, 0.f, 0.f};
-  float *base = R + ((int64_t)b * nrows + rowidx[c]) * tpad + tau0;
-  if (n0 == 0) *(float4 *)base = make_float4(0.f, 0.f, 0.f, 0.f);
-  const float *xl = sxf + 4 * tid;
+  float *rbase = R + ((int64_t)b * nrows + rowidx[c]) * tpad;
+  float s[kRowHalves][4] = {};
+  bool live[kRowHalves];
+  int64_t tau0[kRowHalves];
+#pragma unroll
+  for (int h = 0; h < kRowHalves; ++h) {
+    tau0[h] = blk0 + 4 * tid + 4 * kRowThreads * h;
+    live[h] = tau0[h] < tpad;   // tpad is a multiple of 4
+    if (live[h] && n0 == 0) *(float4 *)(rbase + tau0[h]) = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   for (int n = 1; n <= n1; ++n) {
     const float wk = wmode == DEDISP_W_TAP ? w[(int64_t)c * K + (n - 1)] : 1.0f;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) s[i] += wk * xl[i + n - 1];
-    if (n >= n0) {
-      float v[4];
+    for (int h = 0; h < kRowHalves; ++h) {
+      const float *xl = sxf + 4 * tid + 4 * kRowThreads * h + (n - 1);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)   // windows running past the end of the block are zero
-        v[i] = (seg0 + tau0 + i + n <= nsamp + lead) ? s[i] * wc : 0.0f;
-      *(float4 *)(base + (int64_t)(n - n0) * tpad) = make_float4(v[0], v[1], v[2], v[3]);
+      for (int i = 0; i < 4; ++i) s[h][i] += wk * xl[i];
+    }
+    if (n >= n0) {
+#pragma unroll
+      for (int h = 0; h < kRowHalves; ++h) {
+        if (!live[h]) continue;
+        float v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)   // windows running past the end of the block are zero
+          v[i] = (seg0 + tau0[h] + i + n <= nsamp + lead) ? s[h][i] * wc : 0.0f;
+        *(float4 *)(rbase + (int64_t)(n - n0) * tpad + tau0[h]) = make_float4(v[0], v[1], v[2], v[3]);
+      }
     }
   }
 }

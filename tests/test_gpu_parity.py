@@ -170,13 +170,14 @@ def test_tap_weights_forward_and_backward(dd, orc):
     assert np.allclose(got, ref, rtol=2e-7, atol=1e-6)
 
 
-@pytest.mark.parametrize("tile", [-1, -2])
-@pytest.mark.parametrize("xdtype", ["f32", "u8"])
-def test_tap_backward_many_channel_groups(dd, orc, tile, xdtype):
+@pytest.mark.parametrize("tile,xdtype,K", [(-1, "f32", 4), (-2, "f32", 4), (-1, "u8", 4),
+                                           (-2, "u8", 4), (-1, "f32", 20), (-1, "u8", 37)])
+def test_tap_backward_many_channel_groups(dd, orc, tile, xdtype, K):
     """Dense tap-weight adjoint at 300 channels x 80 trials: the tiled transpose gather
     (several trial groups per channel tile, ragged channel and time tiles) and the
-    general kernels (tile -2), both against the oracle."""
-    B, C, D, K, T = 2, 300, 80, 4, 6000
+    general kernels (tile -2), both against the oracle; 20 and 37 taps take several
+    tap slices in the weight gradient, the last one partly filled."""
+    B, C, D, T = 2, 300, 80, 6000
     rng = np.random.default_rng(4321)
     f = workloads.channel_centres(1.2, 0.3, C)
     dms = np.linspace(0, 1000, D)
