@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdedisp.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-SOURCES = ["plan.cpp", "api.cpp", "kernels_basic.hip", "kernels_search.hip", "kernels_f32.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "kernels_basic.hip", "kernels_search.hip", "kernels_f32.hip",
+           "kernels_mfma.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

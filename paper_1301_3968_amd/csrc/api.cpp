@@ -69,6 +69,13 @@ static dedisp_status run_dedisperse(dedisp_plan p, const void *in, int32_t in_dt
     if (p->wmode == DEDISP_W_UNIT && out_dtype == DEDISP_I32 &&
         255.0 * (double)p->sum_max_ntap >= 2147483647.0)
       return fail(DEDISP_ERR_OVERFLOW, "int32 dedispersion sum could overflow");
+    // int32 output: the matrix-core kernel when the plan fits it
+    if (p->wmode == DEDISP_W_UNIT && out_dtype == DEDISP_I32 && p->tile_choice != -2) {
+      dedisp_status st = run_dedisperse_u8_mfma(p, (const uint8_t *)in, nsamp, in_stride,
+                                                in_bstride, nbatch, (int32_t *)out, out_stride,
+                                                out_bstride, nout, s, kt);
+      if (st != DEDISP_ERR_UNSUPPORTED) return st;
+    }
     if (nsamp * 255.0 >= 2147483647.0)
       return fail(DEDISP_ERR_OVERFLOW, "block too long for the int32 prefix");
     const int64_t pstride = nsamp + 1;

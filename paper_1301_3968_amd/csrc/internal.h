@@ -35,6 +35,7 @@ struct WidthList {
 // tiled fp32 dedispersion.
 struct TiledTables;
 struct F32Tables;
+struct MfmaTables;
 
 struct DevTables {
   int32_t *start = nullptr;   // [ndm][nchan]
@@ -68,6 +69,7 @@ struct dedisp_plan_s {
   dd::TiledTables *tiled = nullptr;     // optimised-search tables (built lazily)
   dd::F32Tables *f32 = nullptr;         // tiled fp32 dedispersion tables (built lazily)
   dd::F32Tables *f32_adj = nullptr;     // tables of the transposed (adjoint) gather
+  dd::MfmaTables *mfma = nullptr;       // matrix-core uint8 dedispersion tables
 
   // Instrumentation events around the dominant kernel (dedisp_set_kernel_events).
   std::vector<hipEvent_t> ev_start, ev_stop;
@@ -107,6 +109,7 @@ inline const float *weights_of(const dedisp_plan_s *p) {
 }
 void free_tiled(TiledTables *t);
 void free_f32(F32Tables *t);
+void free_mfma(MfmaTables *t);
 
 // Launchers (kernels_*.hip).  All enqueue on `stream` and return hipError_t.
 hipError_t launch_prefix_u8(const uint8_t *x, int64_t in_stride, int64_t in_bstride, int32_t nchan,
@@ -170,6 +173,12 @@ dedisp_status run_dedisperse_f32_tiled(dedisp_plan p, const void *in, int32_t in
                                        int32_t nbatch, float *out, int64_t out_stride,
                                        int64_t out_bstride, int64_t nout, hipStream_t s,
                                        KernelTimer *kt);
+// uint8 input, unit weights, int32 output on the int8 matrix cores (kernels_mfma.hip).
+// Returns DEDISP_ERR_UNSUPPORTED (launching nothing) when the plan does not fit.
+dedisp_status run_dedisperse_u8_mfma(dedisp_plan p, const uint8_t *x, int64_t nsamp,
+                                     int64_t in_stride, int64_t in_bstride, int32_t nbatch,
+                                     int32_t *out, int64_t out_stride, int64_t out_bstride,
+                                     int64_t nout, hipStream_t s, KernelTimer *kt);
 // zbar[b][c][tau] = sum_d g[b][d][tau - start[d][c]] for tau in [0, nz) on the same
 // tiled kernel; DEDISP_ERR_UNSUPPORTED (launching nothing) when it does not fit.
 dedisp_status run_adjoint_z_tiled(dedisp_plan p, const float *g, int64_t nout, int64_t gstride,

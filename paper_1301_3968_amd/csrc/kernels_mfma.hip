@@ -1,0 +1,511 @@
+// Dedispersion of uint8 data with unit weights (eq. p_dedisp) on the int8 matrix cores.
+//
+// For a tile of 16 trials and a channel c, the samples a trial adds lie in a short band
+// of delays: trial d takes x[c][t + start[d,c] + k] for k < ntap[d,c], and over the 16
+// trials these delays span [lo_c, lo_c + L_c).  Cutting the band into segments of 16
+// delays, the tile's sums over channel c are
+//     y[d][t] += sum_{segments s} sum_{j<16} mask_s[d][j] * x[c][t + o_s + j],
+// a product of a 16 x 16 0/1 matrix (which delays trial d takes) with a 16 x T Hankel
+// matrix of samples.  Four segments (of one or several channels) make the K = 64 of one
+// v_mfma_i32_16x16x64_i8; the samples enter as int8 x ^ 0x80 = x - 128, and every
+// trial's result is corrected by 128 times its number of samples, so the int32 result
+// is exact.
+//
+// One workgroup takes 16 NWD trials x NWT * 16 NT outputs; each wave 16 trials x 16 NT
+// outputs.  Channel groups are staged into LDS (two buffers: the next group is loaded
+// while the current one is multiplied) as 16 byte-shifted copies of each channel's
+// window, so that the 16 samples a lane needs (window bytes i .. i + 15) are one aligned
+// 16-byte read: the copies are interleaved per 16-byte chunk, chunk q of copy p at
+// 256 q + 16 p, so the 16 lanes of a segment (i = r .. r + 15) read 16 different bank
+// slots.  The host plans, per group of 4 segments (a K block), the 0/1 masks of each
+// lane and the LDS address each lane reads.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+
+namespace dd {
+
+// Workgroup shapes: NWD waves along DM, NWT along time, NT blocks of 16 outputs per wave.
+#define DD_MFMA_CONFIGS(X) \
+  X(0, 4, 2, 16)           \
+  X(1, 4, 2, 8)
+struct MfmaCfg {
+  int nwd, nwt, nt;
+};
+#define DD_MFMA_ENTRY(i, a, b, c) {a, b, c},
+static const MfmaCfg kMfmaCfgs[] = {DD_MFMA_CONFIGS(DD_MFMA_ENTRY)};
+#undef DD_MFMA_ENTRY
+constexpr int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
+constexpr int kPhases = 16;                 // byte-shifted copies of each staged window
+constexpr int kMfmaBufBytes = 80 * 1024;    // LDS per staging buffer (two per workgroup)
+constexpr int kMaxKb = 8;                   // K blocks of one wave in one channel group
+constexpr int kMaxTasks = 3;                // staging tasks (quarter chunks) per thread
+
+struct MGroup {
+  int32_t unit_begin, nunits;   // staging units (16 window bytes of one channel each)
+  int32_t kb_base, pad;         // index into the per-wave K-block ranges
+};
+struct MUnit {
+  int32_t c;      // channel
+  int32_t src;    // first window sample of the chunk, relative to the tile's first output
+  int32_t dst;    // LDS byte offset of the chunk's 256-byte block (16 copies of 16 bytes)
+  int32_t pad;
+};
+
+struct MfmaCfgTables {
+  bool ok = false;
+  int tw = 0, ntw = 0, trials = 0;
+  std::vector<int32_t> perm, ntot, group_begin, kbr;
+  std::vector<MGroup> groups;
+  std::vector<MUnit> units;
+  std::vector<uint8_t> masks;     // [kb][64 lanes][16]
+  std::vector<int32_t> addrs;     // [kb][64 lanes]
+  int32_t *d_perm = nullptr, *d_ntot = nullptr, *d_group_begin = nullptr, *d_kbr = nullptr;
+  int32_t *d_addrs = nullptr;
+  MGroup *d_groups = nullptr;
+  MUnit *d_units = nullptr;
+  uint8_t *d_masks = nullptr;
+};
+struct MfmaTables {
+  MfmaCfgTables cfg[kNumMfmaCfgs];
+  bool tried[kNumMfmaCfgs] = {};
+};
+
+void free_mfma(MfmaTables *t) {
+  if (!t) return;
+  for (auto &c : t->cfg) {
+    (void)hipFree(c.d_perm);
+    (void)hipFree(c.d_ntot);
+    (void)hipFree(c.d_group_begin);
+    (void)hipFree(c.d_kbr);
+    (void)hipFree(c.d_addrs);
+    (void)hipFree(c.d_groups);
+    (void)hipFree(c.d_units);
+    (void)hipFree(c.d_masks);
+  }
+  delete t;
+}
+
+namespace {
+
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
+
+struct MfmaArgs {
+  const uint8_t *x;
+  int64_t in_stride, in_bstride, nsamp;
+  int32_t ntw, ntt, bufbytes, pad0;
+  const int32_t *group_begin, *kbr, *perm, *ntot, *addrs;
+  const MGroup *groups;
+  const MUnit *units;
+  const v4i *masks;
+  int32_t *out;
+  int64_t out_stride, out_bstride, nout;
+};
+
+template <typename T>
+__device__ __forceinline__ T ldc(const T *p, int64_t i) {
+  return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
+// The 24 bytes of the row from the 4-byte aligned address at or below row + pos (pos
+// may be past the row; bytes outside [0, nsamp) read as 0), as 6 dwords.
+__device__ __forceinline__ void load_raw(const uint8_t *row, int64_t nsamp, int64_t pos,
+                                         uint32_t raw[6], int *sh) {
+  const uintptr_t abs = (uintptr_t)(row + pos);
+  *sh = (int)(abs & 3);
+  const int64_t p0 = pos - *sh;   // row-relative position of the aligned first byte
+  const uint32_t *a = (const uint32_t *)(abs - *sh);
+  if (p0 >= 0 && p0 + 24 <= nsamp) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) raw[k] = a[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      uint32_t v = 0;
+      for (int j = 0; j < 4; ++j) {
+        const int64_t q = p0 + 4 * k + j;
+        if (q >= 0 && q < nsamp) v |= (uint32_t)row[q] << (8 * j);
+      }
+      raw[k] = v;
+    }
+  }
+}
+
+// One staging task: copies 4h .. 4h + 3 of a chunk (copy p = window bytes p .. p + 15
+// of the chunk, as int8 x ^ 0x80), from the 24 raw bytes at the chunk start + 4h.  The
+// copies are written in an order rotated by the chunk index, so that the lanes of one
+// write instruction fall on different bank slots.
+__device__ __forceinline__ void store_task(unsigned char *buf, int32_t dst, int h, int rot,
+                                           const uint32_t raw[6], int sh) {
+  uint32_t e[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+    e[k] = __builtin_amdgcn_alignbyte(raw[k + 1], raw[k], (uint32_t)sh) ^ 0x80808080u;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int s = (j + rot) & 3;
+    v4i v;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = (int32_t)__builtin_amdgcn_alignbyte(e[m + 1], e[m], (uint32_t)s);
+    *(v4i *)(buf + dst + 16 * (4 * h + s)) = v;
+  }
+}
+
+template <int NWD, int NWT, int NT>
+__global__ void __launch_bounds__(64 * NWD * NWT)
+k_dedisp_mfma(MfmaArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  constexpr int NW = NWD * NWT, TWV = 16 * NT, TW = NWT * TWV;
+  // XCD-aware tile order (blocks b = x mod 8 run on XCD x): contiguous runs of tiles
+  const int nb = a.ntw * a.ntt;
+  const int bi = blockIdx.x;
+  const int xcd = bi & 7, kk = bi >> 3, q = nb >> 3, rem = nb & 7;
+  const int L = xcd * q + min(xcd, rem) + kk;
+  const int tt = L / a.ntw, tw = L - tt * a.ntw;
+  const int bb = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wd = wave % NWD, wt = wave / NWD;
+  const int64_t T0 = (int64_t)tt * TW;
+  const uint8_t *xb = a.x + (int64_t)bb * a.in_bstride;
+
+  v4i acc[NT];
+#pragma unroll
+  for (int b = 0; b < NT; ++b) acc[b] = (v4i){0, 0, 0, 0};
+
+  const int gb = ldc(a.group_begin, tw), ge = ldc(a.group_begin, tw + 1);
+  // masks and lane addresses of the K blocks of a group, loaded one group ahead
+  v4i mk[kMaxKb], mkn[kMaxKb];
+  int32_t ad[kMaxKb], adn[kMaxKb];
+  int nk = 0, nkn = 0;
+  auto load_kb = [&](int g) {
+    const int base = ldc(&a.groups[g].kb_base, 0);
+    const int k0 = ldc(a.kbr, (int64_t)base + wd), k1 = ldc(a.kbr, (int64_t)base + wd + 1);
+    nkn = k1 - k0;
+#pragma unroll
+    for (int i = 0; i < kMaxKb; ++i)
+      if (i < nkn) {
+        mkn[i] = a.masks[(int64_t)(k0 + i) * 64 + lane];
+        adn[i] = a.addrs[(int64_t)(k0 + i) * 64 + lane];
+      }
+  };
+  load_kb(gb);
+  // staging tasks: thread t takes quarter t % 4 of chunks t / 4, t / 4 + NW * 16, ...
+  constexpr int NTHR = 64 * NW, TPT = kMaxTasks;
+  uint32_t raw[TPT][6];
+  int sh[TPT], dst[TPT], rot[TPT];
+  int ntask = 0;
+  const int h = tid & 3;
+  auto fetch = [&](int g) {
+    const int ub = ldc(&a.groups[g].unit_begin, 0), nu = ldc(&a.groups[g].nunits, 0);
+    ntask = 0;
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) {
+      const int k = (tid >> 2) + (NTHR / 4) * i;
+      if (k < nu) {
+        const MUnit u = a.units[ub + k];
+        load_raw(xb + (int64_t)u.c * a.in_stride, a.nsamp, T0 + u.src + 4 * h, raw[i], &sh[i]);
+        dst[i] = u.dst;
+        rot[i] = k;
+        ntask = i + 1;
+      }
+    }
+  };
+  auto store = [&](unsigned char *buf) {
+#pragma unroll
+    for (int i = 0; i < TPT; ++i)
+      if (i < ntask) store_task(buf, dst[i], h, rot[i], raw[i], sh[i]);
+  };
+  fetch(gb);
+  store(lds);
+  __syncthreads();
+  for (int g = gb; g < ge; ++g) {
+    const int par = (g - gb) & 1;
+    nk = nkn;
+#pragma unroll
+    for (int i = 0; i < kMaxKb; ++i) {
+      mk[i] = mkn[i];
+      ad[i] = adn[i];
+    }
+    if (g + 1 < ge) {
+      load_kb(g + 1);
+      fetch(g + 1);
+    }
+    const unsigned char *buf = lds + par * a.bufbytes + 256 * NT * wt;
+#pragma unroll
+    for (int i = 0; i < kMaxKb; ++i) {
+      if (i >= nk) break;
+      const unsigned char *p = buf + ad[i];
+#pragma unroll
+      for (int b = 0; b < NT; ++b) {
+        const v4i d = *(const v4i *)(p + 256 * b);
+        acc[b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(mk[i], d, acc[b], 0, 0, 0);
+      }
+    }
+    if (g + 1 < ge) store(lds + (par ^ 1) * a.bufbytes);
+    __syncthreads();
+  }
+  // C layout: lane l, element r holds trial row 4 (l / 16) + r, output l % 16
+  int32_t *ob = a.out + (int64_t)bb * a.out_bstride;
+  const int n = lane & 15, g4 = lane >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int slot = tw * 16 * NWD + 16 * wd + 4 * g4 + r;
+    const int d = a.perm[slot];
+    if (d < 0) continue;
+    const int32_t corr = 128 * a.ntot[d];
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      const int64_t t = T0 + (int64_t)TWV * wt + 16 * b + n;
+      if (t < a.nout) ob[(int64_t)d * a.out_stride + t] = acc[b][r] + corr;
+    }
+  }
+}
+
+}  // namespace
+
+// ---- host ----------------------------------------------------------------------
+template <typename T>
+static hipError_t upload(T **dst, const std::vector<T> &v) {
+  if (v.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void **)dst, sizeof(T) * v.size());
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
+}
+
+// Tables of configuration ci: trial order, per DM tile the channel groups with their
+// staging units, and per (group, wave) the K blocks (masks and lane addresses).
+static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
+  const MfmaCfg cf = kMfmaCfgs[ci];
+  const int C = p->nchan, D = p->ndm;
+  const int NWD = cf.nwd, TW = cf.nwt * 16 * cf.nt, DT = 16 * NWD;
+  out = MfmaCfgTables();
+  out.tw = TW;
+  out.trials = DT;
+  std::vector<int32_t> order(D);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p->dm[x] < p->dm[y]; });
+  const int ntw = (D + DT - 1) / DT;
+  out.ntw = ntw;
+  out.perm.assign((size_t)ntw * DT, -1);
+  for (int i = 0; i < D; ++i) out.perm[i] = order[i];
+  out.ntot.assign(D, 0);
+  for (int d = 0; d < D; ++d) {
+    int64_t s = 0;
+    for (int c = 0; c < C; ++c) s += p->ntap[(size_t)d * C + c];
+    if (s > (INT32_MAX - 1) / 256) return false;
+    out.ntot[d] = (int32_t)s;
+  }
+  out.group_begin.assign(ntw + 1, 0);
+  std::vector<int32_t> lo(NWD * C), nseg(NWD * C);
+  std::vector<int32_t> stlo(C), wst(C);
+  for (int tw = 0; tw < ntw; ++tw) {
+    out.group_begin[tw] = (int)out.groups.size();
+    // bands of every sub-tile and the staged window of every channel
+    for (int c = 0; c < C; ++c) {
+      int slo = INT32_MAX, send = INT32_MIN;
+      for (int w = 0; w < NWD; ++w) {
+        int l = INT32_MAX, h = INT32_MIN;
+        for (int m = 0; m < 16; ++m) {
+          const int d = out.perm[(size_t)tw * DT + 16 * w + m];
+          if (d < 0 || p->ntap[(size_t)d * C + c] == 0) continue;
+          l = std::min(l, p->start[(size_t)d * C + c]);
+          h = std::max(h, p->start[(size_t)d * C + c] + p->ntap[(size_t)d * C + c]);
+        }
+        lo[w * C + c] = l;
+        nseg[w * C + c] = l == INT32_MAX ? 0 : (h - l + 15) / 16;
+        if (nseg[w * C + c]) {
+          slo = std::min(slo, l);
+          send = std::max(send, l + 16 * nseg[w * C + c]);
+        }
+      }
+      if (slo == INT32_MAX) {
+        wst[c] = 0;
+        continue;
+      }
+      stlo[c] = slo;
+      wst[c] = (send - slo + TW + 15) / 16 * 16;   // window bytes (16 copies each)
+      if ((int64_t)kPhases * wst[c] > kMfmaBufBytes) return false;
+    }
+    int c = 0;
+    while (c < C) {
+      // channels of the group: within the LDS buffer, and at most kMaxKb K blocks
+      // (4 kMaxKb segments) for every wave
+      int used = 0;
+      const int cbeg = c;
+      std::vector<int> segw(NWD, 0);
+      int nunits = 0;   // at most kMaxTasks quarter chunks per thread
+      while (c < C && (int64_t)used + (int64_t)kPhases * wst[c] <= kMfmaBufBytes &&
+             4 * (nunits + wst[c] / 16) <= kMaxTasks * 64 * NWD * cf.nwt) {
+        bool fits = true;
+        for (int w = 0; w < NWD; ++w) fits = fits && segw[w] + nseg[w * C + c] <= 4 * kMaxKb;
+        if (!fits) break;
+        for (int w = 0; w < NWD; ++w) segw[w] += nseg[w * C + c];
+        used += kPhases * wst[c];
+        nunits += wst[c] / 16;
+        ++c;
+      }
+      MGroup gi{};
+      gi.unit_begin = (int)out.units.size();
+      std::vector<int32_t> region(C, 0);
+      int off = 0;
+      for (int cc = cbeg; cc < c; ++cc) {
+        if (!wst[cc]) continue;
+        region[cc] = off;
+        for (int k = 0; k < wst[cc] / 16; ++k)
+          out.units.push_back(MUnit{cc, stlo[cc] + 16 * k, off + 256 * k, 0});
+        off += kPhases * wst[cc];
+      }
+      gi.nunits = (int)out.units.size() - gi.unit_begin;
+      if (4 * gi.nunits > kMaxTasks * 64 * NWD * cf.nwt) return false;
+      gi.kb_base = (int)out.kbr.size();
+      for (int w = 0; w < NWD; ++w) {
+        out.kbr.push_back((int32_t)(out.addrs.size() / 64));
+        // segments of this sub-tile in the group, four per K block
+        std::vector<std::pair<int, int>> segs;
+        for (int cc = cbeg; cc < c; ++cc)
+          for (int s = 0; s < nseg[w * C + cc]; ++s) segs.push_back({cc, lo[w * C + cc] + 16 * s});
+        for (size_t s0 = 0; s0 < segs.size(); s0 += 4) {
+          for (int lane = 0; lane < 64; ++lane) {
+            const int n = lane & 15, g = lane >> 4;
+            const size_t si = s0 + g;
+            uint8_t mk[16] = {};
+            int32_t ad = 0;
+            if (si < segs.size()) {
+              const int cc = segs[si].first, o = segs[si].second;
+              const int d = out.perm[(size_t)tw * DT + 16 * w + n];
+              if (d >= 0) {
+                const int st = p->start[(size_t)d * C + cc], nt = p->ntap[(size_t)d * C + cc];
+                for (int j = 0; j < 16; ++j) mk[j] = (o + j >= st && o + j < st + nt) ? 1 : 0;
+              }
+              const int rel = o - stlo[cc] + n;
+              ad = region[cc] + 256 * (rel >> 4) + 16 * (rel & 15);
+            } else {
+              // padding segment: zero masks, address of a valid window
+              const int cc = segs[s0].first, rel = segs[s0].second - stlo[cc] + n;
+              ad = region[cc] + 256 * (rel >> 4) + 16 * (rel & 15);
+            }
+            // the mask rows go to lane (trial row n, segment g); the address to lane
+            // (output column n, segment g): both are lane = 16 g + n
+            out.masks.insert(out.masks.end(), mk, mk + 16);
+            out.addrs.push_back(ad);
+          }
+        }
+      }
+      out.kbr.push_back((int32_t)(out.addrs.size() / 64));
+      out.groups.push_back(gi);
+      if (c == cbeg) return false;   // one channel does not fit
+    }
+  }
+  out.group_begin[ntw] = (int)out.groups.size();
+  out.ok = !out.groups.empty();
+  return out.ok;
+}
+
+static hipError_t allow_lds_mfma(const void *fn, bool *done, std::mutex *mu, int bytes) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= 64) return e;
+  std::lock_guard<std::mutex> lk(*mu);
+  if (!done[dev]) {
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) done[dev] = true;
+  }
+  return e;
+}
+
+template <int NWD, int NWT, int NT>
+static hipError_t launch_mfma_cfg(const MfmaArgs &a, int nbatch, hipStream_t s) {
+  static bool done[64] = {};
+  static std::mutex mu;
+  hipError_t e =
+      allow_lds_mfma((const void *)k_dedisp_mfma<NWD, NWT, NT>, done, &mu, 2 * kMfmaBufBytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_dedisp_mfma<NWD, NWT, NT>), dim3(a.ntw * a.ntt, nbatch),
+                     dim3(64 * NWD * NWT), 2 * a.bufbytes, s, a);
+  return hipGetLastError();
+}
+
+static hipError_t launch_mfma(int ci, const MfmaArgs &a, int nbatch, hipStream_t s) {
+  switch (ci) {
+#define DD_MFMA_CASE(i, x, y, z) \
+  case i: return launch_mfma_cfg<x, y, z>(a, nbatch, s);
+    DD_MFMA_CONFIGS(DD_MFMA_CASE)
+#undef DD_MFMA_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+dedisp_status run_dedisperse_u8_mfma(dedisp_plan p, const uint8_t *x, int64_t nsamp,
+                                     int64_t in_stride, int64_t in_bstride, int32_t nbatch,
+                                     int32_t *out, int64_t out_stride, int64_t out_bstride,
+                                     int64_t nout, hipStream_t s, KernelTimer *kt) {
+  if (p->wmode != DEDISP_W_UNIT || nbatch > 65535) return DEDISP_ERR_UNSUPPORTED;
+  // the 16-block shape (512 outputs per workgroup), else the 8-block one
+  int ci = -1;
+  MfmaCfgTables *cfg = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!p->mfma) {
+      p->mfma = new (std::nothrow) MfmaTables;
+      if (!p->mfma) return fail(DEDISP_ERR_OOM, "host allocation failed");
+    }
+    for (int k = 0; k < kNumMfmaCfgs && !cfg; ++k) {
+      MfmaCfgTables &c = p->mfma->cfg[k];
+      if (!p->mfma->tried[k]) {
+        p->mfma->tried[k] = true;
+        if (build_mfma_cfg(p, k, c)) {
+          DD_HIP(upload(&c.d_perm, c.perm));
+          DD_HIP(upload(&c.d_ntot, c.ntot));
+          DD_HIP(upload(&c.d_group_begin, c.group_begin));
+          DD_HIP(upload(&c.d_kbr, c.kbr));
+          DD_HIP(upload(&c.d_addrs, c.addrs));
+          DD_HIP(upload(&c.d_groups, c.groups));
+          DD_HIP(upload(&c.d_units, c.units));
+          DD_HIP(upload(&c.d_masks, c.masks));
+        }
+      }
+      if (c.ok) {
+        cfg = &c;
+        ci = k;
+      }
+    }
+  }
+  if (!cfg) return DEDISP_ERR_UNSUPPORTED;
+  const int64_t ntt = (nout + cfg->tw - 1) / cfg->tw;
+  if (ntt * cfg->ntw > INT32_MAX / 2) return DEDISP_ERR_UNSUPPORTED;
+  MfmaArgs a{};
+  a.x = x;
+  a.in_stride = in_stride;
+  a.in_bstride = in_bstride;
+  a.nsamp = nsamp;
+  a.ntw = cfg->ntw;
+  a.ntt = (int32_t)ntt;
+  a.bufbytes = kMfmaBufBytes;
+  a.group_begin = cfg->d_group_begin;
+  a.kbr = cfg->d_kbr;
+  a.perm = cfg->d_perm;
+  a.ntot = cfg->d_ntot;
+  a.addrs = cfg->d_addrs;
+  a.groups = cfg->d_groups;
+  a.units = cfg->d_units;
+  a.masks = (const v4i *)cfg->d_masks;
+  a.out = out;
+  a.out_stride = out_stride;
+  a.out_bstride = out_bstride;
+  a.nout = nout;
+  hipError_t e = kt ? kt->begin() : hipSuccess;
+  if (e == hipSuccess) e = launch_mfma(ci, a, nbatch, s);
+  if (e == hipSuccess && kt) e = kt->end();
+  if (e != hipSuccess) return hip_fail(e, "mfma dedisperse launch");
+  return DEDISP_OK;
+}
+
+}  // namespace dd

@@ -380,6 +380,7 @@ dedisp_status dedisp_plan_destroy(dedisp_plan p) {
   if (p->tiled) dd::free_tiled(p->tiled);
   if (p->f32) dd::free_f32(p->f32);
   if (p->f32_adj) dd::free_f32(p->f32_adj);
+  if (p->mfma) dd::free_mfma(p->mfma);
   delete p;
   return DEDISP_OK;
 }
