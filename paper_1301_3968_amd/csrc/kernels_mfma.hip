@@ -17,8 +17,11 @@
 // window, so that the 16 samples a lane needs (window bytes i .. i + 15) are one aligned
 // 16-byte read: the copies are interleaved per 16-byte chunk, chunk q of copy p at
 // 256 q + 16 p, so the 16 lanes of a segment (i = r .. r + 15) read 16 different bank
-// slots.  The host plans, per group of 4 segments (a K block), the 0/1 masks of each
-// lane and the LDS address each lane reads.
+// slots.  The host plans, per group of 4 segments (a K block), a 160-byte record: the
+// 16-bit mask of every (trial, segment) (which of the segment's 16 delays the trial
+// takes) and where each segment's window sits in LDS; the records of a channel group
+// are copied into LDS with the windows, and every lane forms its 16 mask bytes and its
+// read address from them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,25 +35,30 @@
 
 namespace dd {
 
-// Workgroup shapes: NWD waves along DM, NWT along time, NT blocks of 16 outputs per wave.
+// Workgroup shapes: NWD waves along DM, NWT along time, NT blocks of 16 outputs per wave,
+// RING 16-byte sample reads in flight per wave.
 #define DD_MFMA_CONFIGS(X) \
-  X(0, 4, 2, 16)           \
-  X(1, 4, 2, 8)
+  X(0, 8, 2, 16, 4)        \
+  X(1, 16, 1, 16, 4)
 struct MfmaCfg {
-  int nwd, nwt, nt;
+  int nwd, nwt, nt, ring;
 };
-#define DD_MFMA_ENTRY(i, a, b, c) {a, b, c},
+#define DD_MFMA_ENTRY(i, a, b, c, r) {a, b, c, r},
 static const MfmaCfg kMfmaCfgs[] = {DD_MFMA_CONFIGS(DD_MFMA_ENTRY)};
 #undef DD_MFMA_ENTRY
 constexpr int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
 constexpr int kPhases = 16;                 // byte-shifted copies of each staged window
 constexpr int kMfmaBufBytes = 80 * 1024;    // LDS per staging buffer (two per workgroup)
 constexpr int kMaxKb = 8;                   // K blocks of one wave in one channel group
+constexpr int kRecBytes = 160;              // K-block record: 64 x u16 masks + 4 x (region, rel)
 constexpr int kMaxTasks = 3;                // staging tasks (quarter chunks) per thread
 
 struct MGroup {
   int32_t unit_begin, nunits;   // staging units (16 window bytes of one channel each)
-  int32_t kb_base, pad;         // index into the per-wave K-block ranges
+  int32_t kb_base;              // index into the per-wave K-block ranges
+  int32_t kb_first, nkb;        // the group's K blocks (all waves): first and count
+  int32_t rec_off;              // LDS byte offset of their records in the buffer
+  int32_t pad0, pad1;
 };
 struct MUnit {
   int32_t c;      // channel
@@ -65,13 +73,11 @@ struct MfmaCfgTables {
   std::vector<int32_t> perm, ntot, group_begin, kbr;
   std::vector<MGroup> groups;
   std::vector<MUnit> units;
-  std::vector<uint8_t> masks;     // [kb][64 lanes][16]
-  std::vector<int32_t> addrs;     // [kb][64 lanes]
+  std::vector<uint8_t> recs;      // [kb][kRecBytes]
   int32_t *d_perm = nullptr, *d_ntot = nullptr, *d_group_begin = nullptr, *d_kbr = nullptr;
-  int32_t *d_addrs = nullptr;
   MGroup *d_groups = nullptr;
   MUnit *d_units = nullptr;
-  uint8_t *d_masks = nullptr;
+  uint8_t *d_recs = nullptr;
 };
 struct MfmaTables {
   MfmaCfgTables cfg[kNumMfmaCfgs];
@@ -85,10 +91,9 @@ void free_mfma(MfmaTables *t) {
     (void)hipFree(c.d_ntot);
     (void)hipFree(c.d_group_begin);
     (void)hipFree(c.d_kbr);
-    (void)hipFree(c.d_addrs);
     (void)hipFree(c.d_groups);
     (void)hipFree(c.d_units);
-    (void)hipFree(c.d_masks);
+    (void)hipFree(c.d_recs);
   }
   delete t;
 }
@@ -96,15 +101,18 @@ void free_mfma(MfmaTables *t) {
 namespace {
 
 typedef int32_t v4i __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
+constexpr unsigned kWaitVm0 = 0x0f70;      // s_waitcnt vmcnt(0) (gfx9 encoding)
+constexpr int kBufWord3 = 0x00020000;      // raw 32-bit buffer descriptor word 3
 
 struct MfmaArgs {
   const uint8_t *x;
   int64_t in_stride, in_bstride, nsamp;
   int32_t ntw, ntt, bufbytes, pad0;
-  const int32_t *group_begin, *kbr, *perm, *ntot, *addrs;
+  const int32_t *group_begin, *kbr, *perm, *ntot;
   const MGroup *groups;
   const MUnit *units;
-  const v4i *masks;
+  const uint8_t *recs;
   int32_t *out;
   int64_t out_stride, out_bstride, nout;
 };
@@ -121,7 +129,10 @@ __device__ __forceinline__ void load_raw(const uint8_t *row, int64_t nsamp, int6
   const uintptr_t abs = (uintptr_t)(row + pos);
   *sh = (int)(abs & 3);
   const int64_t p0 = pos - *sh;   // row-relative position of the aligned first byte
-  const uint32_t *a = (const uint32_t *)(abs - *sh);
+  // a global (not flat) pointer: flat loads would also count against the LDS counter
+  // and force full LDS waits in the product loop while they are in flight
+  const __attribute__((address_space(1))) uint32_t *a =
+      (const __attribute__((address_space(1))) uint32_t *)(abs - *sh);
   if (p0 >= 0 && p0 + 24 <= nsamp) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) raw[k] = a[k];
@@ -158,8 +169,10 @@ __device__ __forceinline__ void store_task(unsigned char *buf, int32_t dst, int 
   }
 }
 
-template <int NWD, int NWT, int NT>
+// One workgroup per CU (its LDS), so NW / 4 waves per SIMD: registers up to 512 / that.
+template <int NWD, int NWT, int NT, int RING>
 __global__ void __launch_bounds__(64 * NWD * NWT)
+__attribute__((amdgpu_waves_per_eu(NWD * NWT / 4, NWD * NWT / 4)))
 k_dedisp_mfma(MfmaArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   constexpr int NW = NWD * NWT, TWV = 16 * NT, TW = NWT * TWV;
@@ -181,22 +194,21 @@ k_dedisp_mfma(MfmaArgs a) {
   for (int b = 0; b < NT; ++b) acc[b] = (v4i){0, 0, 0, 0};
 
   const int gb = ldc(a.group_begin, tw), ge = ldc(a.group_begin, tw + 1);
-  // masks and lane addresses of the K blocks of a group, loaded one group ahead
-  v4i mk[kMaxKb], mkn[kMaxKb];
-  int32_t ad[kMaxKb], adn[kMaxKb];
-  int nk = 0, nkn = 0;
-  auto load_kb = [&](int g) {
-    const int base = ldc(&a.groups[g].kb_base, 0);
-    const int k0 = ldc(a.kbr, (int64_t)base + wd), k1 = ldc(a.kbr, (int64_t)base + wd + 1);
-    nkn = k1 - k0;
-#pragma unroll
-    for (int i = 0; i < kMaxKb; ++i)
-      if (i < nkn) {
-        mkn[i] = a.masks[(int64_t)(k0 + i) * 64 + lane];
-        adn[i] = a.addrs[(int64_t)(k0 + i) * 64 + lane];
-      }
+  // copies the K-block records of group g into LDS (buffer-to-LDS loads, 16 bytes a
+  // lane; waited for with the window loads before the group's barrier)
+  auto stage_recs = [&](int g, unsigned char *buf) {
+    const int kf = ldc(&a.groups[g].kb_first, 0), nkb = ldc(&a.groups[g].nkb, 0);
+    const int ro = ldc(&a.groups[g].rec_off, 0);
+    const int nch = nkb * (kRecBytes / 16);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(a.recs + (int64_t)kf * kRecBytes), (short)0, nkb * kRecBytes, kBufWord3);
+    for (int c0 = 64 * wave; c0 < nch; c0 += 64 * NW) {
+      const int ch = c0 + lane;
+      if (ch < nch)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void *)(buf + ro + 16 * c0), 16, 16 * ch,
+                                                 0, 0, 0);
+    }
   };
-  load_kb(gb);
   // staging tasks: thread t takes quarter t % 4 of chunks t / 4, t / 4 + NW * 16, ...
   constexpr int NTHR = 64 * NW, TPT = kMaxTasks;
   uint32_t raw[TPT][6];
@@ -223,33 +235,53 @@ k_dedisp_mfma(MfmaArgs a) {
     for (int i = 0; i < TPT; ++i)
       if (i < ntask) store_task(buf, dst[i], h, rot[i], raw[i], sh[i]);
   };
+  stage_recs(gb, lds);
   fetch(gb);
   store(lds);
+  __builtin_amdgcn_s_waitcnt(kWaitVm0);
   __syncthreads();
   for (int g = gb; g < ge; ++g) {
     const int par = (g - gb) & 1;
-    nk = nkn;
-#pragma unroll
-    for (int i = 0; i < kMaxKb; ++i) {
-      mk[i] = mkn[i];
-      ad[i] = adn[i];
-    }
+    unsigned char *buf = lds + par * a.bufbytes;
     if (g + 1 < ge) {
-      load_kb(g + 1);
+      stage_recs(g + 1, lds + (par ^ 1) * a.bufbytes);
       fetch(g + 1);
     }
-    const unsigned char *buf = lds + par * a.bufbytes + 256 * NT * wt;
+    const int kbase = ldc(&a.groups[g].kb_base, 0), kf = ldc(&a.groups[g].kb_first, 0);
+    const int ro = ldc(&a.groups[g].rec_off, 0);
+    const int k0 = ldc(a.kbr, (int64_t)kbase + wd), k1 = ldc(a.kbr, (int64_t)kbase + wd + 1);
+    const unsigned char *wbuf = buf + 256 * NT * wt;
+    for (int kb = k0; kb < k1; ++kb) {
+      const unsigned char *rec = buf + ro + (kb - kf) * kRecBytes;
+      // 16 mask bytes of lane (trial row lane % 16, segment lane / 16): bit j -> byte j
+      const uint32_t m16 = *(const uint16_t *)(rec + 2 * lane);
+      v4i mk;
 #pragma unroll
-    for (int i = 0; i < kMaxKb; ++i) {
-      if (i >= nk) break;
-      const unsigned char *p = buf + ad[i];
+      for (int k = 0; k < 4; ++k) mk[k] = (int32_t)((((m16 >> (4 * k)) & 15u) * 0x204081u) & 0x01010101u);
+      // window bytes i .. i + 15 of output column lane % 16 of the lane's segment
+      const int32_t region = *(const int32_t *)(rec + 128 + 8 * (lane >> 4));
+      const int32_t i = *(const int32_t *)(rec + 132 + 8 * (lane >> 4)) + (lane & 15);
+      const unsigned char *p = wbuf + region + 256 * (i >> 4) + 16 * (i & 15);
+      // a ring of RING reads in flight: the read of block b + RING is issued as soon
+      // as block b's product has taken its operand
+      v4i f[RING];
+#pragma unroll
+      for (int b = 0; b < RING; ++b) f[b] = *(const v4i *)(p + 256 * b);
 #pragma unroll
       for (int b = 0; b < NT; ++b) {
-        const v4i d = *(const v4i *)(p + 256 * b);
-        acc[b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(mk[i], d, acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(mk, f[b % RING], acc[b], 0, 0, 0);
+        if (b + RING < NT) f[b % RING] = *(const v4i *)(p + 256 * (b + RING));
+      }
+      // keep that order: RING reads, then one product and one read at a time
+      __builtin_amdgcn_sched_group_barrier(0x100, RING, 0);
+#pragma unroll
+      for (int b = 0; b < NT; ++b) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        if (b + RING < NT) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
       }
     }
     if (g + 1 < ge) store(lds + (par ^ 1) * a.bufbytes);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
   }
   // C layout: lane l, element r holds trial row 4 (l / 16) + r, output l % 16
@@ -342,11 +374,15 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
       const int cbeg = c;
       std::vector<int> segw(NWD, 0);
       int nunits = 0;   // at most kMaxTasks quarter chunks per thread
-      while (c < C && (int64_t)used + (int64_t)kPhases * wst[c] <= kMfmaBufBytes &&
-             4 * (nunits + wst[c] / 16) <= kMaxTasks * 64 * NWD * cf.nwt) {
+      while (c < C && 4 * (nunits + wst[c] / 16) <= kMaxTasks * 64 * NWD * cf.nwt) {
         bool fits = true;
-        for (int w = 0; w < NWD; ++w) fits = fits && segw[w] + nseg[w * C + c] <= 4 * kMaxKb;
-        if (!fits) break;
+        int nrec = 0;   // K-block records with channel c added
+        for (int w = 0; w < NWD; ++w) {
+          fits = fits && segw[w] + nseg[w * C + c] <= 4 * kMaxKb;
+          nrec += (segw[w] + nseg[w * C + c] + 3) / 4;
+        }
+        if (!fits || (int64_t)used + (int64_t)kPhases * wst[c] + (int64_t)nrec * kRecBytes > kMfmaBufBytes)
+          break;
         for (int w = 0; w < NWD; ++w) segw[w] += nseg[w * C + c];
         used += kPhases * wst[c];
         nunits += wst[c] / 16;
@@ -366,40 +402,38 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
       gi.nunits = (int)out.units.size() - gi.unit_begin;
       if (4 * gi.nunits > kMaxTasks * 64 * NWD * cf.nwt) return false;
       gi.kb_base = (int)out.kbr.size();
+      gi.kb_first = (int)(out.recs.size() / kRecBytes);
+      gi.rec_off = off;
       for (int w = 0; w < NWD; ++w) {
-        out.kbr.push_back((int32_t)(out.addrs.size() / 64));
+        out.kbr.push_back((int32_t)(out.recs.size() / kRecBytes));
         // segments of this sub-tile in the group, four per K block
         std::vector<std::pair<int, int>> segs;
         for (int cc = cbeg; cc < c; ++cc)
           for (int s = 0; s < nseg[w * C + cc]; ++s) segs.push_back({cc, lo[w * C + cc] + 16 * s});
         for (size_t s0 = 0; s0 < segs.size(); s0 += 4) {
-          for (int lane = 0; lane < 64; ++lane) {
-            const int n = lane & 15, g = lane >> 4;
-            const size_t si = s0 + g;
-            uint8_t mk[16] = {};
-            int32_t ad = 0;
-            if (si < segs.size()) {
-              const int cc = segs[si].first, o = segs[si].second;
-              const int d = out.perm[(size_t)tw * DT + 16 * w + n];
-              if (d >= 0) {
-                const int st = p->start[(size_t)d * C + cc], nt = p->ntap[(size_t)d * C + cc];
-                for (int j = 0; j < 16; ++j) mk[j] = (o + j >= st && o + j < st + nt) ? 1 : 0;
-              }
-              const int rel = o - stlo[cc] + n;
-              ad = region[cc] + 256 * (rel >> 4) + 16 * (rel & 15);
-            } else {
-              // padding segment: zero masks, address of a valid window
-              const int cc = segs[s0].first, rel = segs[s0].second - stlo[cc] + n;
-              ad = region[cc] + 256 * (rel >> 4) + 16 * (rel & 15);
+          uint8_t rec[kRecBytes] = {};
+          for (int g = 0; g < 4; ++g) {
+            // padding segments: zero masks, a valid window
+            const size_t si = s0 + g < segs.size() ? s0 + g : s0;
+            const int cc = segs[si].first, o = segs[si].second;
+            const int32_t sg[2] = {region[cc], o - stlo[cc]};
+            std::memcpy(rec + 128 + 8 * g, sg, 8);
+            if (s0 + g >= segs.size()) continue;
+            for (int m = 0; m < 16; ++m) {
+              const int d = out.perm[(size_t)tw * DT + 16 * w + m];
+              if (d < 0) continue;
+              const int st = p->start[(size_t)d * C + cc], nt = p->ntap[(size_t)d * C + cc];
+              uint16_t bits = 0;
+              for (int j = 0; j < 16; ++j)
+                if (o + j >= st && o + j < st + nt) bits |= (uint16_t)(1u << j);
+              std::memcpy(rec + 2 * (16 * g + m), &bits, 2);
             }
-            // the mask rows go to lane (trial row n, segment g); the address to lane
-            // (output column n, segment g): both are lane = 16 g + n
-            out.masks.insert(out.masks.end(), mk, mk + 16);
-            out.addrs.push_back(ad);
           }
+          out.recs.insert(out.recs.end(), rec, rec + kRecBytes);
         }
       }
-      out.kbr.push_back((int32_t)(out.addrs.size() / 64));
+      out.kbr.push_back((int32_t)(out.recs.size() / kRecBytes));
+      gi.nkb = (int)(out.recs.size() / kRecBytes) - gi.kb_first;
       out.groups.push_back(gi);
       if (c == cbeg) return false;   // one channel does not fit
     }
@@ -421,22 +455,22 @@ static hipError_t allow_lds_mfma(const void *fn, bool *done, std::mutex *mu, int
   return e;
 }
 
-template <int NWD, int NWT, int NT>
+template <int NWD, int NWT, int NT, int RING>
 static hipError_t launch_mfma_cfg(const MfmaArgs &a, int nbatch, hipStream_t s) {
   static bool done[64] = {};
   static std::mutex mu;
-  hipError_t e =
-      allow_lds_mfma((const void *)k_dedisp_mfma<NWD, NWT, NT>, done, &mu, 2 * kMfmaBufBytes);
+  hipError_t e = allow_lds_mfma((const void *)k_dedisp_mfma<NWD, NWT, NT, RING>, done, &mu,
+                                2 * kMfmaBufBytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_dedisp_mfma<NWD, NWT, NT>), dim3(a.ntw * a.ntt, nbatch),
+  hipLaunchKernelGGL((k_dedisp_mfma<NWD, NWT, NT, RING>), dim3(a.ntw * a.ntt, nbatch),
                      dim3(64 * NWD * NWT), 2 * a.bufbytes, s, a);
   return hipGetLastError();
 }
 
 static hipError_t launch_mfma(int ci, const MfmaArgs &a, int nbatch, hipStream_t s) {
   switch (ci) {
-#define DD_MFMA_CASE(i, x, y, z) \
-  case i: return launch_mfma_cfg<x, y, z>(a, nbatch, s);
+#define DD_MFMA_CASE(i, x, y, z, r) \
+  case i: return launch_mfma_cfg<x, y, z, r>(a, nbatch, s);
     DD_MFMA_CONFIGS(DD_MFMA_CASE)
 #undef DD_MFMA_CASE
     default: return hipErrorInvalidValue;
@@ -448,7 +482,7 @@ dedisp_status run_dedisperse_u8_mfma(dedisp_plan p, const uint8_t *x, int64_t ns
                                      int32_t *out, int64_t out_stride, int64_t out_bstride,
                                      int64_t nout, hipStream_t s, KernelTimer *kt) {
   if (p->wmode != DEDISP_W_UNIT || nbatch > 65535) return DEDISP_ERR_UNSUPPORTED;
-  // the 16-block shape (512 outputs per workgroup), else the 8-block one
+  // 128 trials x 512 outputs per workgroup, else 256 trials x 256 outputs
   int ci = -1;
   MfmaCfgTables *cfg = nullptr;
   {
@@ -466,10 +500,9 @@ dedisp_status run_dedisperse_u8_mfma(dedisp_plan p, const uint8_t *x, int64_t ns
           DD_HIP(upload(&c.d_ntot, c.ntot));
           DD_HIP(upload(&c.d_group_begin, c.group_begin));
           DD_HIP(upload(&c.d_kbr, c.kbr));
-          DD_HIP(upload(&c.d_addrs, c.addrs));
           DD_HIP(upload(&c.d_groups, c.groups));
           DD_HIP(upload(&c.d_units, c.units));
-          DD_HIP(upload(&c.d_masks, c.masks));
+          DD_HIP(upload(&c.d_recs, c.recs));
         }
       }
       if (c.ok) {
@@ -493,10 +526,9 @@ dedisp_status run_dedisperse_u8_mfma(dedisp_plan p, const uint8_t *x, int64_t ns
   a.kbr = cfg->d_kbr;
   a.perm = cfg->d_perm;
   a.ntot = cfg->d_ntot;
-  a.addrs = cfg->d_addrs;
   a.groups = cfg->d_groups;
   a.units = cfg->d_units;
-  a.masks = (const v4i *)cfg->d_masks;
+  a.recs = cfg->d_recs;
   a.out = out;
   a.out_stride = out_stride;
   a.out_bstride = out_bstride;
