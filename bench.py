@@ -23,13 +23,20 @@ if ROOT not in sys.path:
 
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9   # int32 vector lane-ops/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
 PACKED_PEAK_OPS = 2 * VALU_PEAK_OPS    # two 16-bit adds per lane-op (packed uint16 adds)
-KERNEL_SRC = os.path.join(ROOT, "paper_1301_3968_amd", "csrc", "kernels_search.hip")
+MFMA_I8_PEAK_OPS = 5.0e15              # dense int8 matrix-core ops/s (a multiply-add is 2 ops)
+NUM_PACKED_SHAPES = 8                  # search shapes 0-7: packed-add kernel; 8 on: matrix cores
+# sources of the search kernels (both kinds and their shared detection stage)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1301_3968_amd", "csrc", f)
+               for f in ("kernels_search.hip", "kernels_mfma.hip", "boxcar_row.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_search_336ch_65536s_1024dm.json")
 
 
 def _src_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def _traffic(tile: int):
@@ -150,18 +157,31 @@ def main() -> int:
     sums = float(D) * C * nout
     value = sums / ((t1 - t0) / K)
 
-    # Algorithmic integer ops of one launch of the dominant kernel: one add per
-    # DM-channel-sample sum, plus one subtract and one max per boxcar window
-    # evaluation when the detection is fused into that kernel.
+    # Algorithmic integer ops of one launch of the dominant kernel.  Packed-add
+    # kernel: one add per DM-channel-sample sum (of precomputed window sums), plus
+    # one subtract and one max per boxcar window evaluation when the detection is
+    # fused into that kernel.  Matrix-core kernel: the plain definition of the sum,
+    # one int8 multiply-add (2 ops) per sample term, sum over (d, c) of ntap[d, c]
+    # terms per output.
     fused = os.environ.get("DEDISP_BENCH_UNFUSED") is None and _fused(plan)
-    ops = sums + (2.0 * D * nout * nw if fused else 0.0)
-    achieved = ops / (kern_ms * 1e-3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                "unit": "Tops/s", "frac": achieved / VALU_PEAK_OPS,
-                "traffic": _traffic(tile) if fused else None,
-                "kernel_ms": kern_ms, "ops_per_launch": ops,
-                "peak_packed_u16": PACKED_PEAK_OPS / 1e12,
-                "frac_packed_u16": achieved / PACKED_PEAK_OPS}
+    valu_ops = sums + (2.0 * D * nout * nw if fused else 0.0)
+    kern_s = kern_ms * 1e-3
+    if fused and tile >= NUM_PACKED_SHAPES:
+        mma_ops = 2.0 * nout * float(np.sum(ntap, dtype=np.int64))
+        roofline = {"bound": "mfma", "achieved": mma_ops / kern_s / 1e12,
+                    "peak": MFMA_I8_PEAK_OPS / 1e12, "unit": "TOP/s (int8)",
+                    "frac": mma_ops / kern_s / MFMA_I8_PEAK_OPS,
+                    "traffic": _traffic(tile), "kernel_ms": kern_ms, "ops_per_launch": mma_ops,
+                    "sums_per_launch": sums,
+                    "frac_valu_equivalent": valu_ops / kern_s / VALU_PEAK_OPS}
+    else:
+        roofline = {"bound": "alu", "achieved": valu_ops / kern_s / 1e12,
+                    "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
+                    "frac": valu_ops / kern_s / VALU_PEAK_OPS,
+                    "traffic": _traffic(tile) if fused else None,
+                    "kernel_ms": kern_ms, "ops_per_launch": valu_ops,
+                    "peak_packed_u16": PACKED_PEAK_OPS / 1e12,
+                    "frac_packed_u16": valu_ops / kern_s / PACKED_PEAK_OPS}
     line = {
         "metric": "DM-trial*channel*sample sums/s", "value": value, "unit": "sums/s",
         "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": ms_step,

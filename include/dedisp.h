@@ -233,10 +233,13 @@ dedisp_status dedisp_autotune(dedisp_plan plan, const void *d_in, int64_t nsamp,
                               const int32_t *widths, int32_t nw, const double *d_chan_mean,
                               const double *d_chan_sigma, void *d_work, size_t work_bytes,
                               void *stream, int32_t *chosen);
-/* Force a tile configuration of the fused uint8 search kernel (index into its
- * candidate list), -1 for the default, or -2 to always use the general kernels:
- * the unfused search (dedisperse into a temporary, then detect), the untiled fp32
- * dedispersion and the untiled per-tap adjoint. */
+/* Force a shape of the fused uint8 search (index into its candidate list: the
+ * shapes of the packed-add kernel, then those of the int8 matrix-core kernel; the
+ * autotuner times them all), -1 for the default (the first matrix-core shape, or
+ * packed-add shape 0 when the plan does not fit it), or -2 to always use the
+ * general kernels: the unfused search (dedisperse into a temporary, then detect),
+ * the prefix-difference uint8 dedispersion, the untiled fp32 dedispersion and the
+ * untiled per-tap adjoint. */
 dedisp_status dedisp_set_tile(dedisp_plan plan, int32_t tile);
 /* Tile configuration used by the last dedisp_search on this plan (-1: unfused path). */
 dedisp_status dedisp_last_search_tile(dedisp_plan plan, int32_t *tile);

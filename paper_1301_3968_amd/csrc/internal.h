@@ -179,6 +179,15 @@ dedisp_status run_dedisperse_u8_mfma(dedisp_plan p, const uint8_t *x, int64_t ns
                                      int64_t in_stride, int64_t in_bstride, int32_t nbatch,
                                      int32_t *out, int64_t out_stride, int64_t out_bstride,
                                      int64_t nout, hipStream_t s, KernelTimer *kt);
+// Fused search on the matrix-core kernel, shape k of mfma_search_count() (noise
+// tables, the tile kernel, the reduction over time tiles; kernels_mfma.hip).
+// Returns DEDISP_ERR_UNSUPPORTED (launching nothing) when the plan does not fit.
+int mfma_search_count();
+size_t mfma_search_work_bytes(const dedisp_plan_s *p, int32_t nw, int64_t nout);
+dedisp_status run_search_mfma(dedisp_plan p, int k, const uint8_t *x, int64_t nsamp,
+                              int64_t in_stride, int64_t nout, const WidthList &wl,
+                              const double *mu, const double *sigma, double *snr, int32_t *t,
+                              int32_t *w, void *work, hipStream_t s);
 // zbar[b][c][tau] = sum_d g[b][d][tau - start[d][c]] for tau in [0, nz) on the same
 // tiled kernel; DEDISP_ERR_UNSUPPORTED (launching nothing) when it does not fit.
 dedisp_status run_adjoint_z_tiled(dedisp_plan p, const float *g, int64_t nout, int64_t gstride,

@@ -31,6 +31,7 @@
 #include <numeric>
 #include <vector>
 
+#include "boxcar_row.h"
 #include "internal.h"
 
 namespace dd {
@@ -51,7 +52,9 @@ constexpr int kPhases = 16;                 // byte-shifted copies of each stage
 constexpr int kMfmaBufBytes = 80 * 1024;    // LDS per staging buffer (two per workgroup)
 constexpr int kMaxKb = 8;                   // K blocks of one wave in one channel group
 constexpr int kRecBytes = 160;              // K-block record: 64 x u16 masks + 4 x (region, rel)
-constexpr int kMaxTasks = 3;                // staging tasks (quarter chunks) per thread
+// Staging tasks (quarter chunks) per thread: a buffer holds at most kMfmaBufBytes / 256
+// chunks of 16 copies, 4 tasks each.
+constexpr int max_tasks(int nw) { return (4 * (kMfmaBufBytes / 256) + 64 * nw - 1) / (64 * nw); }
 
 struct MGroup {
   int32_t unit_begin, nunits;   // staging units (16 window bytes of one channel each)
@@ -169,26 +172,32 @@ __device__ __forceinline__ void store_task(unsigned char *buf, int32_t dst, int 
   }
 }
 
-// One workgroup per CU (its LDS), so NW / 4 waves per SIMD: registers up to 512 / that.
-template <int NWD, int NWT, int NT, int RING>
-__global__ void __launch_bounds__(64 * NWD * NWT)
-__attribute__((amdgpu_waves_per_eu(NWD * NWT / 4, NWD * NWT / 4)))
-k_dedisp_mfma(MfmaArgs a) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  constexpr int NW = NWD * NWT, TWV = 16 * NT, TW = NWT * TWV;
-  // XCD-aware tile order (blocks b = x mod 8 run on XCD x): contiguous runs of tiles
-  const int nb = a.ntw * a.ntt;
+// XCD-aware tile order (blocks b = x mod 8 run on XCD x): XCD x takes a contiguous
+// run of tiles in time-major order, so the DM tiles of one time tile share its L2.
+__device__ __forceinline__ void tile_of_block(int ntw, int ntt, int *tt, int *tw) {
+  const int nb = ntw * ntt;
   const int bi = blockIdx.x;
   const int xcd = bi & 7, kk = bi >> 3, q = nb >> 3, rem = nb & 7;
   const int L = xcd * q + min(xcd, rem) + kk;
-  const int tt = L / a.ntw, tw = L - tt * a.ntw;
-  const int bb = blockIdx.y;
+  *tt = L / ntw;
+  *tw = L - *tt * ntw;
+}
+
+template <int NT>
+struct TileAcc {
+  v4i v[NT];
+};
+
+// The products of DM tile tw over outputs T0 .. T0 + NWT * 16 NT - 1 (wave (wd, wt):
+// trials 16 wd .. 16 wd + 15 of the tile, outputs T0 + 16 NT wt + ...).  Ends with a
+// workgroup barrier, after which the LDS is free.
+template <int NWD, int NWT, int NT, int RING>
+__device__ __forceinline__ TileAcc<NT> mfma_tile(const MfmaArgs &a, int tw, int64_t T0,
+                                                 const uint8_t *xb, unsigned char *lds) {
+  constexpr int NW = NWD * NWT;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wd = wave % NWD, wt = wave / NWD;
-  const int64_t T0 = (int64_t)tt * TW;
-  const uint8_t *xb = a.x + (int64_t)bb * a.in_bstride;
-
   v4i acc[NT];
 #pragma unroll
   for (int b = 0; b < NT; ++b) acc[b] = (v4i){0, 0, 0, 0};
@@ -210,7 +219,7 @@ k_dedisp_mfma(MfmaArgs a) {
     }
   };
   // staging tasks: thread t takes quarter t % 4 of chunks t / 4, t / 4 + NW * 16, ...
-  constexpr int NTHR = 64 * NW, TPT = kMaxTasks;
+  constexpr int NTHR = 64 * NW, TPT = max_tasks(NW);
   uint32_t raw[TPT][6];
   int sh[TPT], dst[TPT], rot[TPT];
   int ntask = 0;
@@ -284,6 +293,28 @@ k_dedisp_mfma(MfmaArgs a) {
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
   }
+  TileAcc<NT> r;
+#pragma unroll
+  for (int b = 0; b < NT; ++b) r.v[b] = acc[b];
+  return r;
+}
+
+// One workgroup per CU (its LDS), so NW / 4 waves per SIMD: registers up to 512 / that.
+template <int NWD, int NWT, int NT, int RING>
+__global__ void __launch_bounds__(64 * NWD * NWT)
+__attribute__((amdgpu_waves_per_eu(NWD * NWT / 4, NWD * NWT / 4)))
+k_dedisp_mfma(MfmaArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  constexpr int TWV = 16 * NT, TW = NWT * TWV;
+  int tt, tw;
+  tile_of_block(a.ntw, a.ntt, &tt, &tw);
+  const int bb = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wd = wave % NWD, wt = wave / NWD;
+  const int64_t T0 = (int64_t)tt * TW;
+  const TileAcc<NT> tacc = mfma_tile<NWD, NWT, NT, RING>(a, tw, T0, a.x + (int64_t)bb * a.in_bstride, lds);
+  const v4i *acc = tacc.v;
   // C layout: lane l, element r holds trial row 4 (l / 16) + r, output l % 16
   int32_t *ob = a.out + (int64_t)bb * a.out_bstride;
   const int n = lane & 15, g4 = lane >> 4;
@@ -298,6 +329,71 @@ k_dedisp_mfma(MfmaArgs a) {
       const int64_t t = T0 + (int64_t)TWV * wt + 16 * b + n;
       if (t < a.nout) ob[(int64_t)d * a.out_stride + t] = acc[b][r] + corr;
     }
+  }
+}
+
+struct MfmaSearchArgs {
+  MfmaArgs m;             // x, tables, ntw, ntt (out and batch strides unused)
+  const double *M, *S;    // noise tables [ndm][nw]
+  int32_t nw;
+  uint32_t wmask;         // bit W - 1 for every listed width W <= 32
+  CandRec *part;          // [ndm][ntt]
+};
+
+// Time-tile step of the search: the tile's 64 SP outputs less a halo of >= 31 outputs,
+// in whole lanes of SP starts (as the boxcar stage needs).
+constexpr int search_step(int sp) { return 64 * sp - ((32 + sp - 1) / sp) * sp; }
+
+// Fused search: the products of one tile (outputs T0 .. T0 + TW - 1, T0 = tt * TT),
+// then the boxcar search of every trial of the tile over starts T0 .. T0 + TT - 1.
+// The series go through LDS in two passes (the trials of accumulator rows 0-1, then
+// 2-3, of every wave), as rows of TW + 32 ints; each wave searches whole rows.
+template <int NWD, int NWT, int NT, int RING>
+__global__ void __launch_bounds__(64 * NWD * NWT)
+__attribute__((amdgpu_waves_per_eu(NWD * NWT / 4, NWD * NWT / 4)))
+k_search_mfma(MfmaSearchArgs sa) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  constexpr int NW = NWD * NWT, TWV = 16 * NT, TW = NWT * TWV, SP = TW / 64;
+  constexpr int TT = search_step(SP), YROW = TW + kHalo + 4;
+  constexpr int ROWS = 8 * NWD;            // rows of one pass: 8 trials per DM sub-tile
+  static_assert(TW % 64 == 0 && TT % SP == 0 && TW - TT >= 31, "search tile");
+  static_assert(ROWS % NW == 0, "whole rows per wave");
+  static_assert(ROWS * YROW * 4 <= 2 * kMfmaBufBytes, "rows of one pass fit the LDS");
+  const MfmaArgs &a = sa.m;
+  int tt, tw;
+  tile_of_block(a.ntw, a.ntt, &tt, &tw);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wd = wave % NWD, wt = wave / NWD;
+  const int64_t T0 = (int64_t)tt * TT;
+  const TileAcc<NT> tacc = mfma_tile<NWD, NWT, NT, RING>(a, tw, T0, a.x, lds);
+  const v4i *acc = tacc.v;
+  int *Y = (int *)lds;
+  const int n = lane & 15, g4 = lane >> 4;
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    // lanes holding accumulator rows 2 pass, 2 pass + 1 write their trials' outputs
+    if ((g4 >> 1) == pass) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int d = a.perm[tw * 16 * NWD + 16 * wd + 4 * g4 + r];
+        const int32_t corr = d >= 0 ? 128 * a.ntot[d] : 0;
+        int *row = Y + (8 * wd + 4 * (g4 & 1) + r) * YROW + TWV * wt + n;
+#pragma unroll
+        for (int b = 0; b < NT; ++b) row[16 * b] = acc[b][r] + corr;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ROWS / NW; ++k) {
+      const int rw = wave * (ROWS / NW) + k;
+      const int sw = rw >> 3, j = rw & 7;   // DM sub-tile, trial row within the pass
+      const int dg = a.perm[tw * 16 * NWD + 16 * sw + 4 * (2 * pass + (j >> 2)) + (j & 3)];
+      const CandRec rec =
+          boxcar_row<SP>(Y + rw * YROW, lane, T0, TT, a.nout, dg, sa.wmask, sa.nw, sa.M, sa.S);
+      if (dg >= 0 && lane == 0) sa.part[(int64_t)dg * a.ntt + tt] = rec;
+    }
+    __syncthreads();
   }
 }
 
@@ -373,8 +469,8 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
       int used = 0;
       const int cbeg = c;
       std::vector<int> segw(NWD, 0);
-      int nunits = 0;   // at most kMaxTasks quarter chunks per thread
-      while (c < C && 4 * (nunits + wst[c] / 16) <= kMaxTasks * 64 * NWD * cf.nwt) {
+      int nunits = 0;   // at most max_tasks quarter chunks per thread
+      while (c < C && 4 * (nunits + wst[c] / 16) <= max_tasks(NWD * cf.nwt) * 64 * NWD * cf.nwt) {
         bool fits = true;
         int nrec = 0;   // K-block records with channel c added
         for (int w = 0; w < NWD; ++w) {
@@ -400,7 +496,7 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
         off += kPhases * wst[cc];
       }
       gi.nunits = (int)out.units.size() - gi.unit_begin;
-      if (4 * gi.nunits > kMaxTasks * 64 * NWD * cf.nwt) return false;
+      if (4 * gi.nunits > max_tasks(NWD * cf.nwt) * 64 * NWD * cf.nwt) return false;
       gi.kb_base = (int)out.kbr.size();
       gi.kb_first = (int)(out.recs.size() / kRecBytes);
       gi.rec_off = off;
@@ -477,6 +573,50 @@ static hipError_t launch_mfma(int ci, const MfmaArgs &a, int nbatch, hipStream_t
   }
 }
 
+// Tables of configuration k, built and uploaded on first use (nullptr if the plan
+// does not fit it).  Caller holds p->mu.
+static dedisp_status ensure_mfma(dedisp_plan p, int k, MfmaCfgTables **out) {
+  *out = nullptr;
+  if (!p->mfma) {
+    p->mfma = new (std::nothrow) MfmaTables;
+    if (!p->mfma) return fail(DEDISP_ERR_OOM, "host allocation failed");
+  }
+  MfmaCfgTables &c = p->mfma->cfg[k];
+  if (!p->mfma->tried[k]) {
+    p->mfma->tried[k] = true;
+    if (build_mfma_cfg(p, k, c)) {
+      DD_HIP(upload(&c.d_perm, c.perm));
+      DD_HIP(upload(&c.d_ntot, c.ntot));
+      DD_HIP(upload(&c.d_group_begin, c.group_begin));
+      DD_HIP(upload(&c.d_kbr, c.kbr));
+      DD_HIP(upload(&c.d_groups, c.groups));
+      DD_HIP(upload(&c.d_units, c.units));
+      DD_HIP(upload(&c.d_recs, c.recs));
+    }
+  }
+  if (c.ok) *out = &c;
+  return DEDISP_OK;
+}
+
+static void fill_args(dedisp_plan p, const MfmaCfgTables &c, const uint8_t *x, int64_t nsamp,
+                      int64_t in_stride, int64_t nout, MfmaArgs &a) {
+  a = MfmaArgs{};
+  a.x = x;
+  a.in_stride = in_stride;
+  a.nsamp = nsamp;
+  a.ntw = c.ntw;
+  a.bufbytes = kMfmaBufBytes;
+  a.group_begin = c.d_group_begin;
+  a.kbr = c.d_kbr;
+  a.perm = c.d_perm;
+  a.ntot = c.d_ntot;
+  a.groups = c.d_groups;
+  a.units = c.d_units;
+  a.recs = c.d_recs;
+  a.nout = nout;
+  (void)p;
+}
+
 dedisp_status run_dedisperse_u8_mfma(dedisp_plan p, const uint8_t *x, int64_t nsamp,
                                      int64_t in_stride, int64_t in_bstride, int32_t nbatch,
                                      int32_t *out, int64_t out_stride, int64_t out_bstride,
@@ -487,56 +627,106 @@ dedisp_status run_dedisperse_u8_mfma(dedisp_plan p, const uint8_t *x, int64_t ns
   MfmaCfgTables *cfg = nullptr;
   {
     std::lock_guard<std::mutex> lk(p->mu);
-    if (!p->mfma) {
-      p->mfma = new (std::nothrow) MfmaTables;
-      if (!p->mfma) return fail(DEDISP_ERR_OOM, "host allocation failed");
-    }
     for (int k = 0; k < kNumMfmaCfgs && !cfg; ++k) {
-      MfmaCfgTables &c = p->mfma->cfg[k];
-      if (!p->mfma->tried[k]) {
-        p->mfma->tried[k] = true;
-        if (build_mfma_cfg(p, k, c)) {
-          DD_HIP(upload(&c.d_perm, c.perm));
-          DD_HIP(upload(&c.d_ntot, c.ntot));
-          DD_HIP(upload(&c.d_group_begin, c.group_begin));
-          DD_HIP(upload(&c.d_kbr, c.kbr));
-          DD_HIP(upload(&c.d_groups, c.groups));
-          DD_HIP(upload(&c.d_units, c.units));
-          DD_HIP(upload(&c.d_recs, c.recs));
-        }
-      }
-      if (c.ok) {
-        cfg = &c;
-        ci = k;
-      }
+      dedisp_status st = ensure_mfma(p, k, &cfg);
+      if (st != DEDISP_OK) return st;
+      ci = k;
     }
   }
   if (!cfg) return DEDISP_ERR_UNSUPPORTED;
   const int64_t ntt = (nout + cfg->tw - 1) / cfg->tw;
   if (ntt * cfg->ntw > INT32_MAX / 2) return DEDISP_ERR_UNSUPPORTED;
-  MfmaArgs a{};
-  a.x = x;
-  a.in_stride = in_stride;
+  MfmaArgs a;
+  fill_args(p, *cfg, x, nsamp, in_stride, nout, a);
   a.in_bstride = in_bstride;
-  a.nsamp = nsamp;
-  a.ntw = cfg->ntw;
   a.ntt = (int32_t)ntt;
-  a.bufbytes = kMfmaBufBytes;
-  a.group_begin = cfg->d_group_begin;
-  a.kbr = cfg->d_kbr;
-  a.perm = cfg->d_perm;
-  a.ntot = cfg->d_ntot;
-  a.groups = cfg->d_groups;
-  a.units = cfg->d_units;
-  a.recs = cfg->d_recs;
   a.out = out;
   a.out_stride = out_stride;
   a.out_bstride = out_bstride;
-  a.nout = nout;
   hipError_t e = kt ? kt->begin() : hipSuccess;
   if (e == hipSuccess) e = launch_mfma(ci, a, nbatch, s);
   if (e == hipSuccess && kt) e = kt->end();
   if (e != hipSuccess) return hip_fail(e, "mfma dedisperse launch");
+  return DEDISP_OK;
+}
+
+// ---- fused search ----------------------------------------------------------------
+struct MfmaSearchLayout {
+  int64_t ntt = 0;
+  size_t off_part = 0, total = 0;
+};
+
+static MfmaSearchLayout search_layout(const dedisp_plan_s *p, int k, int32_t nw, int64_t nout) {
+  const MfmaCfg cf = kMfmaCfgs[k];
+  const int tw = cf.nwt * 16 * cf.nt, tstep = search_step(tw / 64);
+  MfmaSearchLayout L;
+  L.ntt = (nout + tstep - 1) / tstep;
+  L.off_part = (2 * sizeof(double) * (size_t)p->ndm * nw + 255) & ~(size_t)255;
+  L.total = L.off_part + ((sizeof(CandRec) * (size_t)p->ndm * L.ntt + 255) & ~(size_t)255);
+  return L;
+}
+
+size_t mfma_search_work_bytes(const dedisp_plan_s *p, int32_t nw, int64_t nout) {
+  size_t b = 0;
+  for (int k = 0; k < kNumMfmaCfgs; ++k) b = std::max(b, search_layout(p, k, nw, nout).total);
+  return b;
+}
+
+int mfma_search_count() { return kNumMfmaCfgs; }
+
+template <int NWD, int NWT, int NT, int RING>
+static hipError_t launch_search_cfg(const MfmaSearchArgs &sa, hipStream_t s) {
+  static bool done[64] = {};
+  static std::mutex mu;
+  hipError_t e = allow_lds_mfma((const void *)k_search_mfma<NWD, NWT, NT, RING>, done, &mu,
+                                2 * kMfmaBufBytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_search_mfma<NWD, NWT, NT, RING>), dim3(sa.m.ntw * sa.m.ntt),
+                     dim3(64 * NWD * NWT), 2 * sa.m.bufbytes, s, sa);
+  return hipGetLastError();
+}
+
+static hipError_t launch_search_mfma(int k, const MfmaSearchArgs &sa, hipStream_t s) {
+  switch (k) {
+#define DD_MFMA_SEARCH_CASE(i, x, y, z, r) \
+  case i: return launch_search_cfg<x, y, z, r>(sa, s);
+    DD_MFMA_CONFIGS(DD_MFMA_SEARCH_CASE)
+#undef DD_MFMA_SEARCH_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+dedisp_status run_search_mfma(dedisp_plan p, int k, const uint8_t *x, int64_t nsamp,
+                              int64_t in_stride, int64_t nout, const WidthList &wl,
+                              const double *mu, const double *sigma, double *snr, int32_t *t,
+                              int32_t *w, void *work, hipStream_t s) {
+  if (k < 0 || k >= kNumMfmaCfgs || p->wmode != DEDISP_W_UNIT || wl.w[wl.n - 1] > 32)
+    return DEDISP_ERR_UNSUPPORTED;
+  MfmaCfgTables *cfg = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    dedisp_status st = ensure_mfma(p, k, &cfg);
+    if (st != DEDISP_OK) return st;
+  }
+  if (!cfg) return DEDISP_ERR_UNSUPPORTED;
+  const MfmaSearchLayout L = search_layout(p, k, wl.n, nout);
+  if (L.ntt * cfg->ntw > INT32_MAX / 2) return DEDISP_ERR_UNSUPPORTED;
+  MfmaSearchArgs sa{};
+  fill_args(p, *cfg, x, nsamp, in_stride, nout, sa.m);
+  sa.m.ntt = (int32_t)L.ntt;
+  double *M = (double *)work;
+  sa.M = M;
+  sa.S = M + (size_t)p->ndm * wl.n;
+  sa.nw = wl.n;
+  sa.wmask = 0;
+  for (int i = 0; i < wl.n; ++i) sa.wmask |= 1u << (wl.w[i] - 1);
+  sa.part = (CandRec *)((char *)work + L.off_part);
+  DD_HIP(launch_norm(p, wl, mu, sigma, M, (double *)sa.S, s));
+  KernelTimer kt(p, s);
+  DD_HIP(kt.begin());
+  DD_HIP(launch_search_mfma(k, sa, s));
+  DD_HIP(kt.end());
+  DD_HIP(launch_reduce(p->ndm, (int32_t)L.ntt, sa.part, snr, t, w, s));
   return DEDISP_OK;
 }
 

@@ -31,6 +31,7 @@
 #include <numeric>
 #include <vector>
 
+#include "boxcar_row.h"
 #include "internal.h"
 
 namespace dd {
@@ -60,7 +61,6 @@ static const TileCfg kCfgs[] = {DD_TILE_CONFIGS(DD_CFG_ENTRY)};
 #undef DD_CFG_ENTRY
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 constexpr int kDefaultCfg = 0;
-constexpr int kHalo = 32;                 // boxcar widths up to 32
 // Time-tile step: TY minus a halo of at least 31 outputs, rounded so that every
 // lane (SP = 2 * r2 consecutive starts) owns either all or none of its starts.
 constexpr int tile_step(int r2) { return 128 * r2 - ((32 + 2 * r2 - 1) / (2 * r2)) * (2 * r2); }
@@ -199,28 +199,6 @@ struct SearchArgs {
   int8_t widx[33];          // W -> index into the width list, -1 if absent
   void *part;               // Cand[ndm][ntt]
 };
-
-struct CandRec {
-  double snr;
-  int32_t t;
-  int32_t w;
-};
-
-// Maximum over the 64 lanes of a wave (uniform result): DPP row shifts reduce each
-// row of 16 lanes into its lane 15, two row broadcasts fold the rows into lane 63.
-__device__ __forceinline__ int wave_max_i32(int v) {
-  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x111, 0xf, 0xf, false));   // row_shr:1
-  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x112, 0xf, 0xf, false));   // row_shr:2
-  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x114, 0xf, 0xf, false));   // row_shr:4
-  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x118, 0xf, 0xf, false));   // row_shr:8
-  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x142, 0xa, 0xf, false));   // row_bcast:15
-  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x143, 0xc, 0xf, false));   // row_bcast:31
-  return __builtin_amdgcn_readlane(v, 63);
-}
-
-__device__ __forceinline__ int bitrev5(int v) {
-  return ((v & 1) << 4) | ((v & 2) << 2) | (v & 4) | ((v & 8) >> 2) | ((v & 16) >> 4);
-}
 
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -401,136 +379,14 @@ __device__ __forceinline__ void search_tile(Args &a, const int tt, const int td,
   // group loop ended with one, so the window buffers are free).
   int *Yw = (int *)lds + wave * (YROW + 32);
   CandRec *part = (CandRec *)a.part;
-  // Only the tile holding the end of the series sees outputs past the last valid
-  // one.  Elsewhere every prefix entry is a real output, except the zero halo past
-  // TY: windows of lanes whose starts belong to the next tile may run into it and
-  // come out short, never larger than the same window in the tile that owns the
-  // start, which finds it exactly; so they cannot win falsely.
-  const bool tail = t0 + TY + kHalo > a.nout;
 #pragma unroll
   for (int j = 0; j < DPW; ++j) {
     const int dg = a.perm[td * DT + wave * DPW + j];
 #pragma unroll
     for (int r = 0; r < R2; ++r)
       *(int2 *)(Yw + 2 * lane + 128 * r) = make_int2(acc[j][2 * r], acc[j][2 * r + 1]);
-    if (lane < kHalo) Yw[TY + lane] = 0;
-    // LDS operations of one wave complete in order: the reads below see the writes
-    __builtin_amdgcn_wave_barrier();
-    // Window sums come from the running prefix qv[k] = y[0] + .. + y[k-1] of this
-    // lane's SP + 32 outputs.  In the tail tile, prefix entries past the last
-    // valid output (all of them for lanes without starts in this tile) are pushed
-    // down so that every window that is not a valid (start, width) comes out
-    // negative; windows of unit-weight uint8 sums are otherwise >= 0.
-    const int *yl = Yw + lane * SP;
-    int lim = SP + kHalo;
-    if (tail) {
-      const int64_t room = a.nout - (t0 + lane * SP);
-      lim = (lane * SP < TT) ? (int)(room < SP + kHalo ? room : SP + kHalo) : -1;
-    }
-    int qv[SP + kHalo + 1];
-    qv[0] = 0;
-#pragma unroll
-    for (int k = 0; k < SP + kHalo; ++k) qv[k + 1] = qv[k] + yl[k];
-    __builtin_amdgcn_wave_barrier();
-    if (tail) {
-#pragma unroll
-      for (int k = 0; k <= SP + kHalo; ++k)
-        if (k > lim) qv[k] = (INT_MIN / 4) - (k - lim);
-    }
-    // Per width: the lane maximum over its starts (made for all 32 widths; the
-    // widths not searched are dropped at the S/N step), reduced across the wave
-    // by a transposed butterfly: each level
-    // halves the registers and doubles the lanes each register is reduced over.
-    // Widths are taken in ascending pairs (2r + 1, 2r + 2), so each prefix entry
-    // is needed only for a short run of widths, and the first level (lanes l,
-    // l ^ 32: the lower half keeps width 2r + 1, the upper half 2r + 2) runs as
-    // the maxima are made.
-    int mw[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      int m2[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int w = 2 * r + h + 1;
-        int m = qv[w] - qv[0];
-#pragma unroll
-        for (int i = 1; i < SP; ++i) m = max(m, qv[i + w] - qv[i]);
-        m2[h] = m;
-      }
-      const auto p = __builtin_amdgcn_permlane32_swap(m2[0], m2[1], false, false);
-      mw[r] = max((int)p[0], (int)p[1]);
-    }
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {    // lanes l, l ^ 16: rows 0, 2 keep r, rows 1, 3 r + 8
-      const auto p = __builtin_amdgcn_permlane16_swap(mw[r], mw[r + 8], false, false);
-      mw[r] = max((int)p[0], (int)p[1]);
-    }
-    const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {    // lanes l, l ^ 8 (rotate by 8 within a row)
-      int t = __builtin_amdgcn_update_dpp(0, mw[r + 4], 0x128, 0xf, 0xc, false);
-      t = __builtin_amdgcn_update_dpp(t, mw[r], 0x128, 0xf, 0x3, false);
-      mw[r] = max(b3 ? mw[r + 4] : mw[r], t);
-    }
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {    // lanes l, l ^ 4 (a row rotation by n moves lane i - n to i)
-      int t = __builtin_amdgcn_update_dpp(0, mw[r + 2], 0x124, 0xf, 0xa, false);
-      t = __builtin_amdgcn_update_dpp(t, mw[r], 0x12c, 0xf, 0x5, false);
-      mw[r] = max(b2 ? mw[r + 2] : mw[r], t);
-    }
-    {                                // lanes l, l ^ 2 (quad permutation 2, 3, 0, 1)
-      const int send = b1 ? mw[0] : mw[1];
-      const int t = __builtin_amdgcn_update_dpp(0, send, 0x4e, 0xf, 0xf, false);
-      mw[0] = max(b1 ? mw[1] : mw[0], t);
-    }
-    // lanes l, l ^ 1 (quad permutation 1, 0, 3, 2)
-    const int bmax = max(mw[0], __builtin_amdgcn_update_dpp(0, mw[0], 0xb1, 0xf, 0xf, false));
-    // the width this lane speaks for: register index from lane bits 1-4, pair
-    // member from bit 5 (lanes l and l ^ 1 agree)
-    const int wl = 2 * ((lane >> 1) & 15) + (lane >> 5) + 1;
-    // index of width wl in the sorted width list = number of listed widths below it
-    const int ji = ((a.wmask >> (wl - 1)) & 1u) ? __popc(a.wmask & ((1u << (wl - 1)) - 1u)) : -1;
-    double snr = -INFINITY;
-    if (ji >= 0 && bmax >= 0 && dg >= 0)
-      snr = ((double)bmax - a.M[(int64_t)dg * a.nw + ji]) / a.S[(int64_t)dg * a.nw + ji];
-    // wave argmax over (snr desc, W asc); every lane ends with the result
-    int bw = wl, bb = bmax;
-#pragma unroll
-    for (int sh = 2; sh < 64; sh <<= 1) {
-      const double os = __shfl_xor(snr, sh, 64);
-      const int ow = __shfl_xor(bw, sh, 64), ob = __shfl_xor(bb, sh, 64);
-      if (os > snr || (os == snr && ow < bw)) {
-        snr = os;
-        bw = ow;
-        bb = ob;
-      }
-    }
-    // earliest start of the winning width in this tile: a sliding window of width
-    // bw over this lane's outputs (only valid windows, i + bw <= lim, can match)
-    int first = -1;
-    if (snr != -INFINITY) {
-      int B = 0;
-      for (int k = 0; k < bw; ++k) B += yl[k];
-#pragma unroll
-      for (int i = 0; i < SP; ++i) {
-        if (first < 0 && B == bb && i + bw <= lim) first = i;
-        B += yl[i + bw] - yl[i];
-      }
-    }
-    const unsigned long long hit = __ballot(first >= 0);
-    int tbest = -1;
-    if (hit != 0ull) {
-      const int fl = __builtin_ctzll(hit);
-      const int fi = __shfl(first, fl, 64);
-      tbest = (int)(t0 + fl * SP + fi);
-    }
-    if (dg >= 0 && lane == 0) {
-      CandRec rec;
-      rec.snr = (hit != 0ull) ? snr : -INFINITY;
-      rec.t = (hit != 0ull) ? tbest : -1;
-      rec.w = (hit != 0ull) ? bw : 0;
-      part[(int64_t)dg * a.ntt + tt] = rec;
-    }
+    const CandRec rec = boxcar_row<SP>(Yw, lane, t0, TT, a.nout, dg, a.wmask, a.nw, a.M, a.S);
+    if (dg >= 0 && lane == 0) part[(int64_t)dg * a.ntt + tt] = rec;
   }
   __syncthreads();   // LDS may be reused by whatever runs next in this workgroup
 }
@@ -735,8 +591,19 @@ static hipError_t upload(T **dst, const std::vector<T> &v) {
   return hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
+// Search candidates: the kNumCfgs shapes of k_search, then the shapes of the
+// matrix-core search (kernels_mfma.hip).  Without a choice the first matrix-core
+// shape runs (k_search shape kDefaultCfg if the plan does not fit it).
+static int num_candidates() { return kNumCfgs + mfma_search_count(); }
+
 static int cfg_index(const dedisp_plan_s *p) {
-  return (p->tile_choice >= 0 && p->tile_choice < kNumCfgs) ? p->tile_choice : kDefaultCfg;
+  return (p->tile_choice >= 0 && p->tile_choice < num_candidates()) ? p->tile_choice : kNumCfgs;
+}
+
+// The k_search shape of a choice (the multi-beam kernel has only those).
+static int valu_index(const dedisp_plan_s *p) {
+  const int ci = cfg_index(p);
+  return ci < kNumCfgs ? ci : kDefaultCfg;
 }
 
 // Tables for configuration ci, built and uploaded on first use.  Caller holds p->mu.
@@ -803,7 +670,7 @@ static int64_t count_rows(const dedisp_plan_s *p) {
 size_t search_work_bytes(const dedisp_plan_s *p, int32_t nw, int64_t nout) {
   if (p->wmode != DEDISP_W_UNIT) return 0;
   const int64_t nrows = count_rows(p);
-  size_t best = 0;
+  size_t best = mfma_search_work_bytes(p, nw, nout);
   for (int ci = 0; ci < kNumCfgs; ++ci) best = std::max(best, layout(p, ci, nw, nout, nrows).total);
   return best;
 }
@@ -936,6 +803,12 @@ static dedisp_status search_ci(dedisp_plan p, int ci, const uint8_t *x, int64_t 
                                int64_t in_stride, int64_t nout, const WidthList &wl,
                                const double *mu, const double *sigma, double *snr, int32_t *t,
                                int32_t *w, void *work, hipStream_t s) {
+  if (ci >= kNumCfgs) {
+    const dedisp_status st = run_search_mfma(p, ci - kNumCfgs, x, nsamp, in_stride, nout, wl, mu,
+                                             sigma, snr, t, w, work, s);
+    if (st == DEDISP_OK) p->last_search_tile = ci;
+    return st;
+  }
   SearchArgs a;
   TiledCfgTables *cfg = nullptr;
   Layout L;
@@ -955,10 +828,13 @@ dedisp_status run_search_tiled(dedisp_plan p, const uint8_t *x, int64_t nsamp, i
                                int64_t nout, const WidthList &wl, const double *mu,
                                const double *sigma, double *snr, int32_t *t, int32_t *w,
                                void *work, hipStream_t s) {
-  return search_ci(p, cfg_index(p), x, nsamp, in_stride, nout, wl, mu, sigma, snr, t, w, work, s);
+  const int ci = cfg_index(p);
+  dedisp_status st = search_ci(p, ci, x, nsamp, in_stride, nout, wl, mu, sigma, snr, t, w, work, s);
+  if (st == DEDISP_ERR_UNSUPPORTED && p->tile_choice < 0 && ci != kDefaultCfg)
+    st = search_ci(p, kDefaultCfg, x, nsamp, in_stride, nout, wl, mu, sigma, snr, t, w, work, s);
+  return st;
 }
 
-int search_config_count() { return kNumCfgs; }
 
 }  // namespace dd
 
@@ -966,7 +842,8 @@ extern "C" {
 
 dedisp_status dedisp_set_tile(dedisp_plan p, int32_t tile) {
   if (!p) return dd::fail(DEDISP_ERR_INVALID_ARG, "null plan");
-  if (tile < -2 || tile >= dd::kNumCfgs) return dd::fail(DEDISP_ERR_INVALID_ARG, "tile index out of range");
+  if (tile < -2 || tile >= dd::num_candidates())
+    return dd::fail(DEDISP_ERR_INVALID_ARG, "tile index out of range");
   p->tile_choice = tile;
   return DEDISP_OK;
 }
@@ -1104,7 +981,7 @@ dedisp_status dedisp_batch_create(dedisp_batch *out, int32_t nbeam, const dedisp
   B->nsamp.assign(nsamp, nsamp + nbeam);
   B->wl.n = (int32_t)wv.size();
   for (int i = 0; i < B->wl.n; ++i) B->wl.w[i] = wv[i];
-  B->ci = cfg_index(plans[0]);
+  B->ci = valu_index(plans[0]);
   dedisp_status st = DEDISP_OK;
   size_t off = 0;
   std::vector<size_t> rows;      // window-row bytes of each beam
@@ -1326,7 +1203,7 @@ static int tune_cache_lookup(const std::string &key) {
   int ci = -1, found = -1;
   double ms;
   while (fscanf(f, "%255s %d %lf", k, &ci, &ms) == 3)
-    if (key == k && ci >= 0 && ci < kNumCfgs) found = ci;
+    if (key == k && ci >= 0 && ci < num_candidates()) found = ci;
   fclose(f);
   return found;
 }
@@ -1387,7 +1264,7 @@ extern "C" dedisp_status dedisp_autotune(dedisp_plan p, const void *d_in, int64_
   std::vector<hipEvent_t> es, et;
   es.swap(p->ev_start);
   et.swap(p->ev_stop);
-  for (int ci = 0; ci < kNumCfgs && st == DEDISP_OK; ++ci) {
+  for (int ci = 0; ci < num_candidates() && st == DEDISP_OK; ++ci) {
     st = search_ci(p, ci, (const uint8_t *)d_in, nsamp, in_stride, nout, wl, d_chan_mean,
                    d_chan_sigma, snr, tt, ww, d_work, s);
     if (st == DEDISP_ERR_UNSUPPORTED) {

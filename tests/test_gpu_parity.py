@@ -280,14 +280,23 @@ def cfg2_mid(orc):
     return wl, n, yo
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7, -2])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, -2])
 def test_fused_search_every_tile_config(dd, orc, cfg2_mid, tile):
-    # Ragged in both DM (100 trials) and time (6755 outputs) for every tile shape.
+    # Ragged in both DM (100 trials) and time (6755 outputs) for every shape: 0-7 the
+    # packed-add kernel, 8-9 the matrix-core kernel, -2 the unfused path.
     wl, n, yo = cfg2_mid
     p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule="allnonzero")
     p.set_tile(tile)
     snr, t, W = p.search(_dev(wl.x), wl.widths, wl.chan_mean, wl.chan_sigma)
     assert p.last_search_tile() == (tile if tile >= 0 else -1)
+    _check_detect(orc, yo, n, wl.widths, wl.chan_mean, wl.chan_sigma, snr, t, W)
+
+
+def test_default_search_runs_on_the_matrix_cores(dd, orc, cfg2_mid):
+    wl, n, yo = cfg2_mid
+    p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule="allnonzero")
+    snr, t, W = p.search(_dev(wl.x), wl.widths, wl.chan_mean, wl.chan_sigma)
+    assert p.last_search_tile() == 8
     _check_detect(orc, yo, n, wl.widths, wl.chan_mean, wl.chan_sigma, snr, t, W)
 
 
