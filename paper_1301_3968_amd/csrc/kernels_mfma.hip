@@ -11,8 +11,9 @@
 // trial's result is corrected by 128 times its number of samples, so the int32 result
 // is exact.
 //
-// One workgroup takes 16 NWD trials x NWT * 16 NT outputs; each wave 16 trials x 16 NT
-// outputs.  Channel groups are staged into LDS (two buffers: the next group is loaded
+// One workgroup takes 16 SUB NWD trials x NWT * 16 NT outputs; each wave 16 SUB trials
+// x 16 NT outputs, its SUB halves of 16 trials sharing the segments (the band of all
+// its trials), so that every 16-byte sample read feeds SUB products.  Channel groups are staged into LDS (two buffers: the next group is loaded
 // while the current one is multiplied) as 16 byte-shifted copies of each channel's
 // window, so that the 16 samples a lane needs (window bytes i .. i + 15) are one aligned
 // 16-byte read: the copies are interleaved per 16-byte chunk, chunk q of copy p at
@@ -37,21 +38,22 @@
 namespace dd {
 
 // Workgroup shapes: NWD waves along DM, NWT along time, NT blocks of 16 outputs per wave,
-// RING 16-byte sample reads in flight per wave.
-#define DD_MFMA_CONFIGS(X) \
-  X(0, 8, 2, 16, 4)        \
-  X(1, 16, 1, 16, 4)
+// RING 16-byte sample reads in flight per wave, SUB halves of 16 trials per wave.
+#define DD_MFMA_CONFIGS(X)  \
+  X(0, 8, 2, 16, 4, 1)      \
+  X(1, 16, 1, 16, 4, 1)
 struct MfmaCfg {
-  int nwd, nwt, nt, ring;
+  int nwd, nwt, nt, ring, sub;
 };
-#define DD_MFMA_ENTRY(i, a, b, c, r) {a, b, c, r},
+#define DD_MFMA_ENTRY(i, a, b, c, r, h) {a, b, c, r, h},
 static const MfmaCfg kMfmaCfgs[] = {DD_MFMA_CONFIGS(DD_MFMA_ENTRY)};
 #undef DD_MFMA_ENTRY
 constexpr int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
 constexpr int kPhases = 16;                 // byte-shifted copies of each staged window
 constexpr int kMfmaBufBytes = 80 * 1024;    // LDS per staging buffer (two per workgroup)
-constexpr int kMaxKb = 8;                   // K blocks of one wave in one channel group
-constexpr int kRecBytes = 160;              // K-block record: 64 x u16 masks + 4 x (region, rel)
+// K-block record: per half 64 x u16 masks (lane = 16 segment + trial row), then 4 x
+// (region, rel) for the segments
+constexpr int rec_bytes(int sub) { return 128 * sub + 32; }
 // Staging tasks (quarter chunks) per thread: a buffer holds at most kMfmaBufBytes / 256
 // chunks of 16 copies, 4 tasks each.
 constexpr int max_tasks(int nw) { return (4 * (kMfmaBufBytes / 256) + 64 * nw - 1) / (64 * nw); }
@@ -76,7 +78,8 @@ struct MfmaCfgTables {
   std::vector<int32_t> perm, ntot, group_begin, kbr;
   std::vector<MGroup> groups;
   std::vector<MUnit> units;
-  std::vector<uint8_t> recs;      // [kb][kRecBytes]
+  int rec = 0;                    // record bytes
+  std::vector<uint8_t> recs;      // [kb][rec]
   int32_t *d_perm = nullptr, *d_ntot = nullptr, *d_group_begin = nullptr, *d_kbr = nullptr;
   MGroup *d_groups = nullptr;
   MUnit *d_units = nullptr;
@@ -183,24 +186,26 @@ __device__ __forceinline__ void tile_of_block(int ntw, int ntt, int *tt, int *tw
   *tw = L - *tt * ntw;
 }
 
-template <int NT>
+template <int N>
 struct TileAcc {
-  v4i v[NT];
+  v4i v[N];
 };
 
 // The products of DM tile tw over outputs T0 .. T0 + NWT * 16 NT - 1 (wave (wd, wt):
 // trials 16 wd .. 16 wd + 15 of the tile, outputs T0 + 16 NT wt + ...).  Ends with a
 // workgroup barrier, after which the LDS is free.
-template <int NWD, int NWT, int NT, int RING>
-__device__ __forceinline__ TileAcc<NT> mfma_tile(const MfmaArgs &a, int tw, int64_t T0,
-                                                 const uint8_t *xb, unsigned char *lds) {
-  constexpr int NW = NWD * NWT;
+template <int NWD, int NWT, int NT, int RING, int SUB>
+__device__ __forceinline__ TileAcc<SUB * NT> mfma_tile(const MfmaArgs &a, int tw, int64_t T0,
+                                                       const uint8_t *xb, unsigned char *lds) {
+  constexpr int NW = NWD * NWT, REC = rec_bytes(SUB);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wd = wave % NWD, wt = wave / NWD;
-  v4i acc[NT];
+  v4i acc[SUB][NT];
 #pragma unroll
-  for (int b = 0; b < NT; ++b) acc[b] = (v4i){0, 0, 0, 0};
+  for (int h = 0; h < SUB; ++h)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[h][b] = (v4i){0, 0, 0, 0};
 
   const int gb = ldc(a.group_begin, tw), ge = ldc(a.group_begin, tw + 1);
   // copies the K-block records of group g into LDS (buffer-to-LDS loads, 16 bytes a
@@ -208,9 +213,9 @@ __device__ __forceinline__ TileAcc<NT> mfma_tile(const MfmaArgs &a, int tw, int6
   auto stage_recs = [&](int g, unsigned char *buf) {
     const int kf = ldc(&a.groups[g].kb_first, 0), nkb = ldc(&a.groups[g].nkb, 0);
     const int ro = ldc(&a.groups[g].rec_off, 0);
-    const int nch = nkb * (kRecBytes / 16);
+    const int nch = nkb * (REC / 16);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(a.recs + (int64_t)kf * kRecBytes), (short)0, nkb * kRecBytes, kBufWord3);
+        (void *)(a.recs + (int64_t)kf * REC), (short)0, nkb * REC, kBufWord3);
     for (int c0 = 64 * wave; c0 < nch; c0 += 64 * NW) {
       const int ch = c0 + lane;
       if (ch < nch)
@@ -261,15 +266,20 @@ __device__ __forceinline__ TileAcc<NT> mfma_tile(const MfmaArgs &a, int tw, int6
     const int k0 = ldc(a.kbr, (int64_t)kbase + wd), k1 = ldc(a.kbr, (int64_t)kbase + wd + 1);
     const unsigned char *wbuf = buf + 256 * NT * wt;
     for (int kb = k0; kb < k1; ++kb) {
-      const unsigned char *rec = buf + ro + (kb - kf) * kRecBytes;
-      // 16 mask bytes of lane (trial row lane % 16, segment lane / 16): bit j -> byte j
-      const uint32_t m16 = *(const uint16_t *)(rec + 2 * lane);
-      v4i mk;
+      const unsigned char *rec = buf + ro + (kb - kf) * REC;
+      // 16 mask bytes of lane (trial row lane % 16, segment lane / 16) of each half:
+      // bit j -> byte j
+      v4i mk[SUB];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) mk[k] = (int32_t)((((m16 >> (4 * k)) & 15u) * 0x204081u) & 0x01010101u);
+      for (int h = 0; h < SUB; ++h) {
+        const uint32_t m16 = *(const uint16_t *)(rec + 128 * h + 2 * lane);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          mk[h][k] = (int32_t)((((m16 >> (4 * k)) & 15u) * 0x204081u) & 0x01010101u);
+      }
       // window bytes i .. i + 15 of output column lane % 16 of the lane's segment
-      const int32_t region = *(const int32_t *)(rec + 128 + 8 * (lane >> 4));
-      const int32_t i = *(const int32_t *)(rec + 132 + 8 * (lane >> 4)) + (lane & 15);
+      const int32_t region = *(const int32_t *)(rec + 128 * SUB + 8 * (lane >> 4));
+      const int32_t i = *(const int32_t *)(rec + 128 * SUB + 4 + 8 * (lane >> 4)) + (lane & 15);
       const unsigned char *p = wbuf + region + 256 * (i >> 4) + 16 * (i & 15);
       // a ring of RING reads in flight: the read of block b + RING is issued as soon
       // as block b's product has taken its operand
@@ -278,14 +288,16 @@ __device__ __forceinline__ TileAcc<NT> mfma_tile(const MfmaArgs &a, int tw, int6
       for (int b = 0; b < RING; ++b) f[b] = *(const v4i *)(p + 256 * b);
 #pragma unroll
       for (int b = 0; b < NT; ++b) {
-        acc[b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(mk, f[b % RING], acc[b], 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < SUB; ++h)
+          acc[h][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(mk[h], f[b % RING], acc[h][b], 0, 0, 0);
         if (b + RING < NT) f[b % RING] = *(const v4i *)(p + 256 * (b + RING));
       }
-      // keep that order: RING reads, then one product and one read at a time
+      // keep that order: RING reads, then the SUB products of a read and one read
       __builtin_amdgcn_sched_group_barrier(0x100, RING, 0);
 #pragma unroll
       for (int b = 0; b < NT; ++b) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, SUB, 0);
         if (b + RING < NT) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
       }
     }
@@ -293,14 +305,16 @@ __device__ __forceinline__ TileAcc<NT> mfma_tile(const MfmaArgs &a, int tw, int6
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
   }
-  TileAcc<NT> r;
+  TileAcc<SUB * NT> r;
 #pragma unroll
-  for (int b = 0; b < NT; ++b) r.v[b] = acc[b];
+  for (int h = 0; h < SUB; ++h)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) r.v[h * NT + b] = acc[h][b];
   return r;
 }
 
 // One workgroup per CU (its LDS), so NW / 4 waves per SIMD: registers up to 512 / that.
-template <int NWD, int NWT, int NT, int RING>
+template <int NWD, int NWT, int NT, int RING, int SUB>
 __global__ void __launch_bounds__(64 * NWD * NWT)
 __attribute__((amdgpu_waves_per_eu(NWD * NWT / 4, NWD * NWT / 4)))
 k_dedisp_mfma(MfmaArgs a) {
@@ -313,23 +327,26 @@ k_dedisp_mfma(MfmaArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wd = wave % NWD, wt = wave / NWD;
   const int64_t T0 = (int64_t)tt * TW;
-  const TileAcc<NT> tacc = mfma_tile<NWD, NWT, NT, RING>(a, tw, T0, a.x + (int64_t)bb * a.in_bstride, lds);
-  const v4i *acc = tacc.v;
-  // C layout: lane l, element r holds trial row 4 (l / 16) + r, output l % 16
+  const TileAcc<SUB * NT> tacc =
+      mfma_tile<NWD, NWT, NT, RING, SUB>(a, tw, T0, a.x + (int64_t)bb * a.in_bstride, lds);
+  // C layout: lane l, element r of half h holds trial row 16 h + 4 (l / 16) + r of the
+  // wave's trials, output l % 16
   int32_t *ob = a.out + (int64_t)bb * a.out_bstride;
   const int n = lane & 15, g4 = lane >> 4;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int slot = tw * 16 * NWD + 16 * wd + 4 * g4 + r;
-    const int d = a.perm[slot];
-    if (d < 0) continue;
-    const int32_t corr = 128 * a.ntot[d];
+  for (int h = 0; h < SUB; ++h)
 #pragma unroll
-    for (int b = 0; b < NT; ++b) {
-      const int64_t t = T0 + (int64_t)TWV * wt + 16 * b + n;
-      if (t < a.nout) ob[(int64_t)d * a.out_stride + t] = acc[b][r] + corr;
+    for (int r = 0; r < 4; ++r) {
+      const int slot = tw * 16 * SUB * NWD + 16 * SUB * wd + 16 * h + 4 * g4 + r;
+      const int d = a.perm[slot];
+      if (d < 0) continue;
+      const int32_t corr = 128 * a.ntot[d];
+#pragma unroll
+      for (int b = 0; b < NT; ++b) {
+        const int64_t t = T0 + (int64_t)TWV * wt + 16 * b + n;
+        if (t < a.nout) ob[(int64_t)d * a.out_stride + t] = tacc.v[h * NT + b][r] + corr;
+      }
     }
-  }
 }
 
 struct MfmaSearchArgs {
@@ -346,16 +363,17 @@ constexpr int search_step(int sp) { return 64 * sp - ((32 + sp - 1) / sp) * sp; 
 
 // Fused search: the products of one tile (outputs T0 .. T0 + TW - 1, T0 = tt * TT),
 // then the boxcar search of every trial of the tile over starts T0 .. T0 + TT - 1.
-// The series go through LDS in two passes (the trials of accumulator rows 0-1, then
-// 2-3, of every wave), as rows of TW + 32 ints; each wave searches whole rows.
-template <int NWD, int NWT, int NT, int RING>
+// The series go through LDS in two passes (the first, then the second half of every
+// wave's trials), as rows of TW + 32 ints; each wave searches whole rows.
+template <int NWD, int NWT, int NT, int RING, int SUB>
 __global__ void __launch_bounds__(64 * NWD * NWT)
 __attribute__((amdgpu_waves_per_eu(NWD * NWT / 4, NWD * NWT / 4)))
 k_search_mfma(MfmaSearchArgs sa) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   constexpr int NW = NWD * NWT, TWV = 16 * NT, TW = NWT * TWV, SP = TW / 64;
   constexpr int TT = search_step(SP), YROW = TW + kHalo + 4;
-  constexpr int ROWS = 8 * NWD;            // rows of one pass: 8 trials per DM sub-tile
+  constexpr int PT = 8 * SUB;              // trials of one wave in one pass
+  constexpr int ROWS = PT * NWD;           // rows of one pass
   static_assert(TW % 64 == 0 && TT % SP == 0 && TW - TT >= 31, "search tile");
   static_assert(ROWS % NW == 0, "whole rows per wave");
   static_assert(ROWS * YROW * 4 <= 2 * kMfmaBufBytes, "rows of one pass fit the LDS");
@@ -366,29 +384,32 @@ k_search_mfma(MfmaSearchArgs sa) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wd = wave % NWD, wt = wave / NWD;
   const int64_t T0 = (int64_t)tt * TT;
-  const TileAcc<NT> tacc = mfma_tile<NWD, NWT, NT, RING>(a, tw, T0, a.x, lds);
-  const v4i *acc = tacc.v;
+  const TileAcc<SUB * NT> tacc = mfma_tile<NWD, NWT, NT, RING, SUB>(a, tw, T0, a.x, lds);
+  constexpr int DT = 16 * SUB * NWD;
   int *Y = (int *)lds;
   const int n = lane & 15, g4 = lane >> 4;
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
-    // lanes holding accumulator rows 2 pass, 2 pass + 1 write their trials' outputs
-    if ((g4 >> 1) == pass) {
+    // the wave's trials k = 16 h + 4 g4 + r with k in [PT pass, PT pass + PT) write
+    // their outputs into row PT wd + k - PT pass
+#pragma unroll
+    for (int h = 0; h < SUB; ++h)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int d = a.perm[tw * 16 * NWD + 16 * wd + 4 * g4 + r];
+        const int k = 16 * h + 4 * g4 + r;
+        if (k / PT != pass) continue;
+        const int d = a.perm[tw * DT + 16 * SUB * wd + k];
         const int32_t corr = d >= 0 ? 128 * a.ntot[d] : 0;
-        int *row = Y + (8 * wd + 4 * (g4 & 1) + r) * YROW + TWV * wt + n;
+        int *row = Y + (PT * wd + k - PT * pass) * YROW + TWV * wt + n;
 #pragma unroll
-        for (int b = 0; b < NT; ++b) row[16 * b] = acc[b][r] + corr;
+        for (int b = 0; b < NT; ++b) row[16 * b] = tacc.v[h * NT + b][r] + corr;
       }
-    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < ROWS / NW; ++k) {
       const int rw = wave * (ROWS / NW) + k;
-      const int sw = rw >> 3, j = rw & 7;   // DM sub-tile, trial row within the pass
-      const int dg = a.perm[tw * 16 * NWD + 16 * sw + 4 * (2 * pass + (j >> 2)) + (j & 3)];
+      const int sw = rw / PT, j = rw % PT;   // DM sub-tile, trial row within the pass
+      const int dg = a.perm[tw * DT + 16 * SUB * sw + PT * pass + j];
       const CandRec rec =
           boxcar_row<SP>(Y + rw * YROW, lane, T0, TT, a.nout, dg, sa.wmask, sa.nw, sa.M, sa.S);
       if (dg >= 0 && lane == 0) sa.part[(int64_t)dg * a.ntt + tt] = rec;
@@ -413,10 +434,12 @@ static hipError_t upload(T **dst, const std::vector<T> &v) {
 static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
   const MfmaCfg cf = kMfmaCfgs[ci];
   const int C = p->nchan, D = p->ndm;
-  const int NWD = cf.nwd, TW = cf.nwt * 16 * cf.nt, DT = 16 * NWD;
+  const int NWD = cf.nwd, TW = cf.nwt * 16 * cf.nt, ST = 16 * cf.sub, DT = ST * NWD;
+  const int REC = rec_bytes(cf.sub);
   out = MfmaCfgTables();
   out.tw = TW;
   out.trials = DT;
+  out.rec = REC;
   std::vector<int32_t> order(D);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p->dm[x] < p->dm[y]; });
@@ -441,8 +464,8 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
       int slo = INT32_MAX, send = INT32_MIN;
       for (int w = 0; w < NWD; ++w) {
         int l = INT32_MAX, h = INT32_MIN;
-        for (int m = 0; m < 16; ++m) {
-          const int d = out.perm[(size_t)tw * DT + 16 * w + m];
+        for (int m = 0; m < ST; ++m) {
+          const int d = out.perm[(size_t)tw * DT + ST * w + m];
           if (d < 0 || p->ntap[(size_t)d * C + c] == 0) continue;
           l = std::min(l, p->start[(size_t)d * C + c]);
           h = std::max(h, p->start[(size_t)d * C + c] + p->ntap[(size_t)d * C + c]);
@@ -464,21 +487,15 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
     }
     int c = 0;
     while (c < C) {
-      // channels of the group: within the LDS buffer, and at most kMaxKb K blocks
-      // (4 kMaxKb segments) for every wave
+      // channels of the group: windows and K-block records within the LDS buffer
       int used = 0;
       const int cbeg = c;
       std::vector<int> segw(NWD, 0);
       int nunits = 0;   // at most max_tasks quarter chunks per thread
       while (c < C && 4 * (nunits + wst[c] / 16) <= max_tasks(NWD * cf.nwt) * 64 * NWD * cf.nwt) {
-        bool fits = true;
         int nrec = 0;   // K-block records with channel c added
-        for (int w = 0; w < NWD; ++w) {
-          fits = fits && segw[w] + nseg[w * C + c] <= 4 * kMaxKb;
-          nrec += (segw[w] + nseg[w * C + c] + 3) / 4;
-        }
-        if (!fits || (int64_t)used + (int64_t)kPhases * wst[c] + (int64_t)nrec * kRecBytes > kMfmaBufBytes)
-          break;
+        for (int w = 0; w < NWD; ++w) nrec += (segw[w] + nseg[w * C + c] + 3) / 4;
+        if ((int64_t)used + (int64_t)kPhases * wst[c] + (int64_t)nrec * REC > kMfmaBufBytes) break;
         for (int w = 0; w < NWD; ++w) segw[w] += nseg[w * C + c];
         used += kPhases * wst[c];
         nunits += wst[c] / 16;
@@ -498,38 +515,39 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
       gi.nunits = (int)out.units.size() - gi.unit_begin;
       if (4 * gi.nunits > max_tasks(NWD * cf.nwt) * 64 * NWD * cf.nwt) return false;
       gi.kb_base = (int)out.kbr.size();
-      gi.kb_first = (int)(out.recs.size() / kRecBytes);
+      gi.kb_first = (int)(out.recs.size() / REC);
       gi.rec_off = off;
       for (int w = 0; w < NWD; ++w) {
-        out.kbr.push_back((int32_t)(out.recs.size() / kRecBytes));
+        out.kbr.push_back((int32_t)(out.recs.size() / REC));
         // segments of this sub-tile in the group, four per K block
         std::vector<std::pair<int, int>> segs;
         for (int cc = cbeg; cc < c; ++cc)
           for (int s = 0; s < nseg[w * C + cc]; ++s) segs.push_back({cc, lo[w * C + cc] + 16 * s});
         for (size_t s0 = 0; s0 < segs.size(); s0 += 4) {
-          uint8_t rec[kRecBytes] = {};
+          std::vector<uint8_t> rec(REC, 0);
           for (int g = 0; g < 4; ++g) {
             // padding segments: zero masks, a valid window
             const size_t si = s0 + g < segs.size() ? s0 + g : s0;
             const int cc = segs[si].first, o = segs[si].second;
             const int32_t sg[2] = {region[cc], o - stlo[cc]};
-            std::memcpy(rec + 128 + 8 * g, sg, 8);
+            std::memcpy(rec.data() + 128 * cf.sub + 8 * g, sg, 8);
             if (s0 + g >= segs.size()) continue;
-            for (int m = 0; m < 16; ++m) {
-              const int d = out.perm[(size_t)tw * DT + 16 * w + m];
+            for (int m = 0; m < ST; ++m) {
+              const int d = out.perm[(size_t)tw * DT + ST * w + m];
               if (d < 0) continue;
               const int st = p->start[(size_t)d * C + cc], nt = p->ntap[(size_t)d * C + cc];
               uint16_t bits = 0;
               for (int j = 0; j < 16; ++j)
                 if (o + j >= st && o + j < st + nt) bits |= (uint16_t)(1u << j);
-              std::memcpy(rec + 2 * (16 * g + m), &bits, 2);
+              // half m / 16, lane 16 g + m % 16
+              std::memcpy(rec.data() + 128 * (m / 16) + 2 * (16 * g + m % 16), &bits, 2);
             }
           }
-          out.recs.insert(out.recs.end(), rec, rec + kRecBytes);
+          out.recs.insert(out.recs.end(), rec.begin(), rec.end());
         }
       }
-      out.kbr.push_back((int32_t)(out.recs.size() / kRecBytes));
-      gi.nkb = (int)(out.recs.size() / kRecBytes) - gi.kb_first;
+      out.kbr.push_back((int32_t)(out.recs.size() / REC));
+      gi.nkb = (int)(out.recs.size() / REC) - gi.kb_first;
       out.groups.push_back(gi);
       if (c == cbeg) return false;   // one channel does not fit
     }
@@ -551,22 +569,22 @@ static hipError_t allow_lds_mfma(const void *fn, bool *done, std::mutex *mu, int
   return e;
 }
 
-template <int NWD, int NWT, int NT, int RING>
+template <int NWD, int NWT, int NT, int RING, int SUB>
 static hipError_t launch_mfma_cfg(const MfmaArgs &a, int nbatch, hipStream_t s) {
   static bool done[64] = {};
   static std::mutex mu;
-  hipError_t e = allow_lds_mfma((const void *)k_dedisp_mfma<NWD, NWT, NT, RING>, done, &mu,
+  hipError_t e = allow_lds_mfma((const void *)k_dedisp_mfma<NWD, NWT, NT, RING, SUB>, done, &mu,
                                 2 * kMfmaBufBytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_dedisp_mfma<NWD, NWT, NT, RING>), dim3(a.ntw * a.ntt, nbatch),
+  hipLaunchKernelGGL((k_dedisp_mfma<NWD, NWT, NT, RING, SUB>), dim3(a.ntw * a.ntt, nbatch),
                      dim3(64 * NWD * NWT), 2 * a.bufbytes, s, a);
   return hipGetLastError();
 }
 
 static hipError_t launch_mfma(int ci, const MfmaArgs &a, int nbatch, hipStream_t s) {
   switch (ci) {
-#define DD_MFMA_CASE(i, x, y, z, r) \
-  case i: return launch_mfma_cfg<x, y, z, r>(a, nbatch, s);
+#define DD_MFMA_CASE(i, x, y, z, r, h) \
+  case i: return launch_mfma_cfg<x, y, z, r, h>(a, nbatch, s);
     DD_MFMA_CONFIGS(DD_MFMA_CASE)
 #undef DD_MFMA_CASE
     default: return hipErrorInvalidValue;
@@ -674,22 +692,22 @@ size_t mfma_search_work_bytes(const dedisp_plan_s *p, int32_t nw, int64_t nout) 
 
 int mfma_search_count() { return kNumMfmaCfgs; }
 
-template <int NWD, int NWT, int NT, int RING>
+template <int NWD, int NWT, int NT, int RING, int SUB>
 static hipError_t launch_search_cfg(const MfmaSearchArgs &sa, hipStream_t s) {
   static bool done[64] = {};
   static std::mutex mu;
-  hipError_t e = allow_lds_mfma((const void *)k_search_mfma<NWD, NWT, NT, RING>, done, &mu,
+  hipError_t e = allow_lds_mfma((const void *)k_search_mfma<NWD, NWT, NT, RING, SUB>, done, &mu,
                                 2 * kMfmaBufBytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_search_mfma<NWD, NWT, NT, RING>), dim3(sa.m.ntw * sa.m.ntt),
+  hipLaunchKernelGGL((k_search_mfma<NWD, NWT, NT, RING, SUB>), dim3(sa.m.ntw * sa.m.ntt),
                      dim3(64 * NWD * NWT), 2 * sa.m.bufbytes, s, sa);
   return hipGetLastError();
 }
 
 static hipError_t launch_search_mfma(int k, const MfmaSearchArgs &sa, hipStream_t s) {
   switch (k) {
-#define DD_MFMA_SEARCH_CASE(i, x, y, z, r) \
-  case i: return launch_search_cfg<x, y, z, r>(sa, s);
+#define DD_MFMA_SEARCH_CASE(i, x, y, z, r, h) \
+  case i: return launch_search_cfg<x, y, z, r, h>(sa, s);
     DD_MFMA_CONFIGS(DD_MFMA_SEARCH_CASE)
 #undef DD_MFMA_SEARCH_CASE
     default: return hipErrorInvalidValue;
