@@ -38,25 +38,28 @@
 namespace dd {
 
 // Workgroup shapes: NWD waves along DM, NWT along time, NT blocks of 16 outputs per wave,
-// RING 16-byte sample reads in flight per wave, SUB halves of 16 trials per wave.
-#define DD_MFMA_CONFIGS(X)  \
-  X(0, 8, 2, 16, 4, 1)      \
-  X(1, 16, 1, 16, 4, 1)
+// RING 16-byte sample reads in flight per wave, SUB halves of 16 trials per wave, WG
+// workgroups per CU (each with 1 / WG of the CU's LDS).
+#define DD_MFMA_CONFIGS(X)     \
+  X(0, 8, 2, 16, 4, 1, 1)      \
+  X(1, 16, 1, 16, 4, 1, 1)     \
+  X(2, 8, 1, 16, 4, 1, 2)
 struct MfmaCfg {
-  int nwd, nwt, nt, ring, sub;
+  int nwd, nwt, nt, ring, sub, wg;
 };
-#define DD_MFMA_ENTRY(i, a, b, c, r, h) {a, b, c, r, h},
+#define DD_MFMA_ENTRY(i, a, b, c, r, h, g) {a, b, c, r, h, g},
 static const MfmaCfg kMfmaCfgs[] = {DD_MFMA_CONFIGS(DD_MFMA_ENTRY)};
 #undef DD_MFMA_ENTRY
 constexpr int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
 constexpr int kPhases = 16;                 // byte-shifted copies of each staged window
-constexpr int kMfmaBufBytes = 80 * 1024;    // LDS per staging buffer (two per workgroup)
+constexpr int kMfmaBufBytes = 80 * 1024;    // LDS per staging buffer (two per workgroup) at
+                                            // one workgroup per CU
 // K-block record: per half 64 x u16 masks (lane = 16 segment + trial row), then 4 x
 // (region, rel) for the segments
 constexpr int rec_bytes(int sub) { return 128 * sub + 32; }
-// Staging tasks (quarter chunks) per thread: a buffer holds at most kMfmaBufBytes / 256
-// chunks of 16 copies, 4 tasks each.
-constexpr int max_tasks(int nw) { return (4 * (kMfmaBufBytes / 256) + 64 * nw - 1) / (64 * nw); }
+// Staging tasks (quarter chunks) per thread: a buffer of `buf` bytes holds at most
+// buf / 256 chunks of 16 copies, 4 tasks each.
+constexpr int max_tasks(int nw, int buf) { return (4 * (buf / 256) + 64 * nw - 1) / (64 * nw); }
 
 struct MGroup {
   int32_t unit_begin, nunits;   // staging units (16 window bytes of one channel each)
@@ -79,6 +82,7 @@ struct MfmaCfgTables {
   std::vector<MGroup> groups;
   std::vector<MUnit> units;
   int rec = 0;                    // record bytes
+  int bufbytes = 0;               // LDS bytes of one staging buffer
   std::vector<uint8_t> recs;      // [kb][rec]
   int32_t *d_perm = nullptr, *d_ntot = nullptr, *d_group_begin = nullptr, *d_kbr = nullptr;
   MGroup *d_groups = nullptr;
@@ -194,7 +198,7 @@ struct TileAcc {
 // The products of DM tile tw over outputs T0 .. T0 + NWT * 16 NT - 1 (wave (wd, wt):
 // trials 16 wd .. 16 wd + 15 of the tile, outputs T0 + 16 NT wt + ...).  Ends with a
 // workgroup barrier, after which the LDS is free.
-template <int NWD, int NWT, int NT, int RING, int SUB>
+template <int NWD, int NWT, int NT, int RING, int SUB, int WG>
 __device__ __forceinline__ TileAcc<SUB * NT> mfma_tile(const MfmaArgs &a, int tw, int64_t T0,
                                                        const uint8_t *xb, unsigned char *lds) {
   constexpr int NW = NWD * NWT, REC = rec_bytes(SUB);
@@ -224,7 +228,7 @@ __device__ __forceinline__ TileAcc<SUB * NT> mfma_tile(const MfmaArgs &a, int tw
     }
   };
   // staging tasks: thread t takes quarter t % 4 of chunks t / 4, t / 4 + NW * 16, ...
-  constexpr int NTHR = 64 * NW, TPT = max_tasks(NW);
+  constexpr int NTHR = 64 * NW, TPT = max_tasks(NW, kMfmaBufBytes / WG);
   uint32_t raw[TPT][6];
   int sh[TPT], dst[TPT], rot[TPT];
   int ntask = 0;
@@ -313,10 +317,11 @@ __device__ __forceinline__ TileAcc<SUB * NT> mfma_tile(const MfmaArgs &a, int tw
   return r;
 }
 
-// One workgroup per CU (its LDS), so NW / 4 waves per SIMD: registers up to 512 / that.
-template <int NWD, int NWT, int NT, int RING, int SUB>
+// WG workgroups per CU (their LDS), so WG NW / 4 waves per SIMD: registers up to 512 /
+// that.
+template <int NWD, int NWT, int NT, int RING, int SUB, int WG>
 __global__ void __launch_bounds__(64 * NWD * NWT)
-__attribute__((amdgpu_waves_per_eu(NWD * NWT / 4, NWD * NWT / 4)))
+__attribute__((amdgpu_waves_per_eu(WG * NWD * NWT / 4, WG * NWD * NWT / 4)))
 k_dedisp_mfma(MfmaArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   constexpr int TWV = 16 * NT, TW = NWT * TWV;
@@ -328,7 +333,7 @@ k_dedisp_mfma(MfmaArgs a) {
   const int wd = wave % NWD, wt = wave / NWD;
   const int64_t T0 = (int64_t)tt * TW;
   const TileAcc<SUB * NT> tacc =
-      mfma_tile<NWD, NWT, NT, RING, SUB>(a, tw, T0, a.x + (int64_t)bb * a.in_bstride, lds);
+      mfma_tile<NWD, NWT, NT, RING, SUB, WG>(a, tw, T0, a.x + (int64_t)bb * a.in_bstride, lds);
   // C layout: lane l, element r of half h holds trial row 16 h + 4 (l / 16) + r of the
   // wave's trials, output l % 16
   int32_t *ob = a.out + (int64_t)bb * a.out_bstride;
@@ -365,9 +370,9 @@ constexpr int search_step(int sp) { return 64 * sp - ((32 + sp - 1) / sp) * sp; 
 // then the boxcar search of every trial of the tile over starts T0 .. T0 + TT - 1.
 // The series go through LDS in two passes (the first, then the second half of every
 // wave's trials), as rows of TW + 32 ints; each wave searches whole rows.
-template <int NWD, int NWT, int NT, int RING, int SUB>
+template <int NWD, int NWT, int NT, int RING, int SUB, int WG>
 __global__ void __launch_bounds__(64 * NWD * NWT)
-__attribute__((amdgpu_waves_per_eu(NWD * NWT / 4, NWD * NWT / 4)))
+__attribute__((amdgpu_waves_per_eu(WG * NWD * NWT / 4, WG * NWD * NWT / 4)))
 k_search_mfma(MfmaSearchArgs sa) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   constexpr int NW = NWD * NWT, TWV = 16 * NT, TW = NWT * TWV, SP = TW / 64;
@@ -376,7 +381,7 @@ k_search_mfma(MfmaSearchArgs sa) {
   constexpr int ROWS = PT * NWD;           // rows of one pass
   static_assert(TW % 64 == 0 && TT % SP == 0 && TW - TT >= 31, "search tile");
   static_assert(ROWS % NW == 0, "whole rows per wave");
-  static_assert(ROWS * YROW * 4 <= 2 * kMfmaBufBytes, "rows of one pass fit the LDS");
+  static_assert(ROWS * YROW * 4 <= 2 * (kMfmaBufBytes / WG), "rows of one pass fit the LDS");
   const MfmaArgs &a = sa.m;
   int tt, tw;
   tile_of_block(a.ntw, a.ntt, &tt, &tw);
@@ -384,7 +389,7 @@ k_search_mfma(MfmaSearchArgs sa) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wd = wave % NWD, wt = wave / NWD;
   const int64_t T0 = (int64_t)tt * TT;
-  const TileAcc<SUB * NT> tacc = mfma_tile<NWD, NWT, NT, RING, SUB>(a, tw, T0, a.x, lds);
+  const TileAcc<SUB * NT> tacc = mfma_tile<NWD, NWT, NT, RING, SUB, WG>(a, tw, T0, a.x, lds);
   constexpr int DT = 16 * SUB * NWD;
   int *Y = (int *)lds;
   const int n = lane & 15, g4 = lane >> 4;
@@ -435,11 +440,12 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
   const MfmaCfg cf = kMfmaCfgs[ci];
   const int C = p->nchan, D = p->ndm;
   const int NWD = cf.nwd, TW = cf.nwt * 16 * cf.nt, ST = 16 * cf.sub, DT = ST * NWD;
-  const int REC = rec_bytes(cf.sub);
+  const int REC = rec_bytes(cf.sub), BUF = kMfmaBufBytes / cf.wg;
   out = MfmaCfgTables();
   out.tw = TW;
   out.trials = DT;
   out.rec = REC;
+  out.bufbytes = BUF;
   std::vector<int32_t> order(D);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p->dm[x] < p->dm[y]; });
@@ -483,7 +489,7 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
       }
       stlo[c] = slo;
       wst[c] = (send - slo + TW + 15) / 16 * 16;   // window bytes (16 copies each)
-      if ((int64_t)kPhases * wst[c] > kMfmaBufBytes) return false;
+      if ((int64_t)kPhases * wst[c] > BUF) return false;
     }
     int c = 0;
     while (c < C) {
@@ -492,10 +498,10 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
       const int cbeg = c;
       std::vector<int> segw(NWD, 0);
       int nunits = 0;   // at most max_tasks quarter chunks per thread
-      while (c < C && 4 * (nunits + wst[c] / 16) <= max_tasks(NWD * cf.nwt) * 64 * NWD * cf.nwt) {
+      while (c < C && 4 * (nunits + wst[c] / 16) <= max_tasks(NWD * cf.nwt, BUF) * 64 * NWD * cf.nwt) {
         int nrec = 0;   // K-block records with channel c added
         for (int w = 0; w < NWD; ++w) nrec += (segw[w] + nseg[w * C + c] + 3) / 4;
-        if ((int64_t)used + (int64_t)kPhases * wst[c] + (int64_t)nrec * REC > kMfmaBufBytes) break;
+        if ((int64_t)used + (int64_t)kPhases * wst[c] + (int64_t)nrec * REC > BUF) break;
         for (int w = 0; w < NWD; ++w) segw[w] += nseg[w * C + c];
         used += kPhases * wst[c];
         nunits += wst[c] / 16;
@@ -513,7 +519,7 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
         off += kPhases * wst[cc];
       }
       gi.nunits = (int)out.units.size() - gi.unit_begin;
-      if (4 * gi.nunits > max_tasks(NWD * cf.nwt) * 64 * NWD * cf.nwt) return false;
+      if (4 * gi.nunits > max_tasks(NWD * cf.nwt, BUF) * 64 * NWD * cf.nwt) return false;
       gi.kb_base = (int)out.kbr.size();
       gi.kb_first = (int)(out.recs.size() / REC);
       gi.rec_off = off;
@@ -569,22 +575,22 @@ static hipError_t allow_lds_mfma(const void *fn, bool *done, std::mutex *mu, int
   return e;
 }
 
-template <int NWD, int NWT, int NT, int RING, int SUB>
+template <int NWD, int NWT, int NT, int RING, int SUB, int WG>
 static hipError_t launch_mfma_cfg(const MfmaArgs &a, int nbatch, hipStream_t s) {
   static bool done[64] = {};
   static std::mutex mu;
-  hipError_t e = allow_lds_mfma((const void *)k_dedisp_mfma<NWD, NWT, NT, RING, SUB>, done, &mu,
-                                2 * kMfmaBufBytes);
+  hipError_t e = allow_lds_mfma((const void *)k_dedisp_mfma<NWD, NWT, NT, RING, SUB, WG>, done,
+                                &mu, 2 * (kMfmaBufBytes / WG));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_dedisp_mfma<NWD, NWT, NT, RING, SUB>), dim3(a.ntw * a.ntt, nbatch),
+  hipLaunchKernelGGL((k_dedisp_mfma<NWD, NWT, NT, RING, SUB, WG>), dim3(a.ntw * a.ntt, nbatch),
                      dim3(64 * NWD * NWT), 2 * a.bufbytes, s, a);
   return hipGetLastError();
 }
 
 static hipError_t launch_mfma(int ci, const MfmaArgs &a, int nbatch, hipStream_t s) {
   switch (ci) {
-#define DD_MFMA_CASE(i, x, y, z, r, h) \
-  case i: return launch_mfma_cfg<x, y, z, r, h>(a, nbatch, s);
+#define DD_MFMA_CASE(i, x, y, z, r, h, g) \
+  case i: return launch_mfma_cfg<x, y, z, r, h, g>(a, nbatch, s);
     DD_MFMA_CONFIGS(DD_MFMA_CASE)
 #undef DD_MFMA_CASE
     default: return hipErrorInvalidValue;
@@ -623,7 +629,7 @@ static void fill_args(dedisp_plan p, const MfmaCfgTables &c, const uint8_t *x, i
   a.in_stride = in_stride;
   a.nsamp = nsamp;
   a.ntw = c.ntw;
-  a.bufbytes = kMfmaBufBytes;
+  a.bufbytes = c.bufbytes;
   a.group_begin = c.d_group_begin;
   a.kbr = c.d_kbr;
   a.perm = c.d_perm;
@@ -692,22 +698,22 @@ size_t mfma_search_work_bytes(const dedisp_plan_s *p, int32_t nw, int64_t nout) 
 
 int mfma_search_count() { return kNumMfmaCfgs; }
 
-template <int NWD, int NWT, int NT, int RING, int SUB>
+template <int NWD, int NWT, int NT, int RING, int SUB, int WG>
 static hipError_t launch_search_cfg(const MfmaSearchArgs &sa, hipStream_t s) {
   static bool done[64] = {};
   static std::mutex mu;
-  hipError_t e = allow_lds_mfma((const void *)k_search_mfma<NWD, NWT, NT, RING, SUB>, done, &mu,
-                                2 * kMfmaBufBytes);
+  hipError_t e = allow_lds_mfma((const void *)k_search_mfma<NWD, NWT, NT, RING, SUB, WG>, done,
+                                &mu, 2 * (kMfmaBufBytes / WG));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_search_mfma<NWD, NWT, NT, RING, SUB>), dim3(sa.m.ntw * sa.m.ntt),
+  hipLaunchKernelGGL((k_search_mfma<NWD, NWT, NT, RING, SUB, WG>), dim3(sa.m.ntw * sa.m.ntt),
                      dim3(64 * NWD * NWT), 2 * sa.m.bufbytes, s, sa);
   return hipGetLastError();
 }
 
 static hipError_t launch_search_mfma(int k, const MfmaSearchArgs &sa, hipStream_t s) {
   switch (k) {
-#define DD_MFMA_SEARCH_CASE(i, x, y, z, r, h) \
-  case i: return launch_search_cfg<x, y, z, r, h>(sa, s);
+#define DD_MFMA_SEARCH_CASE(i, x, y, z, r, h, g) \
+  case i: return launch_search_cfg<x, y, z, r, h, g>(sa, s);
     DD_MFMA_CONFIGS(DD_MFMA_SEARCH_CASE)
 #undef DD_MFMA_SEARCH_CASE
     default: return hipErrorInvalidValue;

@@ -292,6 +292,27 @@ def test_fused_search_every_tile_config(dd, orc, cfg2_mid, tile):
     _check_detect(orc, yo, n, wl.widths, wl.chan_mean, wl.chan_sigma, snr, t, W)
 
 
+@pytest.fixture(scope="module")
+def cfg2_dense(orc):
+    wl = workloads.cfg2(nsamp=9000, ndm=300)
+    s = orc.delay_start(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms).astype(np.int32)
+    n = orc.taps_allnonzero(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms).astype(np.int32)
+    yo = orc.dedisperse_u8(wl.x, s, n).astype(np.float64)
+    return wl, n, yo
+
+
+@pytest.mark.parametrize("tile", [8, 9, 10])
+def test_matrix_core_search_shapes(dd, orc, cfg2_dense, tile):
+    # 300 trials (every matrix-core shape takes this plan: the 128-trial tiles of the
+    # two-workgroups-per-CU shape span too many samples at 100 trials), ragged time.
+    wl, n, yo = cfg2_dense
+    p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule="allnonzero")
+    p.set_tile(tile)
+    snr, t, W = p.search(_dev(wl.x), wl.widths, wl.chan_mean, wl.chan_sigma)
+    assert p.last_search_tile() == tile
+    _check_detect(orc, yo, n, wl.widths, wl.chan_mean, wl.chan_sigma, snr, t, W)
+
+
 def test_default_search_runs_on_the_matrix_cores(dd, orc, cfg2_mid):
     wl, n, yo = cfg2_mid
     p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule="allnonzero")
