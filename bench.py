@@ -233,8 +233,9 @@ def _other_workload(args, dd, workloads) -> int:
             x, _ = workloads.cfg4_beam_data(b, int(spec["nsamp"][b]), float(dms[0]), float(dms[-1]))
             plans.append(dd.Plan(f, 0.001, 1e-3, dms, rule="allnonzero"))
             xs.append(torch.from_numpy(x).cuda())
-        for p_ in plans:
-            p_.set_tile(plans[0].autotune(xs[0], list(range(1, 33)), np.full(C, 128.0), np.full(C, 16.0)))
+        # the batch's own choice: the matrix-core kernel when one of its shapes takes
+        # every beam (timed against the packed-add shapes on this workload: 48 against
+        # 63 ms), else the packed-add kernel
         widths = list(range(1, 33))
         B = dd.Batch(plans, [int(v) for v in spec["nsamp"]], widths)
         mu = torch.full((C,), 128.0, dtype=torch.float64, device="cuda")

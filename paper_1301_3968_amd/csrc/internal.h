@@ -188,6 +188,20 @@ dedisp_status run_search_mfma(dedisp_plan p, int k, const uint8_t *x, int64_t ns
                               int64_t in_stride, int64_t nout, const WidthList &wl,
                               const double *mu, const double *sigma, double *snr, int32_t *t,
                               int32_t *w, void *work, hipStream_t s);
+// Multi-beam fused search on the matrix cores (kernels_mfma.hip): one shape for all
+// beams (`prefer` if it takes them all, else the first that does); *out stays null
+// when no shape takes every beam.
+struct MfmaBatch;
+dedisp_status mfma_batch_create(const std::vector<dedisp_plan> &plans,
+                                const std::vector<int64_t> &nsamp, const WidthList &wl, int prefer,
+                                MfmaBatch **out);
+size_t mfma_batch_work_bytes(const MfmaBatch *B);
+dedisp_status mfma_batch_enqueue(MfmaBatch *B, const void *const *in, const int64_t *stride,
+                                 const double *mu, const double *sigma, double *snr, int32_t *t,
+                                 int32_t *w, const std::vector<int64_t> &out_off, void *work,
+                                 hipStream_t s, bool copy_args, KernelTimer *kt);
+dedisp_status mfma_batch_upload(MfmaBatch *B);
+void mfma_batch_free(MfmaBatch *B);
 // zbar[b][c][tau] = sum_d g[b][d][tau - start[d][c]] for tau in [0, nz) on the same
 // tiled kernel; DEDISP_ERR_UNSUPPORTED (launching nothing) when it does not fit.
 dedisp_status run_adjoint_z_tiled(dedisp_plan p, const float *g, int64_t nout, int64_t gstride,

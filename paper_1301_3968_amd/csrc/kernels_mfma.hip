@@ -198,8 +198,8 @@ struct TileAcc {
 // The products of DM tile tw over outputs T0 .. T0 + NWT * 16 NT - 1 (wave (wd, wt):
 // trials 16 wd .. 16 wd + 15 of the tile, outputs T0 + 16 NT wt + ...).  Ends with a
 // workgroup barrier, after which the LDS is free.
-template <int NWD, int NWT, int NT, int RING, int SUB, int WG>
-__device__ __forceinline__ TileAcc<SUB * NT> mfma_tile(const MfmaArgs &a, int tw, int64_t T0,
+template <int NWD, int NWT, int NT, int RING, int SUB, int WG, typename MA>
+__device__ __forceinline__ TileAcc<SUB * NT> mfma_tile(MA &a, int tw, int64_t T0,
                                                        const uint8_t *xb, unsigned char *lds) {
   constexpr int NW = NWD * NWT, REC = rec_bytes(SUB);
   const int tid = threadIdx.x, lane = tid & 63;
@@ -370,11 +370,8 @@ constexpr int search_step(int sp) { return 64 * sp - ((32 + sp - 1) / sp) * sp; 
 // then the boxcar search of every trial of the tile over starts T0 .. T0 + TT - 1.
 // The series go through LDS in two passes (the first, then the second half of every
 // wave's trials), as rows of TW + 32 ints; each wave searches whole rows.
-template <int NWD, int NWT, int NT, int RING, int SUB, int WG>
-__global__ void __launch_bounds__(64 * NWD * NWT)
-__attribute__((amdgpu_waves_per_eu(WG * NWD * NWT / 4, WG * NWD * NWT / 4)))
-k_search_mfma(MfmaSearchArgs sa) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+template <int NWD, int NWT, int NT, int RING, int SUB, int WG, typename SA>
+__device__ __forceinline__ void search_tile_mfma(SA &sa, int tt, int tw, unsigned char *lds) {
   constexpr int NW = NWD * NWT, TWV = 16 * NT, TW = NWT * TWV, SP = TW / 64;
   constexpr int TT = search_step(SP), YROW = TW + kHalo + 4;
   constexpr int PT = 8 * SUB;              // trials of one wave in one pass
@@ -382,9 +379,7 @@ k_search_mfma(MfmaSearchArgs sa) {
   static_assert(TW % 64 == 0 && TT % SP == 0 && TW - TT >= 31, "search tile");
   static_assert(ROWS % NW == 0, "whole rows per wave");
   static_assert(ROWS * YROW * 4 <= 2 * (kMfmaBufBytes / WG), "rows of one pass fit the LDS");
-  const MfmaArgs &a = sa.m;
-  int tt, tw;
-  tile_of_block(a.ntw, a.ntt, &tt, &tw);
+  auto &a = sa.m;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wd = wave % NWD, wt = wave / NWD;
@@ -421,6 +416,46 @@ k_search_mfma(MfmaSearchArgs sa) {
     }
     __syncthreads();
   }
+}
+
+template <int NWD, int NWT, int NT, int RING, int SUB, int WG>
+__global__ void __launch_bounds__(64 * NWD * NWT)
+__attribute__((amdgpu_waves_per_eu(WG * NWD * NWT / 4, WG * NWD * NWT / 4)))
+k_search_mfma(MfmaSearchArgs sa) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  int tt, tw;
+  tile_of_block(sa.m.ntw, sa.m.ntt, &tt, &tw);
+  search_tile_mfma<NWD, NWT, NT, RING, SUB, WG>(sa, tt, tw, lds);
+}
+
+// Multi-beam fused search: one workgroup per (beam, tile).  Beam b owns the blocks
+// [base[b], base[b] + its tile count rounded up to 8), base[b] a multiple of 8, so that
+// block i of a beam runs on XCD i mod 8 and the beam's tiles take the one-beam
+// kernel's XCD-aware order.  Blocks past a beam's tile count exit at once (the whole
+// workgroup, before any barrier).
+template <int NWD, int NWT, int NT, int RING, int SUB, int WG>
+__global__ void __launch_bounds__(64 * NWD * NWT)
+__attribute__((amdgpu_waves_per_eu(WG * NWD * NWT / 4, WG * NWD * NWT / 4)))
+k_search_mfma_batch(const MfmaSearchArgs *__restrict__ beams, const int32_t *__restrict__ base,
+                    int32_t nbeam) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  const int bi = blockIdx.x;
+  int lo = 0, hi = nbeam - 1;   // last beam whose first block <= bi
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ldc(base, mid) <= bi) lo = mid; else hi = mid - 1;
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  // the argument table is read through the constant address space (scalar loads)
+  typedef const __attribute__((address_space(4))) MfmaSearchArgs CArgs;
+  CArgs &sa = ((CArgs *)beams)[lo];
+  const int nb = sa.m.ntw * sa.m.ntt;
+  const int kl = bi - ldc(base, lo);
+  const int xcd = kl & 7, k = kl >> 3, q = nb >> 3, rem = nb & 7;
+  if (k >= q + (xcd < rem ? 1 : 0)) return;
+  const int L = xcd * q + min(xcd, rem) + k;
+  const int tt = L / sa.m.ntw, tw = L - tt * sa.m.ntw;
+  search_tile_mfma<NWD, NWT, NT, RING, SUB, WG>(sa, tt, tw, lds);
 }
 
 }  // namespace
@@ -751,6 +786,164 @@ dedisp_status run_search_mfma(dedisp_plan p, int k, const uint8_t *x, int64_t ns
   DD_HIP(launch_search_mfma(k, sa, s));
   DD_HIP(kt.end());
   DD_HIP(launch_reduce(p->ndm, (int32_t)L.ntt, sa.part, snr, t, w, s));
+  return DEDISP_OK;
+}
+
+// ---- multi-beam fused search -------------------------------------------------------
+struct MfmaBatch {
+  int k = 0;                                // matrix-core shape
+  int nbeam = 0;
+  std::vector<dedisp_plan> plans;
+  std::vector<int64_t> nsamp, nout;
+  std::vector<size_t> off;                  // workspace offset of each beam
+  std::vector<MfmaSearchLayout> lay;
+  std::vector<int32_t> base;                // first block of each beam, then the total
+  WidthList wl{};
+  size_t work_bytes = 0;
+  int32_t *d_base = nullptr;
+  MfmaSearchArgs *d_args = nullptr;
+  std::vector<MfmaSearchArgs> args;         // argument table of the last enqueue
+};
+
+void mfma_batch_free(MfmaBatch *B) {
+  if (!B) return;
+  (void)hipFree(B->d_base);
+  (void)hipFree(B->d_args);
+  delete B;
+}
+
+size_t mfma_batch_work_bytes(const MfmaBatch *B) { return B->work_bytes; }
+
+dedisp_status mfma_batch_create(const std::vector<dedisp_plan> &plans,
+                                const std::vector<int64_t> &nsamp, const WidthList &wl, int prefer,
+                                MfmaBatch **out) {
+  *out = nullptr;
+  if (wl.w[wl.n - 1] > 32) return DEDISP_OK;
+  // the preferred shape, else the first that takes every beam
+  std::vector<int> order;
+  if (prefer >= 0 && prefer < kNumMfmaCfgs) order.push_back(prefer);
+  for (int k = 0; k < kNumMfmaCfgs; ++k)
+    if (k != prefer) order.push_back(k);
+  int chosen = -1;
+  for (int k : order) {
+    bool all = true;
+    for (dedisp_plan p : plans) {
+      if (p->wmode != DEDISP_W_UNIT) return DEDISP_OK;
+      MfmaCfgTables *cfg = nullptr;
+      std::lock_guard<std::mutex> lk(p->mu);
+      dedisp_status st = ensure_mfma(p, k, &cfg);
+      if (st != DEDISP_OK) return st;
+      if (!cfg) {
+        all = false;
+        break;
+      }
+    }
+    if (all) {
+      chosen = k;
+      break;
+    }
+  }
+  if (chosen < 0) return DEDISP_OK;
+  MfmaBatch *B = new (std::nothrow) MfmaBatch;
+  if (!B) return fail(DEDISP_ERR_OOM, "host allocation failed");
+  B->k = chosen;
+  B->nbeam = (int)plans.size();
+  B->plans = plans;
+  B->nsamp = nsamp;
+  B->wl = wl;
+  size_t off = 0;
+  int64_t blocks = 0;
+  for (int b = 0; b < B->nbeam; ++b) {
+    dedisp_plan p = plans[b];
+    const int64_t no = nsamp[b] - p->max_span + 1;
+    B->nout.push_back(no);
+    const MfmaSearchLayout L = search_layout(p, chosen, wl.n, no);
+    B->lay.push_back(L);
+    B->off.push_back(off);
+    off += (L.total + 255) & ~(size_t)255;
+    B->base.push_back((int32_t)blocks);
+    const int64_t nb = ((int64_t)p->mfma->cfg[chosen].ntw * L.ntt + 7) & ~(int64_t)7;
+    blocks += nb;
+    if (blocks > INT32_MAX / 2) {
+      mfma_batch_free(B);
+      return DEDISP_OK;   // too many tiles for one launch: not this path
+    }
+  }
+  B->base.push_back((int32_t)blocks);
+  B->work_bytes = off;
+  hipError_t e = upload(&B->d_base, B->base);
+  if (e == hipSuccess) e = hipMalloc((void **)&B->d_args, sizeof(MfmaSearchArgs) * B->nbeam);
+  if (e != hipSuccess) {
+    mfma_batch_free(B);
+    return hip_fail(e, "batch setup");
+  }
+  *out = B;
+  return DEDISP_OK;
+}
+
+template <int NWD, int NWT, int NT, int RING, int SUB, int WG>
+static hipError_t launch_batch_mfma_cfg(const MfmaBatch *B, hipStream_t s) {
+  static bool done[64] = {};
+  static std::mutex mu;
+  hipError_t e = allow_lds_mfma((const void *)k_search_mfma_batch<NWD, NWT, NT, RING, SUB, WG>, done,
+                                &mu, 2 * (kMfmaBufBytes / WG));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_search_mfma_batch<NWD, NWT, NT, RING, SUB, WG>), dim3(B->base.back()),
+                     dim3(64 * NWD * NWT), 2 * (kMfmaBufBytes / WG), s, B->d_args, B->d_base,
+                     B->nbeam);
+  return hipGetLastError();
+}
+
+static hipError_t launch_batch_mfma(const MfmaBatch *B, hipStream_t s) {
+  switch (B->k) {
+#define DD_MFMA_BATCH_CASE(i, x, y, z, r, h, g) \
+  case i: return launch_batch_mfma_cfg<x, y, z, r, h, g>(B, s);
+    DD_MFMA_CONFIGS(DD_MFMA_BATCH_CASE)
+#undef DD_MFMA_BATCH_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Noise tables of every beam, the argument table (copied when copy_args), one launch
+// over every beam's tiles, the per-beam reductions.  Outputs of beam b start at
+// out_off[b].
+dedisp_status mfma_batch_enqueue(MfmaBatch *B, const void *const *in, const int64_t *stride,
+                                 const double *mu, const double *sigma, double *snr, int32_t *t,
+                                 int32_t *w, const std::vector<int64_t> &out_off, void *work,
+                                 hipStream_t s, bool copy_args, KernelTimer *kt) {
+  B->args.assign(B->nbeam, MfmaSearchArgs{});
+  for (int b = 0; b < B->nbeam; ++b) {
+    dedisp_plan p = B->plans[b];
+    const MfmaCfgTables &c = p->mfma->cfg[B->k];
+    MfmaSearchArgs &sa = B->args[b];
+    fill_args(p, c, (const uint8_t *)in[b], B->nsamp[b], stride[b], B->nout[b], sa.m);
+    sa.m.ntt = (int32_t)B->lay[b].ntt;
+    double *M = (double *)((char *)work + B->off[b]);
+    sa.M = M;
+    sa.S = M + (size_t)p->ndm * B->wl.n;
+    sa.nw = B->wl.n;
+    sa.wmask = 0;
+    for (int i = 0; i < B->wl.n; ++i) sa.wmask |= 1u << (B->wl.w[i] - 1);
+    sa.part = (CandRec *)((char *)work + B->off[b] + B->lay[b].off_part);
+    DD_HIP(launch_norm(p, B->wl, mu, sigma, M, (double *)sa.S, s));
+  }
+  if (copy_args)
+    DD_HIP(hipMemcpyAsync(B->d_args, B->args.data(), sizeof(MfmaSearchArgs) * B->nbeam,
+                          hipMemcpyHostToDevice, s));
+  if (kt) DD_HIP(kt->begin());
+  DD_HIP(launch_batch_mfma(B, s));
+  if (kt) DD_HIP(kt->end());
+  for (int b = 0; b < B->nbeam; ++b) {
+    const int64_t o = out_off[b];
+    DD_HIP(launch_reduce(B->plans[b]->ndm, B->args[b].m.ntt, B->args[b].part, snr + o, t + o,
+                         w + o, s));
+  }
+  return DEDISP_OK;
+}
+
+dedisp_status mfma_batch_upload(MfmaBatch *B) {
+  DD_HIP(hipMemcpy(B->d_args, B->args.data(), sizeof(MfmaSearchArgs) * B->nbeam,
+                   hipMemcpyHostToDevice));
   return DEDISP_OK;
 }
 

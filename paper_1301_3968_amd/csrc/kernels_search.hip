@@ -856,6 +856,7 @@ dedisp_status dedisp_set_tile(dedisp_plan p, int32_t tile) {
 // ------------------------------------------------------------------------------
 struct dedisp_batch_s {
   int32_t nbeam = 0, nchan = 0, ci = 0;
+  dd::MfmaBatch *mb = nullptr;      // the matrix-core path, when it takes every beam
   std::vector<dedisp_plan> plans;
   std::vector<int64_t> nsamp, nout;
   dd::WidthList wl{};
@@ -913,6 +914,11 @@ static dedisp_status batch_enqueue(dedisp_batch_s *B, const void *const *in, con
                                    const double *mu, const double *sigma, double *snr, int32_t *t,
                                    int32_t *w, void *work, hipStream_t s, bool copy_args,
                                    std::vector<SearchArgs> &args) {
+  if (B->mb) {
+    KernelTimer kt(B->plans[0], s);
+    return mfma_batch_enqueue(B->mb, in, stride, mu, sigma, snr, t, w, B->out_off, work, s,
+                              copy_args, &kt);
+  }
   args.assign(B->nbeam, SearchArgs{});
   uint16_t *urows = (uint16_t *)((char *)work + B->u_off);
   for (int b = 0; b < B->nbeam; ++b) {
@@ -983,6 +989,35 @@ dedisp_status dedisp_batch_create(dedisp_batch *out, int32_t nbeam, const dedisp
   for (int i = 0; i < B->wl.n; ++i) B->wl.w[i] = wv[i];
   B->ci = valu_index(plans[0]);
   dedisp_status st = DEDISP_OK;
+  // The matrix-core kernel unless the first plan forces the packed-add kernel or the
+  // general path, or no matrix-core shape takes every beam.
+  const int tc = plans[0]->tile_choice;
+  if (tc != -2 && (tc < 0 || tc >= kNumCfgs)) {
+    for (int b = 0; b < nbeam && st == DEDISP_OK; ++b) {
+      if (!search_supported(plans[b], B->wl))
+        st = fail(DEDISP_ERR_UNSUPPORTED, "a beam's plan cannot use the tiled search");
+      else
+        st = ensure_device(plans[b]);
+    }
+    if (st == DEDISP_OK)
+      st = mfma_batch_create(B->plans, B->nsamp, B->wl, tc >= kNumCfgs ? tc - kNumCfgs : 0, &B->mb);
+    if (st != DEDISP_OK) {
+      dedisp_batch_destroy(B);
+      return st;
+    }
+    if (B->mb) {
+      for (int b = 0; b < nbeam; ++b) {
+        const int64_t no = nsamp[b] - plans[b]->max_span + 1;
+        B->nout.push_back(no);
+        B->out_off.push_back(B->total_trials);
+        B->total_trials += plans[b]->ndm;
+        B->total_sums += (int64_t)plans[b]->ndm * plans[b]->nchan * no;
+      }
+      B->work_bytes = mfma_batch_work_bytes(B->mb);
+      *out = B;
+      return DEDISP_OK;
+    }
+  }
   size_t off = 0;
   std::vector<size_t> rows;      // window-row bytes of each beam
   std::vector<int64_t> blocks;   // workgroups of each beam (a multiple of 8)
@@ -1077,6 +1112,7 @@ dedisp_status dedisp_batch_destroy(dedisp_batch B) {
   if (B->ev_out) (void)hipEventDestroy(B->ev_out);
   (void)hipFree(B->d_tile_begin);
   (void)hipFree(B->d_args);
+  dd::mfma_batch_free(B->mb);
   delete B;
   return DEDISP_OK;
 }
@@ -1152,7 +1188,12 @@ dedisp_status dedisp_batch_run(dedisp_batch B, const void *const *d_in, const in
     if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
     B->graph = g;
     DD_HIP(hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0));
-    DD_HIP(hipMemcpy(B->d_args, args.data(), sizeof(SearchArgs) * B->nbeam, hipMemcpyHostToDevice));
+    if (B->mb) {
+      const dedisp_status su = mfma_batch_upload(B->mb);
+      if (su != DEDISP_OK) return su;
+    } else {
+      DD_HIP(hipMemcpy(B->d_args, args.data(), sizeof(SearchArgs) * B->nbeam, hipMemcpyHostToDevice));
+    }
     B->key = key;
   }
   DD_HIP(hipEventRecord(B->ev_in, s));

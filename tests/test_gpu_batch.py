@@ -1,4 +1,4 @@
-"""Batched persistent search over many beams (own DM grids from the trial-DM rule,
+"""Batched search over many beams (own DM grids from the trial-DM rule,
 uneven lengths), eager and replayed from a HIP graph, checked against the oracle;
 and the tile autotuner."""
 import math
@@ -62,11 +62,18 @@ def _check(orc, beams_, widths, snr, t, W):
         off += D
 
 
-def test_batch_eager_and_graph_replays(dd, orc, beams):
+@pytest.mark.parametrize("kernel", ["matrix", "packed"])
+def test_batch_eager_and_graph_replays(dd, orc, beams, kernel):
     import torch
     C, bl = beams
     widths = list(range(1, 33))
-    B = dd.Batch([b[0] for b in bl], [b[1].shape[1] for b in bl], widths)
+    # the batch takes the matrix-core kernel unless the first plan forces a packed-add shape
+    if kernel == "packed":
+        bl[0][0].set_tile(4)
+    try:
+        B = dd.Batch([b[0] for b in bl], [b[1].shape[1] for b in bl], widths)
+    finally:
+        bl[0][0].set_tile(-1)
     assert B.total_trials == sum(b[0].ndm for b in bl)
     xs = [_dev(b[1]) for b in bl]
     mu = torch.full((C,), 128.0, dtype=torch.float64, device="cuda")
