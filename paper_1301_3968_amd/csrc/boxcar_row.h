@@ -18,6 +18,61 @@ struct CandRec {
   int32_t w;
 };
 
+// Earliest start i < SP (of this lane) whose width-W window, qv[i + W] - qv[i], equals
+// b and lies inside the valid outputs (i + W <= lim); -1 if none.
+template <int SP, int W>
+__device__ __forceinline__ int first_start(const int *qv, int b, int lim) {
+  int first = -1;
+#pragma unroll
+  for (int i = SP - 1; i >= 0; --i)
+    if (i + W <= lim && qv[i + W] - qv[i] == b) first = i;
+  return first;
+}
+
+// first_start for a wave-uniform width w in [LO, HI], by a binary tree of uniform
+// branches (register arrays cannot be indexed by a run-time value).
+template <int SP, int LO, int HI>
+__device__ __forceinline__ int first_start_of(int w, const int *qv, int b, int lim) {
+  if constexpr (LO == HI) {
+    return first_start<SP, LO>(qv, b, lim);
+  } else {
+    constexpr int MID = (LO + HI) / 2;
+    if (w <= MID) return first_start_of<SP, LO, MID>(w, qv, b, lim);
+    return first_start_of<SP, MID + 1, HI>(w, qv, b, lim);
+  }
+}
+
+// One step of a wave maximum of a double: the larger of x and the value the
+// 32-bit lane movement F brings to this lane (applied to both halves).
+template <typename F>
+__device__ __forceinline__ double dmax_step(double x, F move) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = move((uint32_t)u), hi = move((uint32_t)(u >> 32));
+  const double o = __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+  return __builtin_fmax(x, o);
+}
+
+// The larger of the two doubles a permlane swap of x with itself gives this lane
+// (the lane's own value and its partner's, in some order).
+template <bool P32>
+__device__ __forceinline__ double dmax_swap(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+  uint32_t l0, l1, h0, h1;
+  if constexpr (P32) {
+    const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    l0 = pl[0]; l1 = pl[1]; h0 = ph[0]; h1 = ph[1];
+  } else {
+    const auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    l0 = pl[0]; l1 = pl[1]; h0 = ph[0]; h1 = ph[1];
+  }
+  const double a = __builtin_bit_cast(double, ((uint64_t)h0 << 32) | l0);
+  const double b = __builtin_bit_cast(double, ((uint64_t)h1 << 32) | l1);
+  return __builtin_fmax(a, b);
+}
+
 // Yw (16-byte aligned) holds the TY = 64 SP outputs of the tile (outputs t0 .. t0 + TY - 1, written by
 // this wave before the call, or by any wave before a workgroup barrier), followed by
 // kHalo ints that this function sets to zero.  The tile owns starts t0 .. t0 + TT - 1
@@ -32,6 +87,17 @@ __device__ __forceinline__ CandRec boxcar_row(int *Yw, int lane, int64_t t0, int
                                               const double *__restrict__ M,
                                               const double *__restrict__ S) {
   constexpr int TY = 64 * SP;
+  // The width this lane speaks for in the S/N step: register index from lane bits
+  // 1-4, pair member from bit 5 (lanes l and l ^ 1 agree); its index in the sorted
+  // width list is the number of listed widths below it.  Its noise mean and
+  // deviation are loaded first, so that the loads are in flight during the sums.
+  const int wl = 2 * ((lane >> 1) & 15) + (lane >> 5) + 1;
+  const int ji = ((wmask >> (wl - 1)) & 1u) ? __popc(wmask & ((1u << (wl - 1)) - 1u)) : -1;
+  double nm = 0.0, ns = 1.0;
+  if (ji >= 0 && dg >= 0) {
+    nm = M[(int64_t)dg * nw + ji];
+    ns = S[(int64_t)dg * nw + ji];
+  }
   if (lane < kHalo) Yw[TY + lane] = 0;
   // Only the tile holding the end of the series sees outputs past the last valid
   // one.  Elsewhere every prefix entry is a real output, except the zero halo past
@@ -113,30 +179,40 @@ __device__ __forceinline__ CandRec boxcar_row(int *Yw, int lane, int64_t t0, int
   }
   // lanes l, l ^ 1 (quad permutation 1, 0, 3, 2)
   const int bmax = max(mw[0], __builtin_amdgcn_update_dpp(0, mw[0], 0xb1, 0xf, 0xf, false));
-  // the width this lane speaks for: register index from lane bits 1-4, pair
-  // member from bit 5 (lanes l and l ^ 1 agree)
-  const int wl = 2 * ((lane >> 1) & 15) + (lane >> 5) + 1;
-  // index of width wl in the sorted width list = number of listed widths below it
-  const int ji = ((wmask >> (wl - 1)) & 1u) ? __popc(wmask & ((1u << (wl - 1)) - 1u)) : -1;
+  // S/N of the width this lane speaks for (NaN, as from 0 / 0, never wins: -inf)
   double snr = -INFINITY;
-  if (ji >= 0 && bmax >= 0 && dg >= 0)
-    snr = ((double)bmax - M[(int64_t)dg * nw + ji]) / S[(int64_t)dg * nw + ji];
-  // wave argmax over (snr desc, W asc); every lane ends with the result
-  int bw = wl, bb = bmax;
-#pragma unroll
-  for (int sh = 2; sh < 64; sh <<= 1) {
-    const double os = __shfl_xor(snr, sh, 64);
-    const int ow = __shfl_xor(bw, sh, 64), ob = __shfl_xor(bb, sh, 64);
-    if (os > snr || (os == snr && ow < bw)) {
-      snr = os;
-      bw = ow;
-      bb = ob;
-    }
+  if (ji >= 0 && bmax >= 0 && dg >= 0) {
+    const double r = ((double)bmax - nm) / ns;
+    if (!__builtin_isnan(r)) snr = r;
   }
-  // earliest start of the winning width in this tile: a sliding window of width
-  // bw over this lane's outputs (only valid windows, i + bw <= lim, can match)
+  // wave maximum of the S/N over the widths, every lane ending with it
+  double smax = snr;
+  smax = dmax_step(smax, [](uint32_t v) {   // lanes l, l ^ 2 (quad permutation 2, 3, 0, 1)
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, false);
+  });
+  smax = dmax_step(smax, [](uint32_t v) {   // quads q, q + 1 of a row (rotation by 4)
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xf, 0xf, false);
+  });
+  smax = dmax_step(smax, [](uint32_t v) {   // the whole row (rotation by 8)
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false);
+  });
+  smax = dmax_swap<false>(smax);            // rows 2 k, 2 k + 1
+  smax = dmax_swap<true>(smax);             // all four rows
+  CandRec rec;
+  rec.snr = -INFINITY;
+  rec.t = -1;
+  rec.w = 0;
+  if (smax == -INFINITY) return rec;        // no valid window of a listed width
+  // the smallest width with that S/N: lane 2 r (+ 1) speaks for width 2 r + 1,
+  // lane 32 + 2 r (+ 1) for width 2 r + 2, so bit W - 1 of wbits is width W's
+  const uint64_t hit = __ballot(snr == smax);
+  const uint32_t wbits = ((uint32_t)hit & 0x55555555u) | (((uint32_t)(hit >> 32) & 0x55555555u) << 1);
+  const int bw = __builtin_amdgcn_readfirstlane(__builtin_ctz(wbits) + 1);
+  const int bb = __builtin_amdgcn_readlane(bmax, 32 * ((bw - 1) & 1) + ((bw - 1) & ~1));
+  // earliest start of a window of width bw and sum bb: per lane from the prefix,
+  // then the lowest lane that has one
   int first = -1;
-  if (snr != -INFINITY) {
+  {
     int B = 0;
     for (int k = 0; k < bw; ++k) B += yl[k];
 #pragma unroll
@@ -145,17 +221,12 @@ __device__ __forceinline__ CandRec boxcar_row(int *Yw, int lane, int64_t t0, int
       B += yl[i + bw] - yl[i];
     }
   }
-  const unsigned long long hit = __ballot(first >= 0);
-  int tbest = -1;
-  if (hit != 0ull) {
-    const int fl = __builtin_ctzll(hit);
-    const int fi = __shfl(first, fl, 64);
-    tbest = (int)(t0 + fl * SP + fi);
-  }
-  CandRec rec;
-  rec.snr = (hit != 0ull) ? snr : -INFINITY;
-  rec.t = (hit != 0ull) ? tbest : -1;
-  rec.w = (hit != 0ull) ? bw : 0;
+  const uint64_t fh = __ballot(first >= 0);
+  if (fh == 0ull) return rec;
+  const int fl = __builtin_amdgcn_readfirstlane(__builtin_ctzll(fh));
+  rec.snr = smax;
+  rec.t = (int)(t0 + fl * SP + __builtin_amdgcn_readlane(first, fl));
+  rec.w = bw;
   return rec;
 }
 

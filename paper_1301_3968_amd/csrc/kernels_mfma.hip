@@ -11,18 +11,21 @@
 // trial's result is corrected by 128 times its number of samples, so the int32 result
 // is exact.
 //
-// One workgroup takes 16 SUB NWD trials x NWT * 16 NT outputs; each wave 16 SUB trials
-// x 16 NT outputs, its SUB halves of 16 trials sharing the segments (the band of all
-// its trials), so that every 16-byte sample read feeds SUB products.  Channel groups are staged into LDS (two buffers: the next group is loaded
-// while the current one is multiplied) as 16 byte-shifted copies of each channel's
-// window, so that the 16 samples a lane needs (window bytes i .. i + 15) are one aligned
-// 16-byte read: the copies are interleaved per 16-byte chunk, chunk q of copy p at
-// 256 q + 16 p, so the 16 lanes of a segment (i = r .. r + 15) read 16 different bank
-// slots.  The host plans, per group of 4 segments (a K block), a 160-byte record: the
-// 16-bit mask of every (trial, segment) (which of the segment's 16 delays the trial
-// takes) and where each segment's window sits in LDS; the records of a channel group
-// are copied into LDS with the windows, and every lane forms its 16 mask bytes and its
-// read address from them.
+// One wave takes 16 trials x 256 outputs as 16 products (blocks b < 16); column n of
+// block b is output 16 n + b of the wave's run.  So lane n of a segment needs window
+// bytes o + 16 n + b .. o + 16 n + b + 15 for block b: for all 16 blocks, the 32 bytes
+// from o + 16 n, two aligned 16-byte LDS reads when o is a multiple of 16; block b then
+// takes bytes b .. b + 15 of them, a shift by b that is the same for every lane (three
+// byte-align operations per dword, none when b is a multiple of 4).  Segment starts are
+// put on a 4-byte grid (one or two more segments than the band needs, rarely), and each
+// channel's window is staged into LDS as 4 copies shifted by 0, 4, 8 and 12 bytes, so
+// the copy (o / 4) mod 4 holds the segment's bytes at 16-byte alignment.  Channel groups
+// are staged while the previous group is multiplied (two LDS buffers).  The host plans,
+// per group of 4 segments (a K block), a 144-byte record: the 16-bit mask of every
+// (trial, segment) (which of the segment's 16 delays the trial takes) and the LDS
+// address of each segment's aligned bytes; the records of a channel group are copied
+// into LDS with the windows, and every lane forms its 16 mask bytes and its read
+// address from them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,29 +40,31 @@
 
 namespace dd {
 
-// Workgroup shapes: NWD waves along DM, NWT along time, NT blocks of 16 outputs per wave,
-// RING 16-byte sample reads in flight per wave, SUB halves of 16 trials per wave, WG
-// workgroups per CU (each with 1 / WG of the CU's LDS).
-#define DD_MFMA_CONFIGS(X)     \
-  X(0, 8, 2, 16, 4, 1, 1)      \
-  X(1, 16, 1, 16, 4, 1, 1)     \
-  X(2, 8, 1, 16, 4, 1, 2)
+// Workgroup shapes: NWD waves along DM (16 trials each), NWT along time (256 outputs
+// each), WG workgroups per CU (each with 1 / WG of the CU's LDS).
+#define DD_MFMA_CONFIGS(X) \
+  X(0, 8, 2, 1)            \
+  X(1, 16, 1, 1)           \
+  X(2, 8, 1, 2)
 struct MfmaCfg {
-  int nwd, nwt, nt, ring, sub, wg;
+  int nwd, nwt, wg;
 };
-#define DD_MFMA_ENTRY(i, a, b, c, r, h, g) {a, b, c, r, h, g},
+#define DD_MFMA_ENTRY(i, a, b, g) {a, b, g},
 static const MfmaCfg kMfmaCfgs[] = {DD_MFMA_CONFIGS(DD_MFMA_ENTRY)};
 #undef DD_MFMA_ENTRY
 constexpr int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
-constexpr int kPhases = 16;                 // byte-shifted copies of each staged window
+constexpr int kNT = 16;                     // products (blocks) per wave and K block
+constexpr int kTWV = 16 * kNT;              // outputs per wave
+constexpr int kCopies = 4;                  // dword-shifted copies of each staged window
 constexpr int kMfmaBufBytes = 80 * 1024;    // LDS per staging buffer (two per workgroup) at
                                             // one workgroup per CU
-// K-block record: per half 64 x u16 masks (lane = 16 segment + trial row), then 4 x
-// (region, rel) for the segments
-constexpr int rec_bytes(int sub) { return 128 * sub + 32; }
-// Staging tasks (quarter chunks) per thread: a buffer of `buf` bytes holds at most
-// buf / 256 chunks of 16 copies, 4 tasks each.
-constexpr int max_tasks(int nw, int buf) { return (4 * (buf / 256) + 64 * nw - 1) / (64 * nw); }
+// K-block record: 64 x u16 masks (lane = 16 segment + trial row), then the LDS byte
+// address of each of the 4 segments' aligned bytes (lane 16 g + n reads 32 bytes at
+// address[g] + 16 n)
+constexpr int kRecBytes = 144;
+// Staging: one chunk (16 window bytes in all 4 copies) per thread and group, so a
+// group stages at most 64 NW chunks (registers: the chunk's raw bytes are held through
+// the current group's products).
 
 struct MGroup {
   int32_t unit_begin, nunits;   // staging units (16 window bytes of one channel each)
@@ -71,8 +76,8 @@ struct MGroup {
 struct MUnit {
   int32_t c;      // channel
   int32_t src;    // first window sample of the chunk, relative to the tile's first output
-  int32_t dst;    // LDS byte offset of the chunk's 256-byte block (16 copies of 16 bytes)
-  int32_t pad;
+  int32_t dst;    // LDS byte offset of the chunk in copy 0
+  int32_t cs;     // bytes between the copies of the channel's window
 };
 
 struct MfmaCfgTables {
@@ -81,9 +86,8 @@ struct MfmaCfgTables {
   std::vector<int32_t> perm, ntot, group_begin, kbr;
   std::vector<MGroup> groups;
   std::vector<MUnit> units;
-  int rec = 0;                    // record bytes
   int bufbytes = 0;               // LDS bytes of one staging buffer
-  std::vector<uint8_t> recs;      // [kb][rec]
+  std::vector<uint8_t> recs;      // [kb][kRecBytes]
   int32_t *d_perm = nullptr, *d_ntot = nullptr, *d_group_begin = nullptr, *d_kbr = nullptr;
   MGroup *d_groups = nullptr;
   MUnit *d_units = nullptr;
@@ -118,7 +122,8 @@ constexpr int kBufWord3 = 0x00020000;      // raw 32-bit buffer descriptor word 
 struct MfmaArgs {
   const uint8_t *x;
   int64_t in_stride, in_bstride, nsamp;
-  int32_t ntw, ntt, bufbytes, pad0;
+  int32_t ntw, ntt, bufbytes;
+  int32_t vec_out;        // out, out_stride and out_bstride allow 16-byte stores
   const int32_t *group_begin, *kbr, *perm, *ntot;
   const MGroup *groups;
   const MUnit *units;
@@ -132,10 +137,10 @@ __device__ __forceinline__ T ldc(const T *p, int64_t i) {
   return ((const __attribute__((address_space(4))) T *)p)[i];
 }
 
-// The 24 bytes of the row from the 4-byte aligned address at or below row + pos (pos
-// may be past the row; bytes outside [0, nsamp) read as 0), as 6 dwords.
+// The 32 bytes of the row from the 4-byte aligned address at or below row + pos (pos
+// may be past the row; bytes outside [0, nsamp) read as 0), as 8 dwords.
 __device__ __forceinline__ void load_raw(const uint8_t *row, int64_t nsamp, int64_t pos,
-                                         uint32_t raw[6], int *sh) {
+                                         uint32_t raw[8], int *sh) {
   const uintptr_t abs = (uintptr_t)(row + pos);
   *sh = (int)(abs & 3);
   const int64_t p0 = pos - *sh;   // row-relative position of the aligned first byte
@@ -143,12 +148,12 @@ __device__ __forceinline__ void load_raw(const uint8_t *row, int64_t nsamp, int6
   // and force full LDS waits in the product loop while they are in flight
   const __attribute__((address_space(1))) uint32_t *a =
       (const __attribute__((address_space(1))) uint32_t *)(abs - *sh);
-  if (p0 >= 0 && p0 + 24 <= nsamp) {
+  if (p0 >= 0 && p0 + 32 <= nsamp) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) raw[k] = a[k];
+    for (int k = 0; k < 8; ++k) raw[k] = a[k];
   } else {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < 8; ++k) {
       uint32_t v = 0;
       for (int j = 0; j < 4; ++j) {
         const int64_t q = p0 + 4 * k + j;
@@ -159,23 +164,19 @@ __device__ __forceinline__ void load_raw(const uint8_t *row, int64_t nsamp, int6
   }
 }
 
-// One staging task: copies 4h .. 4h + 3 of a chunk (copy p = window bytes p .. p + 15
-// of the chunk, as int8 x ^ 0x80), from the 24 raw bytes at the chunk start + 4h.  The
-// copies are written in an order rotated by the chunk index, so that the lanes of one
-// write instruction fall on different bank slots.
-__device__ __forceinline__ void store_task(unsigned char *buf, int32_t dst, int h, int rot,
-                                           const uint32_t raw[6], int sh) {
-  uint32_t e[5];
+// One staging task: chunk k of the 4 copies of a window (copy p: window bytes 16 k + 4 p
+// .. 16 k + 4 p + 15, as int8 x ^ 0x80), from the raw bytes at the aligned address at or
+// below window byte 16 k.  dst: the chunk's offset in copy 0; cs: bytes between copies.
+__device__ __forceinline__ void store_chunk(unsigned char *buf, int32_t dst, int32_t cs,
+                                            const uint32_t raw[8], int sh) {
+  uint32_t e[7];
 #pragma unroll
-  for (int k = 0; k < 5; ++k)
+  for (int k = 0; k < 7; ++k)
     e[k] = __builtin_amdgcn_alignbyte(raw[k + 1], raw[k], (uint32_t)sh) ^ 0x80808080u;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int s = (j + rot) & 3;
-    v4i v;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) v[m] = (int32_t)__builtin_amdgcn_alignbyte(e[m + 1], e[m], (uint32_t)s);
-    *(v4i *)(buf + dst + 16 * (4 * h + s)) = v;
+  for (int p = 0; p < kCopies; ++p) {
+    const v4i v = {(int32_t)e[p], (int32_t)e[p + 1], (int32_t)e[p + 2], (int32_t)e[p + 3]};
+    *(v4i *)(buf + dst + p * cs) = v;
   }
 }
 
@@ -195,21 +196,47 @@ struct TileAcc {
   v4i v[N];
 };
 
-// The products of DM tile tw over outputs T0 .. T0 + NWT * 16 NT - 1 (wave (wd, wt):
-// trials 16 wd .. 16 wd + 15 of the tile, outputs T0 + 16 NT wt + ...).  Ends with a
+typedef int32_t v8i __attribute__((ext_vector_type(8)));
+
+// The lane's 32 bytes shifted down by S bytes (dwords 0..6; dword 7 unused).
+template <int S>
+__device__ __forceinline__ v8i shifted(const v8i &w) {
+  v8i r;
+#pragma unroll
+  for (int k = 0; k < 7; ++k)
+    r[k] = (int32_t)__builtin_amdgcn_alignbyte((uint32_t)w[k + 1], (uint32_t)w[k], (uint32_t)S);
+  r[7] = 0;
+  return r;
+}
+
+// The products of blocks S, S + 4, S + 8, S + 12 (samples: dwords q .. q + 3 of ws for
+// block 4 q + S).
+template <int S>
+__device__ __forceinline__ void mfma4(v4i (&acc)[kNT], const v4i &mk, const v8i &ws) {
+  acc[S] = __builtin_amdgcn_mfma_i32_16x16x64_i8(mk, __builtin_shufflevector(ws, ws, 0, 1, 2, 3),
+                                                 acc[S], 0, 0, 0);
+  acc[S + 4] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+      mk, __builtin_shufflevector(ws, ws, 1, 2, 3, 4), acc[S + 4], 0, 0, 0);
+  acc[S + 8] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+      mk, __builtin_shufflevector(ws, ws, 2, 3, 4, 5), acc[S + 8], 0, 0, 0);
+  acc[S + 12] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+      mk, __builtin_shufflevector(ws, ws, 3, 4, 5, 6), acc[S + 12], 0, 0, 0);
+}
+
+// The products of DM tile tw over outputs T0 .. T0 + NWT * 256 - 1 (wave (wd, wt):
+// trials 16 wd .. 16 wd + 15 of the tile, outputs T0 + 256 wt + ...; lane l, element r
+// of block b: trial row 4 (l / 16) + r, output 16 (l mod 16) + b).  Ends with a
 // workgroup barrier, after which the LDS is free.
-template <int NWD, int NWT, int NT, int RING, int SUB, int WG, typename MA>
-__device__ __forceinline__ TileAcc<SUB * NT> mfma_tile(MA &a, int tw, int64_t T0,
-                                                       const uint8_t *xb, unsigned char *lds) {
-  constexpr int NW = NWD * NWT, REC = rec_bytes(SUB);
+template <int NWD, int NWT, int WG, typename MA>
+__device__ __forceinline__ TileAcc<kNT> mfma_tile(MA &a, int tw, int64_t T0, const uint8_t *xb,
+                                                  unsigned char *lds) {
+  constexpr int NW = NWD * NWT;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wd = wave % NWD, wt = wave / NWD;
-  v4i acc[SUB][NT];
+  v4i acc[kNT];
 #pragma unroll
-  for (int h = 0; h < SUB; ++h)
-#pragma unroll
-    for (int b = 0; b < NT; ++b) acc[h][b] = (v4i){0, 0, 0, 0};
+  for (int b = 0; b < kNT; ++b) acc[b] = (v4i){0, 0, 0, 0};
 
   const int gb = ldc(a.group_begin, tw), ge = ldc(a.group_begin, tw + 1);
   // copies the K-block records of group g into LDS (buffer-to-LDS loads, 16 bytes a
@@ -217,9 +244,9 @@ __device__ __forceinline__ TileAcc<SUB * NT> mfma_tile(MA &a, int tw, int64_t T0
   auto stage_recs = [&](int g, unsigned char *buf) {
     const int kf = ldc(&a.groups[g].kb_first, 0), nkb = ldc(&a.groups[g].nkb, 0);
     const int ro = ldc(&a.groups[g].rec_off, 0);
-    const int nch = nkb * (REC / 16);
+    const int nch = nkb * (kRecBytes / 16);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(a.recs + (int64_t)kf * REC), (short)0, nkb * REC, kBufWord3);
+        (void *)(a.recs + (int64_t)kf * kRecBytes), (short)0, nkb * kRecBytes, kBufWord3);
     for (int c0 = 64 * wave; c0 < nch; c0 += 64 * NW) {
       const int ch = c0 + lane;
       if (ch < nch)
@@ -227,37 +254,30 @@ __device__ __forceinline__ TileAcc<SUB * NT> mfma_tile(MA &a, int tw, int64_t T0
                                                  0, 0, 0);
     }
   };
-  // staging tasks: thread t takes quarter t % 4 of chunks t / 4, t / 4 + NW * 16, ...
-  constexpr int NTHR = 64 * NW, TPT = max_tasks(NW, kMfmaBufBytes / WG);
-  uint32_t raw[TPT][6];
-  int sh[TPT], dst[TPT], rot[TPT];
-  int ntask = 0;
-  const int h = tid & 3;
+  // staging: thread t takes chunk t of the group
+  uint32_t raw[8];
+  int sh = 0, dst = 0, cs = 0;
+  bool has = false;
   auto fetch = [&](int g) {
     const int ub = ldc(&a.groups[g].unit_begin, 0), nu = ldc(&a.groups[g].nunits, 0);
-    ntask = 0;
-#pragma unroll
-    for (int i = 0; i < TPT; ++i) {
-      const int k = (tid >> 2) + (NTHR / 4) * i;
-      if (k < nu) {
-        const MUnit u = a.units[ub + k];
-        load_raw(xb + (int64_t)u.c * a.in_stride, a.nsamp, T0 + u.src + 4 * h, raw[i], &sh[i]);
-        dst[i] = u.dst;
-        rot[i] = k;
-        ntask = i + 1;
-      }
+    has = tid < nu;
+    if (has) {
+      const MUnit u = a.units[ub + tid];
+      load_raw(xb + (int64_t)u.c * a.in_stride, a.nsamp, T0 + u.src, raw, &sh);
+      dst = u.dst;
+      cs = u.cs;
     }
   };
   auto store = [&](unsigned char *buf) {
-#pragma unroll
-    for (int i = 0; i < TPT; ++i)
-      if (i < ntask) store_task(buf, dst[i], h, rot[i], raw[i], sh[i]);
+    if (has) store_chunk(buf, dst, cs, raw, sh);
   };
   stage_recs(gb, lds);
   fetch(gb);
   store(lds);
   __builtin_amdgcn_s_waitcnt(kWaitVm0);
   __syncthreads();
+  // the lane's byte offset within a segment's aligned bytes
+  const int loff = 16 * (lane & 15) + kTWV * wt;
   for (int g = gb; g < ge; ++g) {
     const int par = (g - gb) & 1;
     unsigned char *buf = lds + par * a.bufbytes;
@@ -268,63 +288,57 @@ __device__ __forceinline__ TileAcc<SUB * NT> mfma_tile(MA &a, int tw, int64_t T0
     const int kbase = ldc(&a.groups[g].kb_base, 0), kf = ldc(&a.groups[g].kb_first, 0);
     const int ro = ldc(&a.groups[g].rec_off, 0);
     const int k0 = ldc(a.kbr, (int64_t)kbase + wd), k1 = ldc(a.kbr, (int64_t)kbase + wd + 1);
-    const unsigned char *wbuf = buf + 256 * NT * wt;
+    const unsigned char *rb = buf + ro + (int64_t)(k0 - kf) * kRecBytes;
+    // the next K block's mask and samples are read while this one's products run
+    uint32_t m16n = 0;
+    v4i r0n = {0, 0, 0, 0}, r1n = {0, 0, 0, 0};
+    if (k0 < k1) {
+      m16n = *(const uint16_t *)(rb + 2 * lane);
+      const int32_t ad = *(const int32_t *)(rb + 128 + 4 * (lane >> 4)) + loff;
+      r0n = *(const v4i *)(buf + ad);
+      r1n = *(const v4i *)(buf + ad + 16);
+    }
     for (int kb = k0; kb < k1; ++kb) {
-      const unsigned char *rec = buf + ro + (kb - kf) * REC;
-      // 16 mask bytes of lane (trial row lane % 16, segment lane / 16) of each half:
-      // bit j -> byte j
-      v4i mk[SUB];
-#pragma unroll
-      for (int h = 0; h < SUB; ++h) {
-        const uint32_t m16 = *(const uint16_t *)(rec + 128 * h + 2 * lane);
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          mk[h][k] = (int32_t)((((m16 >> (4 * k)) & 15u) * 0x204081u) & 0x01010101u);
+      const uint32_t m16 = m16n;
+      const v8i W = __builtin_shufflevector(r0n, r1n, 0, 1, 2, 3, 4, 5, 6, 7);
+      rb += kRecBytes;
+      if (kb + 1 < k1) {
+        m16n = *(const uint16_t *)(rb + 2 * lane);
+        const int32_t ad = *(const int32_t *)(rb + 128 + 4 * (lane >> 4)) + loff;
+        r0n = *(const v4i *)(buf + ad);
+        r1n = *(const v4i *)(buf + ad + 16);
       }
-      // window bytes i .. i + 15 of output column lane % 16 of the lane's segment
-      const int32_t region = *(const int32_t *)(rec + 128 * SUB + 8 * (lane >> 4));
-      const int32_t i = *(const int32_t *)(rec + 128 * SUB + 4 + 8 * (lane >> 4)) + (lane & 15);
-      const unsigned char *p = wbuf + region + 256 * (i >> 4) + 16 * (i & 15);
-      // a ring of RING reads in flight: the read of block b + RING is issued as soon
-      // as block b's product has taken its operand
-      v4i f[RING];
+      // 16 mask bytes of lane (trial row lane % 16, segment lane / 16): bit j -> byte j
+      v4i mk;
 #pragma unroll
-      for (int b = 0; b < RING; ++b) f[b] = *(const v4i *)(p + 256 * b);
-#pragma unroll
-      for (int b = 0; b < NT; ++b) {
-#pragma unroll
-        for (int h = 0; h < SUB; ++h)
-          acc[h][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(mk[h], f[b % RING], acc[h][b], 0, 0, 0);
-        if (b + RING < NT) f[b % RING] = *(const v4i *)(p + 256 * (b + RING));
-      }
-      // keep that order: RING reads, then the SUB products of a read and one read
-      __builtin_amdgcn_sched_group_barrier(0x100, RING, 0);
-#pragma unroll
-      for (int b = 0; b < NT; ++b) {
-        __builtin_amdgcn_sched_group_barrier(0x008, SUB, 0);
-        if (b + RING < NT) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-      }
+      for (int k = 0; k < 4; ++k)
+        mk[k] = (int32_t)((((m16 >> (4 * k)) & 15u) * 0x204081u) & 0x01010101u);
+      // Block b = 4 q + s takes bytes b .. b + 15 of the lane's 32: dwords q .. q + 3 of
+      // the lane's bytes shifted down by s, so the blocks of one shift share the 7
+      // shifted dwords and each takes 4 consecutive ones
+      mfma4<0>(acc, mk, W);
+      mfma4<1>(acc, mk, shifted<1>(W));
+      mfma4<2>(acc, mk, shifted<2>(W));
+      mfma4<3>(acc, mk, shifted<3>(W));
     }
     if (g + 1 < ge) store(lds + (par ^ 1) * a.bufbytes);
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
   }
-  TileAcc<SUB * NT> r;
+  TileAcc<kNT> r;
 #pragma unroll
-  for (int h = 0; h < SUB; ++h)
-#pragma unroll
-    for (int b = 0; b < NT; ++b) r.v[h * NT + b] = acc[h][b];
+  for (int b = 0; b < kNT; ++b) r.v[b] = acc[b];
   return r;
 }
 
 // WG workgroups per CU (their LDS), so WG NW / 4 waves per SIMD: registers up to 512 /
 // that.
-template <int NWD, int NWT, int NT, int RING, int SUB, int WG>
+template <int NWD, int NWT, int WG>
 __global__ void __launch_bounds__(64 * NWD * NWT)
 __attribute__((amdgpu_waves_per_eu(WG * NWD * NWT / 4, WG * NWD * NWT / 4)))
 k_dedisp_mfma(MfmaArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  constexpr int TWV = 16 * NT, TW = NWT * TWV;
+  constexpr int TW = NWT * kTWV;
   int tt, tw;
   tile_of_block(a.ntw, a.ntt, &tt, &tw);
   const int bb = blockIdx.y;
@@ -332,26 +346,29 @@ k_dedisp_mfma(MfmaArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wd = wave % NWD, wt = wave / NWD;
   const int64_t T0 = (int64_t)tt * TW;
-  const TileAcc<SUB * NT> tacc =
-      mfma_tile<NWD, NWT, NT, RING, SUB, WG>(a, tw, T0, a.x + (int64_t)bb * a.in_bstride, lds);
-  // C layout: lane l, element r of half h holds trial row 16 h + 4 (l / 16) + r of the
-  // wave's trials, output l % 16
+  const TileAcc<kNT> acc =
+      mfma_tile<NWD, NWT, WG>(a, tw, T0, a.x + (int64_t)bb * a.in_bstride, lds);
+  // lane l holds, for trial rows 4 (l / 16) + r, the 16 outputs from 16 (l mod 16)
   int32_t *ob = a.out + (int64_t)bb * a.out_bstride;
-  const int n = lane & 15, g4 = lane >> 4;
+  const int64_t t0 = T0 + (int64_t)kTWV * wt + 16 * (lane & 15);
+  const int g4 = lane >> 4;
 #pragma unroll
-  for (int h = 0; h < SUB; ++h)
+  for (int r = 0; r < 4; ++r) {
+    const int d = a.perm[tw * 16 * NWD + 16 * wd + 4 * g4 + r];
+    if (d < 0) continue;
+    const int32_t corr = 128 * a.ntot[d];
+    int32_t *o = ob + (int64_t)d * a.out_stride + t0;
+    if (a.vec_out && t0 + 16 <= a.nout) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int slot = tw * 16 * SUB * NWD + 16 * SUB * wd + 16 * h + 4 * g4 + r;
-      const int d = a.perm[slot];
-      if (d < 0) continue;
-      const int32_t corr = 128 * a.ntot[d];
+      for (int q = 0; q < 4; ++q)
+        *(v4i *)(o + 4 * q) = (v4i){acc.v[4 * q][r] + corr, acc.v[4 * q + 1][r] + corr,
+                                    acc.v[4 * q + 2][r] + corr, acc.v[4 * q + 3][r] + corr};
+    } else {
 #pragma unroll
-      for (int b = 0; b < NT; ++b) {
-        const int64_t t = T0 + (int64_t)TWV * wt + 16 * b + n;
-        if (t < a.nout) ob[(int64_t)d * a.out_stride + t] = tacc.v[h * NT + b][r] + corr;
-      }
+      for (int b = 0; b < kNT; ++b)
+        if (t0 + b < a.nout) o[b] = acc.v[b][r] + corr;
     }
+  }
 }
 
 struct MfmaSearchArgs {
@@ -368,48 +385,66 @@ constexpr int search_step(int sp) { return 64 * sp - ((32 + sp - 1) / sp) * sp; 
 
 // Fused search: the products of one tile (outputs T0 .. T0 + TW - 1, T0 = tt * TT),
 // then the boxcar search of every trial of the tile over starts T0 .. T0 + TT - 1.
-// The series go through LDS in two passes (the first, then the second half of every
-// wave's trials), as rows of TW + 32 ints; each wave searches whole rows.
-template <int NWD, int NWT, int NT, int RING, int SUB, int WG, typename SA>
+// The series go through LDS in two passes (trial rows 0-7, then 8-15 of every wave),
+// as rows of TW + 36 ints; each wave searches whole rows.
+template <int NWD, int NWT, int WG, typename SA>
 __device__ __forceinline__ void search_tile_mfma(SA &sa, int tt, int tw, unsigned char *lds) {
-  constexpr int NW = NWD * NWT, TWV = 16 * NT, TW = NWT * TWV, SP = TW / 64;
+  constexpr int NW = NWD * NWT, TW = NWT * kTWV, SP = TW / 64;
   constexpr int TT = search_step(SP), YROW = TW + kHalo + 4;
-  constexpr int PT = 8 * SUB;              // trials of one wave in one pass
+  constexpr int PT = 8;                    // trials of one wave in one pass
   constexpr int ROWS = PT * NWD;           // rows of one pass
   static_assert(TW % 64 == 0 && TT % SP == 0 && TW - TT >= 31, "search tile");
   static_assert(ROWS % NW == 0, "whole rows per wave");
   static_assert(ROWS * YROW * 4 <= 2 * (kMfmaBufBytes / WG), "rows of one pass fit the LDS");
+  static_assert(YROW % 4 == 0, "16-byte aligned rows");
   auto &a = sa.m;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wd = wave % NWD, wt = wave / NWD;
   const int64_t T0 = (int64_t)tt * TT;
-  const TileAcc<SUB * NT> tacc = mfma_tile<NWD, NWT, NT, RING, SUB, WG>(a, tw, T0, a.x, lds);
-  constexpr int DT = 16 * SUB * NWD;
+  const TileAcc<kNT> acc = mfma_tile<NWD, NWT, WG>(a, tw, T0, a.x, lds);
+  constexpr int DT = 16 * NWD;
   int *Y = (int *)lds;
-  const int n = lane & 15, g4 = lane >> 4;
+  // A lane's 4 trial rows (4 (l / 16) + r) are those of one pass: lanes 0-31 hold the
+  // first pass's trials, lanes 32-63 the second's.  Swapping the upper lanes of blocks
+  // b < 8 with the lower lanes of blocks b + 8 puts each pass's values into 8
+  // registers (b) per row of every lane, so the second pass's values take 32
+  // registers (not 64) during the first pass's search, and each pass writes its rows
+  // with all lanes.  After the swap, register (b, r) of pass p holds, in lane l, trial
+  // row 4 ((l / 16) mod 2) + r of the pass, output 16 (l mod 16) + 8 (l / 32) + b of
+  // the wave's run.
+  v4i ps[2][kNT / 2];
+#pragma unroll
+  for (int b = 0; b < kNT / 2; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const auto p = __builtin_amdgcn_permlane32_swap(acc.v[b][r], acc.v[b + kNT / 2][r], false,
+                                                      false);
+      ps[0][b][r] = (int32_t)p[0];
+      ps[1][b][r] = (int32_t)p[1];
+    }
+  const int col = kTWV * wt + 16 * (lane & 15) + 8 * (lane >> 5);
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
-    // the wave's trials k = 16 h + 4 g4 + r with k in [PT pass, PT pass + PT) write
-    // their outputs into row PT wd + k - PT pass
 #pragma unroll
-    for (int h = 0; h < SUB; ++h)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = 16 * h + 4 * g4 + r;
-        if (k / PT != pass) continue;
-        const int d = a.perm[tw * DT + 16 * SUB * wd + k];
-        const int32_t corr = d >= 0 ? 128 * a.ntot[d] : 0;
-        int *row = Y + (PT * wd + k - PT * pass) * YROW + TWV * wt + n;
-#pragma unroll
-        for (int b = 0; b < NT; ++b) row[16 * b] = tacc.v[h * NT + b][r] + corr;
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * ((lane >> 4) & 1) + r;   // trial row within the pass
+      const int d = a.perm[tw * DT + 16 * wd + PT * pass + k];
+      const int32_t corr = d >= 0 ? 128 * a.ntot[d] : 0;
+      int *row = Y + (PT * wd + k) * YROW + col;
+      *(v4i *)row = (v4i){ps[pass][0][r] + corr, ps[pass][1][r] + corr, ps[pass][2][r] + corr,
+                          ps[pass][3][r] + corr};
+      *(v4i *)(row + 4) = (v4i){ps[pass][4][r] + corr, ps[pass][5][r] + corr,
+                                ps[pass][6][r] + corr, ps[pass][7][r] + corr};
+    }
     __syncthreads();
-#pragma unroll
+    // one row at a time, not unrolled: the search code then stays small enough
+    // for the instruction cache
+#pragma unroll 1
     for (int k = 0; k < ROWS / NW; ++k) {
       const int rw = wave * (ROWS / NW) + k;
       const int sw = rw / PT, j = rw % PT;   // DM sub-tile, trial row within the pass
-      const int dg = a.perm[tw * DT + 16 * SUB * sw + PT * pass + j];
+      const int dg = a.perm[tw * DT + 16 * sw + PT * pass + j];
       const CandRec rec =
           boxcar_row<SP>(Y + rw * YROW, lane, T0, TT, a.nout, dg, sa.wmask, sa.nw, sa.M, sa.S);
       if (dg >= 0 && lane == 0) sa.part[(int64_t)dg * a.ntt + tt] = rec;
@@ -418,14 +453,14 @@ __device__ __forceinline__ void search_tile_mfma(SA &sa, int tt, int tw, unsigne
   }
 }
 
-template <int NWD, int NWT, int NT, int RING, int SUB, int WG>
+template <int NWD, int NWT, int WG>
 __global__ void __launch_bounds__(64 * NWD * NWT)
 __attribute__((amdgpu_waves_per_eu(WG * NWD * NWT / 4, WG * NWD * NWT / 4)))
 k_search_mfma(MfmaSearchArgs sa) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   int tt, tw;
   tile_of_block(sa.m.ntw, sa.m.ntt, &tt, &tw);
-  search_tile_mfma<NWD, NWT, NT, RING, SUB, WG>(sa, tt, tw, lds);
+  search_tile_mfma<NWD, NWT, WG>(sa, tt, tw, lds);
 }
 
 // Multi-beam fused search: one workgroup per (beam, tile).  Beam b owns the blocks
@@ -433,7 +468,7 @@ k_search_mfma(MfmaSearchArgs sa) {
 // block i of a beam runs on XCD i mod 8 and the beam's tiles take the one-beam
 // kernel's XCD-aware order.  Blocks past a beam's tile count exit at once (the whole
 // workgroup, before any barrier).
-template <int NWD, int NWT, int NT, int RING, int SUB, int WG>
+template <int NWD, int NWT, int WG>
 __global__ void __launch_bounds__(64 * NWD * NWT)
 __attribute__((amdgpu_waves_per_eu(WG * NWD * NWT / 4, WG * NWD * NWT / 4)))
 k_search_mfma_batch(const MfmaSearchArgs *__restrict__ beams, const int32_t *__restrict__ base,
@@ -455,7 +490,7 @@ k_search_mfma_batch(const MfmaSearchArgs *__restrict__ beams, const int32_t *__r
   if (k >= q + (xcd < rem ? 1 : 0)) return;
   const int L = xcd * q + min(xcd, rem) + k;
   const int tt = L / sa.m.ntw, tw = L - tt * sa.m.ntw;
-  search_tile_mfma<NWD, NWT, NT, RING, SUB, WG>(sa, tt, tw, lds);
+  search_tile_mfma<NWD, NWT, WG>(sa, tt, tw, lds);
 }
 
 }  // namespace
@@ -474,12 +509,12 @@ static hipError_t upload(T **dst, const std::vector<T> &v) {
 static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
   const MfmaCfg cf = kMfmaCfgs[ci];
   const int C = p->nchan, D = p->ndm;
-  const int NWD = cf.nwd, TW = cf.nwt * 16 * cf.nt, ST = 16 * cf.sub, DT = ST * NWD;
-  const int REC = rec_bytes(cf.sub), BUF = kMfmaBufBytes / cf.wg;
+  const int NWD = cf.nwd, NW = cf.nwd * cf.nwt, TW = cf.nwt * kTWV, DT = 16 * NWD;
+  const int BUF = kMfmaBufBytes / cf.wg;
+  const int maxunits = 64 * NW;
   out = MfmaCfgTables();
   out.tw = TW;
   out.trials = DT;
-  out.rec = REC;
   out.bufbytes = BUF;
   std::vector<int32_t> order(D);
   std::iota(order.begin(), order.end(), 0);
@@ -496,35 +531,46 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
     out.ntot[d] = (int32_t)s;
   }
   out.group_begin.assign(ntw + 1, 0);
-  std::vector<int32_t> lo(NWD * C), nseg(NWD * C);
-  std::vector<int32_t> stlo(C), wst(C);
+  // per (sub-tile, channel): first segment (window-relative, a multiple of 4) and count
+  std::vector<int32_t> so(NWD * C), nseg(NWD * C);
+  // per channel: window origin (absolute delay of window byte 0) and copy length
+  std::vector<int32_t> wlo(C), clen(C);
   for (int tw = 0; tw < ntw; ++tw) {
     out.group_begin[tw] = (int)out.groups.size();
-    // bands of every sub-tile and the staged window of every channel
     for (int c = 0; c < C; ++c) {
-      int slo = INT32_MAX, send = INT32_MIN;
+      int l[64], h[64];
+      int slo = INT32_MAX;
       for (int w = 0; w < NWD; ++w) {
-        int l = INT32_MAX, h = INT32_MIN;
-        for (int m = 0; m < ST; ++m) {
-          const int d = out.perm[(size_t)tw * DT + ST * w + m];
+        l[w] = INT32_MAX;
+        h[w] = INT32_MIN;
+        for (int m = 0; m < 16; ++m) {
+          const int d = out.perm[(size_t)tw * DT + 16 * w + m];
           if (d < 0 || p->ntap[(size_t)d * C + c] == 0) continue;
-          l = std::min(l, p->start[(size_t)d * C + c]);
-          h = std::max(h, p->start[(size_t)d * C + c] + p->ntap[(size_t)d * C + c]);
+          l[w] = std::min(l[w], p->start[(size_t)d * C + c]);
+          h[w] = std::max(h[w], p->start[(size_t)d * C + c] + p->ntap[(size_t)d * C + c]);
         }
-        lo[w * C + c] = l;
-        nseg[w * C + c] = l == INT32_MAX ? 0 : (h - l + 15) / 16;
-        if (nseg[w * C + c]) {
-          slo = std::min(slo, l);
-          send = std::max(send, l + 16 * nseg[w * C + c]);
-        }
+        slo = std::min(slo, l[w]);
       }
+      clen[c] = 0;
       if (slo == INT32_MAX) {
-        wst[c] = 0;
+        for (int w = 0; w < NWD; ++w) nseg[w * C + c] = 0;
         continue;
       }
-      stlo[c] = slo;
-      wst[c] = (send - slo + TW + 15) / 16 * 16;   // window bytes (16 copies each)
-      if ((int64_t)kPhases * wst[c] > BUF) return false;
+      wlo[c] = slo;
+      int qmax = 0;
+      for (int w = 0; w < NWD; ++w) {
+        if (l[w] == INT32_MAX) {
+          nseg[w * C + c] = 0;
+          continue;
+        }
+        const int o = (l[w] - slo) / 4 * 4;   // on the 4-byte grid, at or below the band
+        so[w * C + c] = o;
+        nseg[w * C + c] = (h[w] - (slo + o) + 15) / 16;
+        qmax = std::max(qmax, (o + 16 * (nseg[w * C + c] - 1)) / 16);
+      }
+      // lane n of time wave wt reads chunks q + n + 16 wt and q + n + 1 + 16 wt
+      clen[c] = 16 * (qmax + 16 * cf.nwt + 1);
+      if ((int64_t)kCopies * clen[c] + kRecBytes > BUF || clen[c] / 16 > maxunits) return false;
     }
     int c = 0;
     while (c < C) {
@@ -532,65 +578,66 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
       int used = 0;
       const int cbeg = c;
       std::vector<int> segw(NWD, 0);
-      int nunits = 0;   // at most max_tasks quarter chunks per thread
-      while (c < C && 4 * (nunits + wst[c] / 16) <= max_tasks(NWD * cf.nwt, BUF) * 64 * NWD * cf.nwt) {
+      int nunits = 0;
+      while (c < C && nunits + clen[c] / 16 <= maxunits) {
         int nrec = 0;   // K-block records with channel c added
         for (int w = 0; w < NWD; ++w) nrec += (segw[w] + nseg[w * C + c] + 3) / 4;
-        if ((int64_t)used + (int64_t)kPhases * wst[c] + (int64_t)nrec * REC > BUF) break;
+        if ((int64_t)used + (int64_t)kCopies * clen[c] + (int64_t)nrec * kRecBytes > BUF) break;
         for (int w = 0; w < NWD; ++w) segw[w] += nseg[w * C + c];
-        used += kPhases * wst[c];
-        nunits += wst[c] / 16;
+        used += kCopies * clen[c];
+        nunits += clen[c] / 16;
         ++c;
       }
+      if (c == cbeg) return false;   // one channel does not fit
       MGroup gi{};
       gi.unit_begin = (int)out.units.size();
       std::vector<int32_t> region(C, 0);
       int off = 0;
       for (int cc = cbeg; cc < c; ++cc) {
-        if (!wst[cc]) continue;
+        if (!clen[cc]) continue;
         region[cc] = off;
-        for (int k = 0; k < wst[cc] / 16; ++k)
-          out.units.push_back(MUnit{cc, stlo[cc] + 16 * k, off + 256 * k, 0});
-        off += kPhases * wst[cc];
+        for (int k = 0; k < clen[cc] / 16; ++k)
+          out.units.push_back(MUnit{cc, wlo[cc] + 16 * k, off + 16 * k, clen[cc]});
+        off += kCopies * clen[cc];
       }
       gi.nunits = (int)out.units.size() - gi.unit_begin;
-      if (4 * gi.nunits > max_tasks(NWD * cf.nwt, BUF) * 64 * NWD * cf.nwt) return false;
       gi.kb_base = (int)out.kbr.size();
-      gi.kb_first = (int)(out.recs.size() / REC);
+      gi.kb_first = (int)(out.recs.size() / kRecBytes);
       gi.rec_off = off;
       for (int w = 0; w < NWD; ++w) {
-        out.kbr.push_back((int32_t)(out.recs.size() / REC));
-        // segments of this sub-tile in the group, four per K block
+        out.kbr.push_back((int32_t)(out.recs.size() / kRecBytes));
+        // segments of this sub-tile in the group (channel, window-relative start), four
+        // per K block
         std::vector<std::pair<int, int>> segs;
         for (int cc = cbeg; cc < c; ++cc)
-          for (int s = 0; s < nseg[w * C + cc]; ++s) segs.push_back({cc, lo[w * C + cc] + 16 * s});
+          for (int sg = 0; sg < nseg[w * C + cc]; ++sg) segs.push_back({cc, so[w * C + cc] + 16 * sg});
         for (size_t s0 = 0; s0 < segs.size(); s0 += 4) {
-          std::vector<uint8_t> rec(REC, 0);
+          std::vector<uint8_t> rec(kRecBytes, 0);
           for (int g = 0; g < 4; ++g) {
-            // padding segments: zero masks, a valid window
+            // padding segments: zero masks, a valid address
             const size_t si = s0 + g < segs.size() ? s0 + g : s0;
             const int cc = segs[si].first, o = segs[si].second;
-            const int32_t sg[2] = {region[cc], o - stlo[cc]};
-            std::memcpy(rec.data() + 128 * cf.sub + 8 * g, sg, 8);
+            // copy (o / 4) mod 4 holds window byte o at offset 16 (o / 16)
+            const int32_t ad = region[cc] + ((o >> 2) & 3) * clen[cc] + 16 * (o >> 4);
+            std::memcpy(rec.data() + 128 + 4 * g, &ad, 4);
             if (s0 + g >= segs.size()) continue;
-            for (int m = 0; m < ST; ++m) {
-              const int d = out.perm[(size_t)tw * DT + ST * w + m];
+            const int oa = wlo[cc] + o;   // absolute delay of the segment's first byte
+            for (int m = 0; m < 16; ++m) {
+              const int d = out.perm[(size_t)tw * DT + 16 * w + m];
               if (d < 0) continue;
               const int st = p->start[(size_t)d * C + cc], nt = p->ntap[(size_t)d * C + cc];
               uint16_t bits = 0;
               for (int j = 0; j < 16; ++j)
-                if (o + j >= st && o + j < st + nt) bits |= (uint16_t)(1u << j);
-              // half m / 16, lane 16 g + m % 16
-              std::memcpy(rec.data() + 128 * (m / 16) + 2 * (16 * g + m % 16), &bits, 2);
+                if (oa + j >= st && oa + j < st + nt) bits |= (uint16_t)(1u << j);
+              std::memcpy(rec.data() + 2 * (16 * g + m), &bits, 2);
             }
           }
           out.recs.insert(out.recs.end(), rec.begin(), rec.end());
         }
       }
-      out.kbr.push_back((int32_t)(out.recs.size() / REC));
-      gi.nkb = (int)(out.recs.size() / REC) - gi.kb_first;
+      out.kbr.push_back((int32_t)(out.recs.size() / kRecBytes));
+      gi.nkb = (int)(out.recs.size() / kRecBytes) - gi.kb_first;
       out.groups.push_back(gi);
-      if (c == cbeg) return false;   // one channel does not fit
     }
   }
   out.group_begin[ntw] = (int)out.groups.size();
@@ -610,22 +657,22 @@ static hipError_t allow_lds_mfma(const void *fn, bool *done, std::mutex *mu, int
   return e;
 }
 
-template <int NWD, int NWT, int NT, int RING, int SUB, int WG>
+template <int NWD, int NWT, int WG>
 static hipError_t launch_mfma_cfg(const MfmaArgs &a, int nbatch, hipStream_t s) {
   static bool done[64] = {};
   static std::mutex mu;
-  hipError_t e = allow_lds_mfma((const void *)k_dedisp_mfma<NWD, NWT, NT, RING, SUB, WG>, done,
-                                &mu, 2 * (kMfmaBufBytes / WG));
+  hipError_t e = allow_lds_mfma((const void *)k_dedisp_mfma<NWD, NWT, WG>, done, &mu,
+                                2 * (kMfmaBufBytes / WG));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_dedisp_mfma<NWD, NWT, NT, RING, SUB, WG>), dim3(a.ntw * a.ntt, nbatch),
+  hipLaunchKernelGGL((k_dedisp_mfma<NWD, NWT, WG>), dim3(a.ntw * a.ntt, nbatch),
                      dim3(64 * NWD * NWT), 2 * a.bufbytes, s, a);
   return hipGetLastError();
 }
 
 static hipError_t launch_mfma(int ci, const MfmaArgs &a, int nbatch, hipStream_t s) {
   switch (ci) {
-#define DD_MFMA_CASE(i, x, y, z, r, h, g) \
-  case i: return launch_mfma_cfg<x, y, z, r, h, g>(a, nbatch, s);
+#define DD_MFMA_CASE(i, x, y, g) \
+  case i: return launch_mfma_cfg<x, y, g>(a, nbatch, s);
     DD_MFMA_CONFIGS(DD_MFMA_CASE)
 #undef DD_MFMA_CASE
     default: return hipErrorInvalidValue;
@@ -681,7 +728,7 @@ dedisp_status run_dedisperse_u8_mfma(dedisp_plan p, const uint8_t *x, int64_t ns
                                      int32_t *out, int64_t out_stride, int64_t out_bstride,
                                      int64_t nout, hipStream_t s, KernelTimer *kt) {
   if (p->wmode != DEDISP_W_UNIT || nbatch > 65535) return DEDISP_ERR_UNSUPPORTED;
-  // 128 trials x 512 outputs per workgroup, else 256 trials x 256 outputs
+  // the first shape that takes the plan
   int ci = -1;
   MfmaCfgTables *cfg = nullptr;
   {
@@ -702,6 +749,7 @@ dedisp_status run_dedisperse_u8_mfma(dedisp_plan p, const uint8_t *x, int64_t ns
   a.out = out;
   a.out_stride = out_stride;
   a.out_bstride = out_bstride;
+  a.vec_out = ((uintptr_t)out % 16 == 0 && out_stride % 4 == 0 && out_bstride % 4 == 0) ? 1 : 0;
   hipError_t e = kt ? kt->begin() : hipSuccess;
   if (e == hipSuccess) e = launch_mfma(ci, a, nbatch, s);
   if (e == hipSuccess && kt) e = kt->end();
@@ -717,7 +765,7 @@ struct MfmaSearchLayout {
 
 static MfmaSearchLayout search_layout(const dedisp_plan_s *p, int k, int32_t nw, int64_t nout) {
   const MfmaCfg cf = kMfmaCfgs[k];
-  const int tw = cf.nwt * 16 * cf.nt, tstep = search_step(tw / 64);
+  const int tw = cf.nwt * kTWV, tstep = search_step(tw / 64);
   MfmaSearchLayout L;
   L.ntt = (nout + tstep - 1) / tstep;
   L.off_part = (2 * sizeof(double) * (size_t)p->ndm * nw + 255) & ~(size_t)255;
@@ -733,22 +781,22 @@ size_t mfma_search_work_bytes(const dedisp_plan_s *p, int32_t nw, int64_t nout) 
 
 int mfma_search_count() { return kNumMfmaCfgs; }
 
-template <int NWD, int NWT, int NT, int RING, int SUB, int WG>
+template <int NWD, int NWT, int WG>
 static hipError_t launch_search_cfg(const MfmaSearchArgs &sa, hipStream_t s) {
   static bool done[64] = {};
   static std::mutex mu;
-  hipError_t e = allow_lds_mfma((const void *)k_search_mfma<NWD, NWT, NT, RING, SUB, WG>, done,
-                                &mu, 2 * (kMfmaBufBytes / WG));
+  hipError_t e = allow_lds_mfma((const void *)k_search_mfma<NWD, NWT, WG>, done, &mu,
+                                2 * (kMfmaBufBytes / WG));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_search_mfma<NWD, NWT, NT, RING, SUB, WG>), dim3(sa.m.ntw * sa.m.ntt),
+  hipLaunchKernelGGL((k_search_mfma<NWD, NWT, WG>), dim3(sa.m.ntw * sa.m.ntt),
                      dim3(64 * NWD * NWT), 2 * sa.m.bufbytes, s, sa);
   return hipGetLastError();
 }
 
 static hipError_t launch_search_mfma(int k, const MfmaSearchArgs &sa, hipStream_t s) {
   switch (k) {
-#define DD_MFMA_SEARCH_CASE(i, x, y, z, r, h, g) \
-  case i: return launch_search_cfg<x, y, z, r, h, g>(sa, s);
+#define DD_MFMA_SEARCH_CASE(i, x, y, g) \
+  case i: return launch_search_cfg<x, y, g>(sa, s);
     DD_MFMA_CONFIGS(DD_MFMA_SEARCH_CASE)
 #undef DD_MFMA_SEARCH_CASE
     default: return hipErrorInvalidValue;
@@ -881,14 +929,14 @@ dedisp_status mfma_batch_create(const std::vector<dedisp_plan> &plans,
   return DEDISP_OK;
 }
 
-template <int NWD, int NWT, int NT, int RING, int SUB, int WG>
+template <int NWD, int NWT, int WG>
 static hipError_t launch_batch_mfma_cfg(const MfmaBatch *B, hipStream_t s) {
   static bool done[64] = {};
   static std::mutex mu;
-  hipError_t e = allow_lds_mfma((const void *)k_search_mfma_batch<NWD, NWT, NT, RING, SUB, WG>, done,
-                                &mu, 2 * (kMfmaBufBytes / WG));
+  hipError_t e = allow_lds_mfma((const void *)k_search_mfma_batch<NWD, NWT, WG>, done, &mu,
+                                2 * (kMfmaBufBytes / WG));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_search_mfma_batch<NWD, NWT, NT, RING, SUB, WG>), dim3(B->base.back()),
+  hipLaunchKernelGGL((k_search_mfma_batch<NWD, NWT, WG>), dim3(B->base.back()),
                      dim3(64 * NWD * NWT), 2 * (kMfmaBufBytes / WG), s, B->d_args, B->d_base,
                      B->nbeam);
   return hipGetLastError();
@@ -896,8 +944,8 @@ static hipError_t launch_batch_mfma_cfg(const MfmaBatch *B, hipStream_t s) {
 
 static hipError_t launch_batch_mfma(const MfmaBatch *B, hipStream_t s) {
   switch (B->k) {
-#define DD_MFMA_BATCH_CASE(i, x, y, z, r, h, g) \
-  case i: return launch_batch_mfma_cfg<x, y, z, r, h, g>(B, s);
+#define DD_MFMA_BATCH_CASE(i, x, y, g) \
+  case i: return launch_batch_mfma_cfg<x, y, g>(B, s);
     DD_MFMA_CONFIGS(DD_MFMA_BATCH_CASE)
 #undef DD_MFMA_BATCH_CASE
     default: return hipErrorInvalidValue;
