@@ -43,9 +43,10 @@ namespace dd {
 // Workgroup shapes: NWD waves along DM (16 trials each), NWT along time (256 outputs
 // each), WG workgroups per CU (each with 1 / WG of the CU's LDS).
 #define DD_MFMA_CONFIGS(X) \
-  X(0, 8, 2, 1)            \
-  X(1, 16, 1, 1)           \
-  X(2, 8, 1, 2)
+  X(0, 4, 2, 2)            \
+  X(1, 8, 1, 2)            \
+  X(2, 8, 2, 1)            \
+  X(3, 16, 1, 1)
 struct MfmaCfg {
   int nwd, nwt, wg;
 };
@@ -123,7 +124,7 @@ struct MfmaArgs {
   const uint8_t *x;
   int64_t in_stride, in_bstride, nsamp;
   int32_t ntw, ntt, bufbytes;
-  int32_t vec_out;        // out, out_stride and out_bstride allow 16-byte stores
+  int32_t pad0;
   const int32_t *group_begin, *kbr, *perm, *ntot;
   const MGroup *groups;
   const MUnit *units;
@@ -348,26 +349,49 @@ k_dedisp_mfma(MfmaArgs a) {
   const int64_t T0 = (int64_t)tt * TW;
   const TileAcc<kNT> acc =
       mfma_tile<NWD, NWT, WG>(a, tw, T0, a.x + (int64_t)bb * a.in_bstride, lds);
-  // lane l holds, for trial rows 4 (l / 16) + r, the 16 outputs from 16 (l mod 16)
-  int32_t *ob = a.out + (int64_t)bb * a.out_bstride;
-  const int64_t t0 = T0 + (int64_t)kTWV * wt + 16 * (lane & 15);
-  const int g4 = lane >> 4;
+  // Lane l holds, for trial rows 4 (l / 16) + r, the 16 outputs from 16 (l mod 16): the
+  // rows go out through LDS (free after the tile's last barrier; each wave has its own
+  // 8 rows), so that each store instruction writes 256 consecutive bytes of a row.
+  // Swapping the upper lanes of blocks b < 8 with the lower lanes of blocks b + 8 first
+  // gives every lane, in pass p, trial row 8 p + 4 ((l / 16) mod 2) + r at outputs
+  // 16 (l mod 16) + 8 (l / 32) + b, b < 8.
+  constexpr int OROW = kTWV + 4;
+  static_assert(NWD * NWT * 8 * OROW * 4 <= 2 * (kMfmaBufBytes / WG), "output rows fit the LDS");
+  int *R = (int *)lds + wave * 8 * OROW;
+  v4i ps[2][kNT / 2];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int d = a.perm[tw * 16 * NWD + 16 * wd + 4 * g4 + r];
-    if (d < 0) continue;
-    const int32_t corr = 128 * a.ntot[d];
-    int32_t *o = ob + (int64_t)d * a.out_stride + t0;
-    if (a.vec_out && t0 + 16 <= a.nout) {
+  for (int b = 0; b < kNT / 2; ++b)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        *(v4i *)(o + 4 * q) = (v4i){acc.v[4 * q][r] + corr, acc.v[4 * q + 1][r] + corr,
-                                    acc.v[4 * q + 2][r] + corr, acc.v[4 * q + 3][r] + corr};
-    } else {
-#pragma unroll
-      for (int b = 0; b < kNT; ++b)
-        if (t0 + b < a.nout) o[b] = acc.v[b][r] + corr;
+    for (int r = 0; r < 4; ++r) {
+      const auto p = __builtin_amdgcn_permlane32_swap(acc.v[b][r], acc.v[b + kNT / 2][r], false,
+                                                      false);
+      ps[0][b][r] = (int32_t)p[0];
+      ps[1][b][r] = (int32_t)p[1];
     }
+  int32_t *ob = a.out + (int64_t)bb * a.out_bstride;
+  const int64_t t0 = T0 + (int64_t)kTWV * wt;
+  const int col = 16 * (lane & 15) + 8 * (lane >> 5);
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int *row = R + (4 * ((lane >> 4) & 1) + r) * OROW + col;
+      *(v4i *)row = (v4i){ps[pass][0][r], ps[pass][1][r], ps[pass][2][r], ps[pass][3][r]};
+      *(v4i *)(row + 4) = (v4i){ps[pass][4][r], ps[pass][5][r], ps[pass][6][r], ps[pass][7][r]};
+    }
+    // LDS operations of one wave complete in order: the reads below see the writes
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+    for (int k = 0; k < 8; ++k) {
+      const int d = a.perm[tw * 16 * NWD + 16 * wd + 8 * pass + k];
+      if (d < 0) continue;
+      const int32_t corr = 128 * a.ntot[d];
+      int32_t *o = ob + (int64_t)d * a.out_stride + t0;
+#pragma unroll
+      for (int j = 0; j < kTWV / 64; ++j)
+        if (t0 + lane + 64 * j < a.nout) o[lane + 64 * j] = R[k * OROW + lane + 64 * j] + corr;
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -749,7 +773,6 @@ dedisp_status run_dedisperse_u8_mfma(dedisp_plan p, const uint8_t *x, int64_t ns
   a.out = out;
   a.out_stride = out_stride;
   a.out_bstride = out_bstride;
-  a.vec_out = ((uintptr_t)out % 16 == 0 && out_stride % 4 == 0 && out_bstride % 4 == 0) ? 1 : 0;
   hipError_t e = kt ? kt->begin() : hipSuccess;
   if (e == hipSuccess) e = launch_mfma(ci, a, nbatch, s);
   if (e == hipSuccess && kt) e = kt->end();

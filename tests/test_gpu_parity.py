@@ -280,10 +280,10 @@ def cfg2_mid(orc):
     return wl, n, yo
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, -2])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, -2])
 def test_fused_search_every_tile_config(dd, orc, cfg2_mid, tile):
     # Ragged in both DM (100 trials) and time (6755 outputs) for every shape: 0-7 the
-    # packed-add kernel, 8-9 the matrix-core kernel, -2 the unfused path.
+    # packed-add kernel, 8-11 the matrix-core kernel, -2 the unfused path.
     wl, n, yo = cfg2_mid
     p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule="allnonzero")
     p.set_tile(tile)
@@ -301,10 +301,10 @@ def cfg2_dense(orc):
     return wl, n, yo
 
 
-@pytest.mark.parametrize("tile", [8, 9, 10])
+@pytest.mark.parametrize("tile", [8, 9, 10, 11])
 def test_matrix_core_search_shapes(dd, orc, cfg2_dense, tile):
-    # 300 trials (every matrix-core shape takes this plan: the 128-trial tiles of the
-    # two-workgroups-per-CU shape span too many samples at 100 trials), ragged time.
+    # 300 trials: three DM tiles of 128 (or five of 64) trials with a ragged last tile,
+    # ragged time.
     wl, n, yo = cfg2_dense
     p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule="allnonzero")
     p.set_tile(tile)
