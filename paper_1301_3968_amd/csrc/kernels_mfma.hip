@@ -199,29 +199,42 @@ struct TileAcc {
 
 typedef int32_t v8i __attribute__((ext_vector_type(8)));
 
-// The lane's 32 bytes shifted down by S bytes (dwords 0..6; dword 7 unused).
-template <int S>
+// Shifted samples: T[k] = the lane's bytes shifted down by S bytes, dword k + O (k < 6;
+// dwords 6, 7 unused).  Block 4 q + S takes dwords q .. q + 3 of the shifted bytes: from
+// the O = 0 tuple at offset q for even q, from the O = 1 tuple at offset q - 1 for odd q,
+// so that every operand starts at an even register of its tuple (4-register operands
+// must; an odd start would be copied into place).
+template <int S, int O>
 __device__ __forceinline__ v8i shifted(const v8i &w) {
+  // the O = 1 tuple by byte permutes (bytes S .. S + 3 of the dword pair), the O = 0
+  // tuple by byte aligns: the same values, which the compiler would otherwise compute
+  // once and then copy into the second tuple
+  constexpr uint32_t sel = (uint32_t)S | (uint32_t)(S + 1) << 8 | (uint32_t)(S + 2) << 16 |
+                           (uint32_t)(S + 3) << 24;
   v8i r;
 #pragma unroll
-  for (int k = 0; k < 7; ++k)
-    r[k] = (int32_t)__builtin_amdgcn_alignbyte((uint32_t)w[k + 1], (uint32_t)w[k], (uint32_t)S);
+  for (int k = 0; k < 6; ++k)
+    r[k] = S == 0 ? w[k + O]
+           : O == 0 ? (int32_t)__builtin_amdgcn_alignbyte((uint32_t)w[k + 1], (uint32_t)w[k], (uint32_t)S)
+                    : (int32_t)__builtin_amdgcn_perm((uint32_t)w[k + 2], (uint32_t)w[k + 1], sel);
+  r[6] = 0;
   r[7] = 0;
   return r;
 }
 
-// The products of blocks S, S + 4, S + 8, S + 12 (samples: dwords q .. q + 3 of ws for
-// block 4 q + S).
+// The products of blocks S, S + 4, S + 8, S + 12.
 template <int S>
-__device__ __forceinline__ void mfma4(v4i (&acc)[kNT], const v4i &mk, const v8i &ws) {
-  acc[S] = __builtin_amdgcn_mfma_i32_16x16x64_i8(mk, __builtin_shufflevector(ws, ws, 0, 1, 2, 3),
+__device__ __forceinline__ void mfma4(v4i (&acc)[kNT], const v4i &mk, const v8i &w) {
+  const v8i e = S == 0 ? w : shifted<S, 0>(w);
+  const v8i o = shifted<S, 1>(w);
+  acc[S] = __builtin_amdgcn_mfma_i32_16x16x64_i8(mk, __builtin_shufflevector(e, e, 0, 1, 2, 3),
                                                  acc[S], 0, 0, 0);
   acc[S + 4] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-      mk, __builtin_shufflevector(ws, ws, 1, 2, 3, 4), acc[S + 4], 0, 0, 0);
+      mk, __builtin_shufflevector(o, o, 0, 1, 2, 3), acc[S + 4], 0, 0, 0);
   acc[S + 8] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-      mk, __builtin_shufflevector(ws, ws, 2, 3, 4, 5), acc[S + 8], 0, 0, 0);
+      mk, __builtin_shufflevector(e, e, 2, 3, 4, 5), acc[S + 8], 0, 0, 0);
   acc[S + 12] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-      mk, __builtin_shufflevector(ws, ws, 3, 4, 5, 6), acc[S + 12], 0, 0, 0);
+      mk, __builtin_shufflevector(o, o, 2, 3, 4, 5), acc[S + 12], 0, 0, 0);
 }
 
 // The products of DM tile tw over outputs T0 .. T0 + NWT * 256 - 1 (wave (wd, wt):
@@ -292,22 +305,20 @@ __device__ __forceinline__ TileAcc<kNT> mfma_tile(MA &a, int tw, int64_t T0, con
     const unsigned char *rb = buf + ro + (int64_t)(k0 - kf) * kRecBytes;
     // the next K block's mask and samples are read while this one's products run
     uint32_t m16n = 0;
-    v4i r0n = {0, 0, 0, 0}, r1n = {0, 0, 0, 0};
+    v8i wn = {0, 0, 0, 0, 0, 0, 0, 0};   // one 8-register tuple (two 16-byte reads)
     if (k0 < k1) {
       m16n = *(const uint16_t *)(rb + 2 * lane);
       const int32_t ad = *(const int32_t *)(rb + 128 + 4 * (lane >> 4)) + loff;
-      r0n = *(const v4i *)(buf + ad);
-      r1n = *(const v4i *)(buf + ad + 16);
+      wn = *(const v8i *)(buf + ad);
     }
     for (int kb = k0; kb < k1; ++kb) {
       const uint32_t m16 = m16n;
-      const v8i W = __builtin_shufflevector(r0n, r1n, 0, 1, 2, 3, 4, 5, 6, 7);
+      const v8i W = wn;
       rb += kRecBytes;
       if (kb + 1 < k1) {
         m16n = *(const uint16_t *)(rb + 2 * lane);
         const int32_t ad = *(const int32_t *)(rb + 128 + 4 * (lane >> 4)) + loff;
-        r0n = *(const v4i *)(buf + ad);
-        r1n = *(const v4i *)(buf + ad + 16);
+        wn = *(const v8i *)(buf + ad);
       }
       // 16 mask bytes of lane (trial row lane % 16, segment lane / 16): bit j -> byte j
       v4i mk;
@@ -315,12 +326,11 @@ __device__ __forceinline__ TileAcc<kNT> mfma_tile(MA &a, int tw, int64_t T0, con
       for (int k = 0; k < 4; ++k)
         mk[k] = (int32_t)((((m16 >> (4 * k)) & 15u) * 0x204081u) & 0x01010101u);
       // Block b = 4 q + s takes bytes b .. b + 15 of the lane's 32: dwords q .. q + 3 of
-      // the lane's bytes shifted down by s, so the blocks of one shift share the 7
-      // shifted dwords and each takes 4 consecutive ones
+      // the lane's bytes shifted down by s
       mfma4<0>(acc, mk, W);
-      mfma4<1>(acc, mk, shifted<1>(W));
-      mfma4<2>(acc, mk, shifted<2>(W));
-      mfma4<3>(acc, mk, shifted<3>(W));
+      mfma4<1>(acc, mk, W);
+      mfma4<2>(acc, mk, W);
+      mfma4<3>(acc, mk, W);
     }
     if (g + 1 < ge) store(lds + (par ^ 1) * a.bufbytes);
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
