@@ -42,6 +42,14 @@ __device__ __forceinline__ int first_start_of(int w, const int *qv, int b, int l
   }
 }
 
+// Lane l's double.
+__device__ __forceinline__ double rl_double(double x, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // One step of a wave maximum of a double: the larger of x and the value the
 // 32-bit lane movement F brings to this lane (applied to both halves).
 template <typename F>
@@ -208,17 +216,32 @@ __device__ __forceinline__ CandRec boxcar_row(int *Yw, int lane, int64_t t0, int
   const uint64_t hit = __ballot(snr == smax);
   const uint32_t wbits = ((uint32_t)hit & 0x55555555u) | (((uint32_t)(hit >> 32) & 0x55555555u) << 1);
   const int bw = __builtin_amdgcn_readfirstlane(__builtin_ctz(wbits) + 1);
-  const int bb = __builtin_amdgcn_readlane(bmax, 32 * ((bw - 1) & 1) + ((bw - 1) & ~1));
-  // earliest start of a window of width bw and sum bb: per lane from the prefix,
-  // then the lowest lane that has one
+  const int wlane = 32 * ((bw - 1) & 1) + ((bw - 1) & ~1);
+  const int bb = __builtin_amdgcn_readlane(bmax, wlane);
+  // The winning windows: those of width bw whose S/N equals smax.  With a noise deviation
+  // 0 < S < inf the S/N rises strictly with the window sum, so they are the windows of
+  // sum bb; with S = 0 (every window above the mean has S/N +inf) or S = inf (every
+  // finite window 0) other sums tie, so their S/N is compared itself.
+  const double ws = rl_double(ns, wlane), wm = rl_double(nm, wlane);
+  const bool strict = ws > 0.0 && ws < INFINITY;
+  // earliest such start: per lane a sliding window over its outputs (only valid windows,
+  // i + bw <= lim, count), then the lowest lane that has one
   int first = -1;
   {
     int B = 0;
     for (int k = 0; k < bw; ++k) B += yl[k];
+    if (strict) {
 #pragma unroll
-    for (int i = 0; i < SP; ++i) {
-      if (first < 0 && B == bb && i + bw <= lim) first = i;
-      B += yl[i + bw] - yl[i];
+      for (int i = 0; i < SP; ++i) {
+        if (first < 0 && B == bb && i + bw <= lim) first = i;
+        B += yl[i + bw] - yl[i];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < SP; ++i) {
+        if (first < 0 && ((double)B - wm) / ws == smax && i + bw <= lim) first = i;
+        B += yl[i + bw] - yl[i];
+      }
     }
   }
   const uint64_t fh = __ballot(first >= 0);

@@ -261,6 +261,30 @@ def test_edge_cases(dd, orc):
     assert np.array_equal(p1.dedisperse(_dev(x)).cpu().numpy()[0], x[0].astype(np.int32))
 
 
+@pytest.mark.parametrize("tile", [-1, 0, 9, -2])
+def test_search_zero_noise_deviation(dd, orc, tile):
+    # Zero channel means and deviations: a window of zeros has S/N 0 / 0 (NaN, which never
+    # wins), any window with signal +inf (ties to the smaller width, then the earlier
+    # start); trials whose series is all zeros have no candidate (-inf, -1, 0).
+    wl = workloads.cfg2(nsamp=3000, ndm=40)
+    p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule="allnonzero")
+    p.set_tile(tile)
+    s, n = p.tables()
+    # signal only in the last samples of the most delayed channel: only the trials with
+    # the largest delays there reach it
+    x = np.zeros_like(wl.x)
+    x[int(np.argmax(s[-1])), -4:] = 200
+    C = x.shape[0]
+    mu, sg = np.zeros(C), np.zeros(C)
+    snr, t, W = p.search(_dev(x), wl.widths, mu, sg)
+    yo = orc.dedisperse_u8(x, s, n).astype(np.float64)
+    M, S = orc.boxcar_norm(n, wl.widths, mu, sg)
+    so, to, wo = orc.boxcar_detect(yo, wl.widths, M, S)
+    assert np.isposinf(so).any() and np.isneginf(so).any()
+    assert np.array_equal(snr.cpu().numpy(), so)
+    assert np.array_equal(t.cpu().numpy(), to) and np.array_equal(W.cpu().numpy(), wo)
+
+
 def test_deterministic(dd):
     wl = workloads.cfg2(nsamp=5000, ndm=64)
     p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule=wl.rule)
