@@ -23,6 +23,7 @@ if ROOT not in sys.path:
 
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9   # int32 vector lane-ops/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
 PACKED_PEAK_OPS = 2 * VALU_PEAK_OPS    # two 16-bit adds per lane-op (packed uint16 adds)
+HBM_PEAK_BYTES = 8e12                  # MI355X HBM3E peak, bytes/s
 MFMA_I8_PEAK_OPS = 5.0e15              # dense int8 matrix-core ops/s (a multiply-add is 2 ops)
 NUM_PACKED_SHAPES = 8                  # search shapes 0-7: packed-add kernel; 8 on: matrix cores
 # sources of the search kernels (both kinds and their shared detection stage)
@@ -173,7 +174,8 @@ def main() -> int:
                     "frac": mma_ops / kern_s / MFMA_I8_PEAK_OPS,
                     "traffic": _traffic(tile), "kernel_ms": kern_ms, "ops_per_launch": mma_ops,
                     "sums_per_launch": sums,
-                    "frac_valu_equivalent": valu_ops / kern_s / VALU_PEAK_OPS}
+                    "frac_valu_equivalent": valu_ops / kern_s / VALU_PEAK_OPS,
+                    "frac_valu_equivalent_packed_u16": valu_ops / kern_s / PACKED_PEAK_OPS}
     else:
         roofline = {"bound": "alu", "achieved": valu_ops / kern_s / 1e12,
                     "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
@@ -192,6 +194,10 @@ def main() -> int:
                    "nchan": C, "nsamp": T, "ndm": D, "nout": nout, "widths": nw,
                    "rule": args.rule, "fused_search": bool(fused), "tile_config": tile},
         "roofline": roofline,
+        # the "effective bandwidth" convention: one input byte per DM-channel-sample sum,
+        # against the 8 TB/s HBM peak (the path reads each byte far fewer times than that)
+        "effective_bandwidth": {"unit": "TB/s", "value": value / 1e12,
+                                "frac_of_hbm_peak": value / HBM_PEAK_BYTES},
     }
     if not args.no_cpu_baseline:
         print("timing the oracle on a sample", file=sys.stderr, flush=True)
