@@ -13,9 +13,12 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -83,10 +86,11 @@ def main() -> int:
     ap.add_argument("--cpu-sample-trials", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="search",
-                    choices=["search", "batch", "weighted", "autograd"],
+                    choices=["search", "batch", "weighted", "autograd", "completeness"],
                     help="search: the headline fused search (default); batch: 36 beams in one "
                          "launch; weighted: 4096-channel fp32-weighted dedispersion; "
-                         "autograd: forward / adjoint timing of the 8-tap learnable profile")
+                         "autograd: forward / adjoint timing of the 8-tap learnable profile; "
+                         "completeness: largest S/N over the trial DMs against a test pulse's DM")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (the reference kernel "
                          "for scaling HBM byte counters) and exit")
@@ -263,6 +267,8 @@ def _other_workload(args, dd, workloads) -> int:
                                         "trial-DM grids of 300-1200 trials (0.8 of optimal)",
                             "total_trials": B.total_trials, "total_sums": B.total_sums,
                             "ms_eager": t_eager * 1e3, "ms_one_plan_at_a_time": t_single * 1e3})
+    elif args.workload == "completeness":
+        line = dict(base, **_completeness(dd, workloads, K, W))
     elif args.workload == "weighted":
         print("generating the 4096-channel block", file=sys.stderr, flush=True)
         wl = workloads.cfg3()
@@ -315,6 +321,86 @@ def _other_workload(args, dd, workloads) -> int:
                             "ratio_fwd_plus_sparse_adjoint": (t_fwd + t_adj_sparse) / t_fwd})
     print(json.dumps(line), flush=True)
     return 0
+
+
+# Survey examples of Section 5.3: (name, band low edge GHz, bandwidth GHz, channels, dt s,
+# test pulse width s, DM range, DM error factor).
+COMPLETENESS_CASES = [
+    ("700-1004 MHz, 304 x 1 MHz, 1 ms, 1 ms pulse", 0.700, 0.304, 304, 1e-3, 1e-3, 10.0, 3000.0, 1.492),
+    ("21-23 GHz, 256 x 7.8125 MHz, 100 us, 100 us pulse", 21.0, 2.0, 256, 1e-4, 1e-4, 50.0, 10000.0, 0.580),
+    ("21-23 GHz, 32 x 62.5 MHz, 100 us, 100 us pulse", 21.0, 2.0, 32, 1e-4, 1e-4, 50.0, 10000.0, 0.287),
+]
+
+
+def completeness_case(dd, workloads, case, true_dms, chunk=64, lead=64):
+    """Largest S/N over the trial DMs (eq. trial DMs) for a noiseless rectangular test pulse
+    at each true DM, normalised to P0 sqrt(beta tau) / k T_sys (Section 5.3): greedy sample
+    sets (Section 2.2) per trial, batched fp32 dedispersion, per-trial S/N at width 1 with
+    unit noise per sample, largest over the trials on the host.  Returns (plan, S/N [n],
+    best trial [n], per-trial S/N [n][D], seconds)."""
+    import torch
+    _, flo, band, C, dt, tau, lo, hi, eps = case
+    f = workloads.channel_centres(flo, band, C)
+    bw = band / C
+    dms = dd.trial_dms(lo, hi, eps, f, bw, dt, cap=100000)
+    plan = dd.Plan(f, bw, dt, dms, rule="greedy", width_s=tau)
+    T = plan.max_span + 2 * lead
+    D = len(dms)
+    mean, sig = np.zeros(C), np.ones(C)
+    work = torch.empty(plan.work_bytes(T, 1), dtype=torch.uint8, device="cuda")
+    snr_all = np.empty((len(true_dms), D))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i0 in range(0, len(true_dms), chunk):
+        dm_c = true_dms[i0:i0 + chunk]
+        x = torch.zeros((len(dm_c), C, T), dtype=torch.float32, device="cuda")
+        for b, dm in enumerate(dm_c):
+            c, n, v = workloads.rect_pulse_cells(f, bw, dt, float(dm), tau, lead * dt)
+            ok = (n >= 0) & (n < T)
+            idx = torch.from_numpy(c[ok] * T + n[ok]).cuda()
+            x[b].view(-1).index_put_((idx,), torch.from_numpy(v[ok].astype(np.float32)).cuda(),
+                                     accumulate=True)
+        y = plan.dedisperse(x)
+        for b in range(len(dm_c)):
+            snr, _, _ = plan.detect(y[b], [1], mean, sig, work=work)
+            snr_all[i0 + b] = snr.cpu().numpy()
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    norm = math.sqrt(dt / (C * tau))
+    best = snr_all.max(axis=1) * norm
+    return plan, best, snr_all.argmax(axis=1), snr_all * norm, secs
+
+
+def _completeness(dd, workloads, K, W):
+    """Section 5.3 completeness curves: the S/N at every trial DM (peaks) and half-way
+    between adjacent trials (troughs) for the three survey examples."""
+    out = {"metric": "completeness points/s (largest S/N over trial DMs per test pulse)",
+           "unit": "points/s", "dtype": "fp32", "config": {"workload": "completeness", "cases": []}}
+    total_pts, total_s = 0, 0.0
+    for case in COMPLETENESS_CASES:
+        f = workloads.channel_centres(case[1], case[2], case[3])
+        dms = dd.trial_dms(case[6], case[7], case[8], f, case[2] / case[3], case[4], cap=100000)
+        true = np.concatenate([dms, 0.5 * (dms[:-1] + dms[1:])])
+        completeness_case(dd, workloads, case, true[:8])          # warm-up
+        plan, best, arg, _, secs = completeness_case(dd, workloads, case, true)
+        D = len(dms)
+        pk, tr = best[:D], best[D:]
+        ratio = tr / (0.5 * (pk[:-1] + pk[1:]))
+        q = max(1, D // 10)
+        out["config"]["cases"].append({
+            "name": case[0], "trials": D, "points": len(true), "seconds": secs,
+            "peak_snr_first_tenth": float(np.mean(pk[:q])),
+            "peak_snr_last_tenth": float(np.mean(pk[-q:])),
+            "trough_over_peak_mean": float(np.mean(ratio)),
+            "trough_over_peak_min": float(np.min(ratio)),
+            "trough_over_peak_max": float(np.max(ratio)),
+            "dropout_closed_form": (case[8] ** 2 + 1.0) ** -0.25,
+            "pulse_found_at_own_trial": float(np.mean(arg[:D] == np.arange(D)))})
+        total_pts += len(true)
+        total_s += secs
+    out["value"] = total_pts / total_s
+    out["ms_per_step"] = total_s * 1e3
+    return out
 
 
 def _fused(plan) -> bool:

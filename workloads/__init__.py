@@ -90,6 +90,40 @@ def render_pulse(freqs_ghz: np.ndarray, chan_bw_ghz: float, dt_s: float, nsamp: 
     return t_lo, cells
 
 
+def rect_pulse_cells(freqs_ghz: np.ndarray, chan_bw_ghz: float, dt_s: float, dm: float,
+                     width_s: float, t_arrival_s: float, nsub: int = 32):
+    """Noiseless dispersed rectangular pulse (power 1 while it lasts) as cell means: the
+    cells (channel, sample, value) it touches.  Each channel is cut into `nsub` sub-bands;
+    in sub-band nu the pulse occupies [d(nu), d(nu) + width) with d(nu) = t_arrival +
+    K DM (nu^-2 - nu_top^-2), nu_top the top of the band; a cell holds the mean over
+    sub-bands of the fraction of [n dt, (n + 1) dt) it occupies.  Entries may repeat a
+    cell (add them)."""
+    C = freqs_ghz.shape[0]
+    nu_top = float(np.max(freqs_ghz) + 0.5 * chan_bw_ghz)
+    sub = (np.arange(nsub) + 0.5) / nsub - 0.5
+    nu = freqs_ghz[:, None] + sub[None, :] * chan_bw_ghz                 # [C, J]
+    d0 = t_arrival_s + SIGNAL_KDM_S * dm * (nu ** -2 - nu_top ** -2)     # pulse start
+    d1 = d0 + width_s
+    L = int(math.ceil(width_s / dt_s)) + 2
+    n = np.floor(d0 / dt_s).astype(np.int64)[:, :, None] + np.arange(L)[None, None, :]
+    lo = np.maximum(n * dt_s, d0[:, :, None])
+    hi = np.minimum((n + 1) * dt_s, d1[:, :, None])
+    frac = np.clip(hi - lo, 0.0, None) / dt_s / nsub                     # [C, J, L]
+    cc = np.broadcast_to(np.arange(C)[:, None, None], n.shape)
+    keep = frac > 0.0
+    return cc[keep], n[keep], frac[keep]
+
+
+def render_rect_pulse(freqs_ghz: np.ndarray, chan_bw_ghz: float, dt_s: float, nsamp: int,
+                      dm: float, width_s: float, t_arrival_s: float, nsub: int = 32) -> np.ndarray:
+    """rect_pulse_cells as a dense fp32 block [C, nsamp] (cells outside it dropped)."""
+    c, n, v = rect_pulse_cells(freqs_ghz, chan_bw_ghz, dt_s, dm, width_s, t_arrival_s, nsub)
+    x = np.zeros((freqs_ghz.shape[0], nsamp), dtype=np.float64)
+    ok = (n >= 0) & (n < nsamp)
+    np.add.at(x, (c[ok], n[ok]), v[ok])
+    return x.astype(np.float32)
+
+
 def add_pulse(x: np.ndarray, freqs_ghz: np.ndarray, chan_bw_ghz: float, dt_s: float, p: Pulse) -> None:
     """Add a rendered pulse in place into a float array x[C, T]."""
     C, T = x.shape
