@@ -332,17 +332,19 @@ COMPLETENESS_CASES = [
 ]
 
 
-def completeness_case(dd, workloads, case, true_dms, chunk=64, lead=64):
+def completeness_case(dd, workloads, case, true_dms, chunk=64, lead=64, dms=None):
     """Largest S/N over the trial DMs (eq. trial DMs) for a noiseless rectangular test pulse
     at each true DM, normalised to P0 sqrt(beta tau) / k T_sys (Section 5.3): greedy sample
     sets (Section 2.2) per trial, batched fp32 dedispersion, per-trial S/N at width 1 with
     unit noise per sample, largest over the trials on the host.  Returns (plan, S/N [n],
-    best trial [n], per-trial S/N [n][D], seconds)."""
+    best trial [n], per-trial S/N [n][D], seconds).  dms: the trial DMs (default: the
+    library's eq. trial DMs for the case)."""
     import torch
     _, flo, band, C, dt, tau, lo, hi, eps = case
     f = workloads.channel_centres(flo, band, C)
     bw = band / C
-    dms = dd.trial_dms(lo, hi, eps, f, bw, dt, cap=100000)
+    if dms is None:
+        dms = dd.trial_dms(lo, hi, eps, f, bw, dt, cap=100000)
     plan = dd.Plan(f, bw, dt, dms, rule="greedy", width_s=tau)
     T = plan.max_span + 2 * lead
     D = len(dms)

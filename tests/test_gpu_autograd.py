@@ -10,14 +10,14 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
-def setup(orc):
+def setup(orc, otables):
     import torch
     import paper_1301_3968_amd as dd
     wl = workloads.cfg5(batch=4, nsamp=4096, ndm=32, nchan=48)
     K = wl.extra["ktaps"]
     p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule="fixed", ktaps=K, wmode="tap",
                 weights=wl.weights)
-    s, n = p.tables()
+    s, n = otables(p, wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, "fixed", ktaps=K)
     nout = p.out_len(wl.x.shape[2])
     b = np.arange(len(wl.pulses))
     d = np.array([pl[1] for pl in wl.pulses])

@@ -25,7 +25,7 @@ def dd():
 
 
 @pytest.fixture(scope="module")
-def beams(dd, orc):
+def beams(dd, orc, otables):
     rng = np.random.default_rng(4242)
     C = 96
     f = workloads.channel_centres(1.2, 0.336 * C / 336, C)
@@ -33,10 +33,12 @@ def beams(dd, orc):
     for b in range(5):
         T = int(rng.integers(3000, 9000))
         ntr = int(rng.integers(20, 70))
-        dms = dd.trial_dms(0.0, 1e9, EPS_08 / 2, f, 0.001, 1e-3, cap=ntr)
+        dms = orc.trial_dms(0.0, 1e9, EPS_08 / 2, f, 0.001, 1e-3, cap=ntr)
+        np.testing.assert_allclose(dd.trial_dms(0.0, 1e9, EPS_08 / 2, f, 0.001, 1e-3, cap=ntr),
+                                   dms, rtol=1e-12)
         x = workloads.u8_noise(rng, C, T)
         p = dd.Plan(f, 0.001, 1e-3, dms, rule="allnonzero")
-        s, n = p.tables()
+        s, n = otables(p, f, 0.001, 1e-3, dms, "allnonzero")
         yo = orc.dedisperse_u8(x, s, n).astype(np.float64)
         out.append((p, x, n, yo))
     return C, out

@@ -17,18 +17,17 @@ def dd():
     return dd
 
 
-def test_completeness_curve_matches_oracle(dd, orc):
+def test_completeness_curve_matches_oracle(dd, orc, otables):
     case = bench.COMPLETENESS_CASES[2]
     _, flo, band, C, dt, tau, lo, hi, eps = case
     f = workloads.channel_centres(flo, band, C)
-    dms = dd.trial_dms(lo, hi, eps, f, band / C, dt, cap=100000)
+    dms = orc.trial_dms(lo, hi, eps, f, band / C, dt)
     assert len(dms) == 128                               # the count the paper quotes
     pick = np.arange(0, 127, 9)
     true = np.concatenate([dms[pick], 0.5 * (dms[pick] + dms[pick + 1])])
-    plan, best, arg, snr, _ = bench.completeness_case(dd, workloads, case, true, chunk=8)
-    s, n = plan.tables()
-    # the plan's greedy tables are the oracle's (pinned separately); here the sums and
-    # the detection on them
+    np.testing.assert_allclose(dd.trial_dms(lo, hi, eps, f, band / C, dt), dms, rtol=1e-12)
+    plan, best, arg, snr, _ = bench.completeness_case(dd, workloads, case, true, chunk=8, dms=dms)
+    s, n = otables(plan, f, band / C, dt, dms, "greedy", width_s=tau)
     T = plan.max_span + 128
     M, S = orc.boxcar_norm(n, [1], np.zeros(C), np.ones(C))
     norm = np.sqrt(dt / (C * tau))

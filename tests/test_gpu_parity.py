@@ -40,10 +40,10 @@ def _check_detect(orc, y64, n, widths, mu, sg, snr, t, W, wmode="unit", w=None):
         assert alt == pytest.approx(so[d], rel=1e-12), (d, t[d], W[d], to[d], wo[d])
 
 
-def test_cfg1_full(dd, orc):
+def test_cfg1_full(dd, orc, otables):
     wl = workloads.cfg1()
     p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule=wl.rule)
-    s, n = p.tables()
+    s, n = otables(p, wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, wl.rule)
     x = _dev(wl.x)
     y = p.dedisperse(x)
     yo = orc.dedisperse_u8(wl.x, s, n)
@@ -58,11 +58,11 @@ def test_cfg1_full(dd, orc):
 
 
 @pytest.mark.parametrize("rule", ["allnonzero", "smear"])
-def test_cfg2_reduced_all_outputs(dd, orc, rule):
+def test_cfg2_reduced_all_outputs(dd, orc, otables, rule):
     # Several DM tiles and a ragged time tail: 96 trials over 4000 + 2246 samples.
     wl = workloads.cfg2(nsamp=6246, ndm=96, rule=rule)
     p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule=rule)
-    s, n = p.tables()
+    s, n = otables(p, wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule)
     x = _dev(wl.x)
     y = p.dedisperse(x)
     yo = orc.dedisperse_u8(wl.x, s, n)
@@ -71,11 +71,11 @@ def test_cfg2_reduced_all_outputs(dd, orc, rule):
     _check_detect(orc, yo.astype(np.float64), n, wl.widths, wl.chan_mean, wl.chan_sigma, snr, t, W)
 
 
-def test_cfg2_full_size_sampled_trials(dd, orc):
+def test_cfg2_full_size_sampled_trials(dd, orc, otables):
     # Full 336 x 65536 block and 1024 trials; the oracle recomputes 6 whole trials.
     wl = workloads.cfg2()
     p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule=wl.rule)
-    s, n = p.tables()
+    s, n = otables(p, wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, wl.rule)
     x = _dev(wl.x)
     snr, t, W = p.search(x, wl.widths, wl.chan_mean, wl.chan_sigma)
     pick = np.array([0, 1, 257, 512, 1000, 1023])
@@ -94,23 +94,23 @@ def test_cfg2_full_size_sampled_trials(dd, orc):
         assert sn[lo:hi].max() > 6.0
 
 
-def test_cfg3_channel_weights_fp32(dd, orc):
+def test_cfg3_channel_weights_fp32(dd, orc, otables):
     wl = workloads.cfg3(nsamp=20000, ndm=40)
     p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule=wl.rule, wmode="channel",
                 weights=wl.weights)
-    s, n = p.tables()
+    s, n = otables(p, wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, wl.rule)
     y = p.dedisperse(_dev(wl.x)).cpu().numpy()
     yo = orc.dedisperse_f64(wl.x, s, n, "channel", wl.weights)
     rel = np.abs(y - yo) / np.abs(yo)
     assert rel.max() < 1e-5
 
 
-def test_cfg3_full_size_sampled_points(dd, orc):
+def test_cfg3_full_size_sampled_points(dd, orc, otables):
     import torch
     wl = workloads.cfg3(nsamp=262144, ndm=4096)
     p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule=wl.rule, wmode="channel",
                 weights=wl.weights)
-    s, n = p.tables()
+    s, n = otables(p, wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, wl.rule)
     x = _dev(wl.x)
     y = p.dedisperse(x)
     rng = np.random.default_rng(99)
@@ -132,12 +132,12 @@ def _tap_case(B=3, T=3000, D=24, C=40, K=8):
     return f, dms, x, w
 
 
-def test_tap_weights_forward_and_backward(dd, orc):
+def test_tap_weights_forward_and_backward(dd, orc, otables):
     f, dms, x, w = _tap_case()
     B, C, T = x.shape
     K = w.shape[1]
     p = dd.Plan(f, 0.001, 1e-3, dms, rule="fixed", ktaps=K, wmode="tap", weights=w)
-    s, n = p.tables()
+    s, n = otables(p, f, 0.001, 1e-3, dms, "fixed", ktaps=K)
     xd = _dev(x)
     y = p.dedisperse(xd).cpu().numpy()
     yo = orc.dedisperse_f64(x, s, n, "tap", w)
@@ -172,7 +172,7 @@ def test_tap_weights_forward_and_backward(dd, orc):
 
 @pytest.mark.parametrize("tile,xdtype,K", [(-1, "f32", 4), (-2, "f32", 4), (-1, "u8", 4),
                                            (-2, "u8", 4), (-1, "f32", 20), (-1, "u8", 37)])
-def test_tap_backward_many_channel_groups(dd, orc, tile, xdtype, K):
+def test_tap_backward_many_channel_groups(dd, orc, otables, tile, xdtype, K):
     """Dense tap-weight adjoint at 300 channels x 80 trials: the tiled transpose gather
     (several trial groups per channel tile, ragged channel and time tiles) and the
     general kernels (tile -2), both against the oracle; 20 and 37 taps take several
@@ -188,7 +188,7 @@ def test_tap_backward_many_channel_groups(dd, orc, tile, xdtype, K):
     w = (1.0 + 0.1 * rng.standard_normal((C, K))).astype(np.float32)
     p = dd.Plan(f, 0.001, 1e-3, dms, rule="fixed", ktaps=K, wmode="tap", weights=w)
     p.set_tile(tile)
-    s, n = p.tables()
+    s, n = otables(p, f, 0.001, 1e-3, dms, "fixed", ktaps=K)
     assert int(s.max()) > 1000   # delays across a 32-channel tile reach ~150 samples
     nout = p.out_len(T)
     g = rng.standard_normal((B, D, nout)).astype(np.float32)
@@ -262,14 +262,14 @@ def test_edge_cases(dd, orc):
 
 
 @pytest.mark.parametrize("tile", [-1, 0, 9, -2])
-def test_search_zero_noise_deviation(dd, orc, tile):
+def test_search_zero_noise_deviation(dd, orc, otables, tile):
     # Zero channel means and deviations: a window of zeros has S/N 0 / 0 (NaN, which never
     # wins), any window with signal +inf (ties to the smaller width, then the earlier
     # start); trials whose series is all zeros have no candidate (-inf, -1, 0).
     wl = workloads.cfg2(nsamp=3000, ndm=40)
     p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule="allnonzero")
     p.set_tile(tile)
-    s, n = p.tables()
+    s, n = otables(p, wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, "allnonzero")
     # signal only in the last samples of the most delayed channel: only the trials with
     # the largest delays there reach it
     x = np.zeros_like(wl.x)
