@@ -58,10 +58,14 @@ def _traffic(tile: int):
     return t.get("per_tile", {}).get(str(tile), {}).get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(wl, start, ntap, ndm_sample: int):
+def cpu_baseline(wl, rule: str, ndm_sample: int):
     import numpy as np
 
     import oracle
+    # the oracle's own tables for the rule (not timed)
+    start = oracle.delay_start(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms).astype(np.int32)
+    taps = {"smear": oracle.taps_smear, "allnonzero": oracle.taps_allnonzero}[rule]
+    ntap = taps(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms).astype(np.int32)
     pick = np.linspace(0, len(wl.dms) - 1, ndm_sample).round().astype(int)
     T = wl.x.shape[1]
     tout = T - int(np.max(start + ntap)) + 1
@@ -205,7 +209,7 @@ def main() -> int:
     }
     if not args.no_cpu_baseline:
         print("timing the oracle on a sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(wl, start, ntap, args.cpu_sample_trials)
+        line["cpu_baseline"] = cpu_baseline(wl, args.rule, args.cpu_sample_trials)
     print(json.dumps(line), flush=True)
     return 0
 
