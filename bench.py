@@ -90,11 +90,12 @@ def main() -> int:
     ap.add_argument("--cpu-sample-trials", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="search",
-                    choices=["search", "batch", "weighted", "autograd", "completeness"],
+                    choices=["search", "batch", "weighted", "autograd", "completeness", "dm_error"],
                     help="search: the headline fused search (default); batch: 36 beams in one "
                          "launch; weighted: 4096-channel fp32-weighted dedispersion; "
                          "autograd: forward / adjoint timing of the 8-tap learnable profile; "
-                         "completeness: largest S/N over the trial DMs against a test pulse's DM")
+                         "completeness: largest S/N over the trial DMs against a test pulse's DM; "
+                         "dm_error: S/N attenuation with DM error about one trial DM")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (the reference kernel "
                          "for scaling HBM byte counters) and exit")
@@ -273,6 +274,8 @@ def _other_workload(args, dd, workloads) -> int:
                             "ms_eager": t_eager * 1e3, "ms_one_plan_at_a_time": t_single * 1e3})
     elif args.workload == "completeness":
         line = dict(base, **_completeness(dd, workloads, K, W))
+    elif args.workload == "dm_error":
+        line = dict(base, **_dm_error(dd, workloads))
     elif args.workload == "weighted":
         print("generating the 4096-channel block", file=sys.stderr, flush=True)
         wl = workloads.cfg3()
@@ -407,6 +410,71 @@ def _completeness(dd, workloads, K, W):
     out["value"] = total_pts / total_s
     out["ms_per_step"] = total_s * 1e3
     return out
+
+
+# Section 5.1 example: 700-1004 MHz, 1 MHz channels, 1 ms, 1 ms rectangular pulse, trial DM 30.
+DM_ERROR_CASE = (0.700, 0.304, 304, 1e-3, 1e-3, 30.0)
+KDM_S = 1.0 / (2.41e-16 * 1e18)     # dispersion constant, s GHz^2 / (pc cm^-3)
+
+
+def dm_error_unit(case=DM_ERROR_CASE):
+    """The DM-error unit of Section 5.2: (1/C) sqrt(DM^2 + DM_diag^2 + DM_tau^2), with DM_diag
+    and DM_tau the DMs whose mean channel smearing equals dt and the pulse width."""
+    flo, band, C, dt, tau, dm = case
+    f = np.linspace(flo, flo + band, C, endpoint=False) + 0.5 * band / C
+    bw = band / C
+    inv3 = float(np.mean(f ** -3.0))
+    dm_diag = dt / (2.0 * KDM_S * bw * inv3)
+    dm_tau = tau / (2.0 * KDM_S * bw * inv3)
+    return math.sqrt(dm * dm + dm_diag * dm_diag + dm_tau * dm_tau) / C
+
+
+def dm_error_profiles(dd, workloads, xs, case=DM_ERROR_CASE, lead=64):
+    """Dedispersed profiles (eq. rel_snr2) of rectangular test pulses at DM = trial + x units
+    of DM error, through the greedy sample set of the trial DM: batched fp32 dedispersion
+    of the rendered pulses.  Returns (plan, profiles [len(xs)][nout] relative to the
+    matched pulse's peak, seconds)."""
+    import torch
+    flo, band, C, dt, tau, dm = case
+    f = workloads.channel_centres(flo, band, C)
+    bw = band / C
+    plan = dd.Plan(f, bw, dt, [dm], rule="greedy", width_s=tau)
+    T = plan.max_span + 2 * lead
+    unit = dm_error_unit(case)
+    dms = [dm] + [dm + float(x) * unit for x in xs]
+    x = torch.zeros((len(dms), C, T), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b, d in enumerate(dms):
+        c, n, v = workloads.rect_pulse_cells(f, bw, dt, d, tau, lead * dt)
+        ok = (n >= 0) & (n < T)
+        idx = torch.from_numpy(c[ok] * T + n[ok]).cuda()
+        x[b].view(-1).index_put_((idx,), torch.from_numpy(v[ok].astype(np.float32)).cuda(),
+                                 accumulate=True)
+    y = plan.dedisperse(x)[:, 0, :].cpu().numpy().astype(np.float64)
+    secs = time.perf_counter() - t0
+    return plan, y[1:] / y[0].max(), secs
+
+
+def _dm_error(dd, workloads):
+    """Section 5.2: peak relative S/N against the normalised DM error, beside the closed
+    form of eq. snrb/snri_approx, (x^2 + 1)^(-1/4)."""
+    xs = np.linspace(-8.0, 8.0, 161)
+    dm_error_profiles(dd, workloads, xs[:4])                  # warm-up
+    _, prof, secs = dm_error_profiles(dd, workloads, xs)
+    peak = prof.max(axis=1)
+    closed = (xs * xs + 1.0) ** -0.25
+    pick = [0, 40, 60, 70, 75, 80, 85, 90, 100, 120, 160]
+    return {"metric": "DM-error profiles/s (dedispersed test pulses about one trial DM)",
+            "value": len(xs) / secs, "unit": "profiles/s", "ms_per_step": secs * 1e3,
+            "dtype": "fp32",
+            "config": {"workload": "700-1004 MHz x 304 ch, 1 ms, 1 ms pulse, trial DM 30, "
+                                   "DM error -8..8 units",
+                       "dm_error_unit": dm_error_unit(),
+                       "x": [float(xs[i]) for i in pick],
+                       "peak_relative_snr": [float(peak[i]) for i in pick],
+                       "closed_form": [float(closed[i]) for i in pick],
+                       "max_abs_difference": float(np.max(np.abs(peak - closed)))}}
 
 
 def _fused(plan) -> bool:
