@@ -90,12 +90,14 @@ def main() -> int:
     ap.add_argument("--cpu-sample-trials", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="search",
-                    choices=["search", "batch", "weighted", "autograd", "completeness", "dm_error"],
+                    choices=["search", "batch", "weighted", "autograd", "completeness", "dm_error",
+                             "resolution"],
                     help="search: the headline fused search (default); batch: 36 beams in one "
                          "launch; weighted: 4096-channel fp32-weighted dedispersion; "
                          "autograd: forward / adjoint timing of the 8-tap learnable profile; "
                          "completeness: largest S/N over the trial DMs against a test pulse's DM; "
-                         "dm_error: S/N attenuation with DM error about one trial DM")
+                         "dm_error: S/N attenuation with DM error about one trial DM; "
+                         "resolution: peak S/N against the time and frequency resolution")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (the reference kernel "
                          "for scaling HBM byte counters) and exit")
@@ -276,6 +278,8 @@ def _other_workload(args, dd, workloads) -> int:
         line = dict(base, **_completeness(dd, workloads, K, W))
     elif args.workload == "dm_error":
         line = dict(base, **_dm_error(dd, workloads))
+    elif args.workload == "resolution":
+        line = dict(base, **_resolution(dd, workloads))
     elif args.workload == "weighted":
         print("generating the 4096-channel block", file=sys.stderr, flush=True)
         wl = workloads.cfg3()
@@ -475,6 +479,62 @@ def _dm_error(dd, workloads):
                        "peak_relative_snr": [float(peak[i]) for i in pick],
                        "closed_form": [float(closed[i]) for i in pick],
                        "max_abs_difference": float(np.max(np.abs(peak - closed)))}}
+
+
+# Section 4 example: 700 MHz - 1 GHz, 1 ms rectangular pulse, DM 30, no scattering.
+RES_BAND = (0.700, 0.300)
+RES_TAU, RES_DM = 1e-3, 30.0
+
+
+def res_delta_nu0(band=RES_BAND, tau=RES_TAU, dm=RES_DM):
+    """The channel width whose intra-channel smearing equals the pulse width, with the
+    band-averaged nu^-3 (GHz)."""
+    lo, bw = band
+    inv3 = (lo ** -2 - (lo + bw) ** -2) / (2.0 * bw)       # mean of nu^-3 over the band
+    return tau / (2.0 * KDM_S * dm * inv3)
+
+
+def resolution_point(dd, workloads, a, b, rule, band=RES_BAND, tau=RES_TAU, dm=RES_DM, lead=16):
+    """Peak dedispersed S/N (normalised to P0 sqrt(beta tau) / k T_sys) of the test pulse at
+    time resolution a tau and channel width b dnu_0 (channel count rounded), sample sets by
+    `rule`: fp32 dedispersion of one trial on the GPU.  Returns (S/N, plan, dt, channel
+    width, rendered block)."""
+    import torch
+    lo, bw = band
+    C = max(1, int(round(bw / (b * res_delta_nu0(band, tau, dm)))))
+    cw = bw / C
+    dt = a * tau
+    f = workloads.channel_centres(lo, bw, C)
+    plan = dd.Plan(f, cw, dt, [dm], rule=rule, width_s=tau)
+    T = plan.max_span + 2 * lead
+    x = workloads.render_rect_pulse(f, cw, dt, T, dm, tau, lead * dt)
+    y = plan.dedisperse(torch.from_numpy(x).cuda())[0].cpu().numpy().astype(np.float64)
+    _, n = plan.tables()
+    snr = y.max() / math.sqrt(float(n.sum())) * math.sqrt(dt / (C * tau))
+    return snr, plan, dt, cw, x
+
+
+def _resolution(dd, workloads):
+    """Section 4: peak S/N over a grid of dt / tau and dnu / dnu_0 with greedy sample sets
+    (Section 2.2) and with every non-zero sample (eq. num_samples)."""
+    grid = [0.125, 0.25, 0.5, 1.0, 2.0, 4.0, 8.0]
+    t0 = time.perf_counter()
+    g = np.array([[resolution_point(dd, workloads, a, b, "greedy")[0] for b in grid] for a in grid])
+    z = np.array([[resolution_point(dd, workloads, a, b, "allnonzero")[0] for b in grid]
+                  for a in grid])
+    secs = time.perf_counter() - t0
+    diag = np.array([g[i, i] for i in range(len(grid))])
+    return {"metric": "resolution grid points/s (peak S/N, greedy and all-nonzero sample sets)",
+            "value": 2 * len(grid) ** 2 / secs, "unit": "points/s", "ms_per_step": secs * 1e3,
+            "dtype": "fp32",
+            "config": {"workload": "700 MHz-1 GHz, 1 ms rectangular pulse, DM 30, dt/tau and "
+                                   "dnu/dnu0 in 1/8..8",
+                       "dnu0_mhz": res_delta_nu0() * 1e3, "grid": grid,
+                       "snr_greedy": g.tolist(), "snr_allnonzero": z.tolist(),
+                       "greedy_over_allnonzero_max": float(np.max(g / z)),
+                       "greedy_over_allnonzero_min": float(np.min(g / z)),
+                       "diagonal_greedy": diag.tolist(),
+                       "diagonal_closed_form": [float((1.0 + 2.0 * m) ** -0.5) for m in grid]}}
 
 
 def _fused(plan) -> bool:
