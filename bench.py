@@ -91,13 +91,14 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="search",
                     choices=["search", "batch", "weighted", "autograd", "completeness", "dm_error",
-                             "resolution"],
+                             "resolution", "detectors"],
                     help="search: the headline fused search (default); batch: 36 beams in one "
                          "launch; weighted: 4096-channel fp32-weighted dedispersion; "
                          "autograd: forward / adjoint timing of the 8-tap learnable profile; "
                          "completeness: largest S/N over the trial DMs against a test pulse's DM; "
                          "dm_error: S/N attenuation with DM error about one trial DM; "
-                         "resolution: peak S/N against the time and frequency resolution")
+                         "resolution: peak S/N against the time and frequency resolution; "
+                         "detectors: matched filters and boxcar against the greedy detector")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (the reference kernel "
                          "for scaling HBM byte counters) and exit")
@@ -280,6 +281,8 @@ def _other_workload(args, dd, workloads) -> int:
         line = dict(base, **_dm_error(dd, workloads))
     elif args.workload == "resolution":
         line = dict(base, **_resolution(dd, workloads))
+    elif args.workload == "detectors":
+        line = dict(base, **_detectors(dd, workloads))
     elif args.workload == "weighted":
         print("generating the 4096-channel block", file=sys.stderr, flush=True)
         wl = workloads.cfg3()
@@ -535,6 +538,71 @@ def _resolution(dd, workloads):
                        "greedy_over_allnonzero_min": float(np.min(g / z)),
                        "diagonal_greedy": diag.tolist(),
                        "diagonal_closed_form": [float((1.0 + 2.0 * m) ** -0.5) for m in grid]}}
+
+
+def detector_snrs(dd, workloads, b, band=RES_BAND, tau=RES_TAU, dm=RES_DM, lead=16):
+    """Section 4 detectors for the rendered test pulse at channel width b dnu_0 and dt = tau,
+    each as a dedispersion of the block at the pulse's DM on the GPU (normalised to
+    P0 sqrt(beta tau) / k T_sys, unit noise per sample): the dynamic-spectrum matched filter
+    (tap weights = the pulse's own cells P), the time-series matched filter (every
+    channel weighted by the channel sum of P at each tap), the time-series boxcar (unit
+    weights over the pulse's dedispersed width in every channel) and the greedy detector
+    (Section 2.2 sample set).  Returns ({name: S/N}, P [C][K], dt, channel width)."""
+    import torch
+    lo, bw = band
+    C = max(1, int(round(bw / (b * res_delta_nu0(band, tau, dm)))))
+    cw, dt = bw / C, tau
+    f = workloads.channel_centres(lo, bw, C)
+    p0 = dd.Plan(f, cw, dt, [dm], rule="allnonzero", width_s=tau)
+    s0, n0 = p0.tables()
+    K = int(n0.max())
+    T = p0.max_span + K + 2 * lead
+    x = workloads.render_rect_pulse(f, cw, dt, T, dm, tau, lead * dt)
+    xd = torch.from_numpy(x).cuda()
+    idx = lead + s0[0][:, None] + np.arange(K)[None, :]
+    P = x[np.arange(C)[:, None], idx].astype(np.float64)        # [C][K] cells of the pulse
+    norm = math.sqrt(dt / (C * tau))
+    start = s0.copy()
+    full = np.full((1, C), K, dtype=np.int32)
+
+    def weighted(w):
+        p = dd.Plan(f, cw, dt, [dm], rule="explicit", start=start, ntap=full, ktaps=K,
+                    wmode="tap", weights=w.astype(np.float32))
+        y = p.dedisperse(xd)[0].cpu().numpy().astype(np.float64)
+        w32 = w.astype(np.float32).astype(np.float64)
+        return y.max() / math.sqrt(float(np.sum(w32 ** 2))) * norm
+
+    out = {"dsmf": weighted(P)}
+    prof = P.sum(axis=0)                                         # channel sum per tap
+    out["mf"] = weighted(np.broadcast_to(prof, (C, K)).copy())
+    nt = int(np.count_nonzero(prof > 0.0))
+    nts = np.full((1, C), nt, dtype=np.int32)
+    first = int(np.argmax(prof > 0.0))
+    pb = dd.Plan(f, cw, dt, [dm], rule="explicit", start=start + first, ntap=nts)
+    yb = pb.dedisperse(xd)[0].cpu().numpy().astype(np.float64)
+    out["boxcar"] = yb.max() / math.sqrt(float(C * nt)) * norm
+    pg = dd.Plan(f, cw, dt, [dm], rule="greedy", width_s=tau)
+    yg = pg.dedisperse(xd)[0].cpu().numpy().astype(np.float64)
+    out["greedy"] = yg.max() / math.sqrt(float(pg.tables()[1].sum())) * norm
+    return out, P, dt, cw
+
+
+def _detectors(dd, workloads):
+    """Section 4: the four detectors against the channel width, dt = tau."""
+    grid = [0.125, 0.25, 0.5, 1.0, 2.0, 4.0, 8.0]
+    t0 = time.perf_counter()
+    res = [detector_snrs(dd, workloads, b)[0] for b in grid]
+    secs = time.perf_counter() - t0
+    names = ["dsmf", "mf", "boxcar", "greedy"]
+    return {"metric": "detector comparisons/s (four detectors per channel width)",
+            "value": len(grid) / secs, "unit": "points/s", "ms_per_step": secs * 1e3,
+            "dtype": "fp32",
+            "config": {"workload": "700 MHz-1 GHz, 1 ms rectangular pulse, DM 30, dt = tau, "
+                                   "dnu/dnu0 in 1/8..8",
+                       "dnu_over_dnu0": grid,
+                       **{k: [float(r[k]) for r in res] for k in names},
+                       "dsmf_best_everywhere": bool(all(r["dsmf"] >= max(r[k] for k in names) - 1e-9
+                                                        for r in res))}}
 
 
 def _fused(plan) -> bool:
