@@ -185,8 +185,8 @@ __device__ __forceinline__ void norm_terms(int wmode, int K, const float *__rest
 // channel residues.  The trials' tap counts and the channel statistics are staged
 // in LDS a chunk of channels at a time; the kNormSplit partial sums of a (trial,
 // width) are added in a fixed order, so results do not vary between runs.
-constexpr int kNormTrials = 2, kNormSplit = 4, kNormChunk = 512;
-static_assert(kThreads == kNormTrials * 32 * kNormSplit, "thread layout of k_norm");
+constexpr int kNormTrials = 1, kNormSplit = 16, kNormChunk = 512;
+constexpr int kNormThreads = kNormTrials * 32 * kNormSplit;
 
 // Sum and sum of squares of the n-box convolved with the W-box: a trapezoid
 // 1, 2, .., L, .., L, .., 2, 1 with L = min(n, W) (exact integers).
@@ -201,7 +201,7 @@ __device__ __forceinline__ void trapezoid(int n, int W, double &s1, double &s2) 
   }
 }
 
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kNormThreads)
 k_norm(const int32_t *__restrict__ ntap, int32_t nchan, int32_t ndm, int32_t wmode, int32_t K,
        const float *__restrict__ w, const double *__restrict__ mu,
        const double *__restrict__ sigma, WidthList wl, double *__restrict__ M,
@@ -220,11 +220,11 @@ k_norm(const int32_t *__restrict__ ntap, int32_t nchan, int32_t ndm, int32_t wmo
   for (int c0 = 0; c0 < nchan; c0 += kNormChunk) {
     const int cn = min(kNormChunk, nchan - c0);
     __syncthreads();
-    for (int i = tid; i < kNormTrials * kNormChunk; i += kThreads) {
+    for (int i = tid; i < kNormTrials * kNormChunk; i += kNormThreads) {
       const int t = i / kNormChunk, c = i - t * kNormChunk;
       sn[t][c] = (c < cn && d0 + t < ndm) ? ntap[(int64_t)(d0 + t) * nchan + c0 + c] : 0;
     }
-    for (int c = tid; c < cn; c += kThreads) {
+    for (int c = tid; c < cn; c += kNormThreads) {
       smu[c] = mu[c0 + c];
       svar[c] = sigma[c0 + c] * sigma[c0 + c];
     }
@@ -711,7 +711,7 @@ hipError_t launch_dedisp_1tap_f32(const dedisp_plan_s *p, const float *z, int64_
 
 hipError_t launch_norm(const dedisp_plan_s *p, const WidthList &wl, const double *mu,
                        const double *sigma, double *M, double *S, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm, dim3((unsigned)((p->ndm + kNormTrials - 1) / kNormTrials)), dim3(kThreads), 0, s,
+  hipLaunchKernelGGL(k_norm, dim3((unsigned)((p->ndm + kNormTrials - 1) / kNormTrials)), dim3(kNormThreads), 0, s,
                      p->dev.ntap, p->nchan, p->ndm, p->wmode, p->ktaps, weights_of(p), mu, sigma,
                      wl, M, S);
   return hipGetLastError();
