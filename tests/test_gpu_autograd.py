@@ -101,3 +101,29 @@ def test_training_improves_snr(setup):
         opt.step()
         first = float(L) if first is None else first
     assert float(matched_filter_loss(x, w, p, b, d, t)) < first
+
+
+def test_training_approaches_the_dynamic_spectrum_matched_filter(setup, orc):
+    # The loss is the negative mean S/N of <G, w> / ||w|| with G = d(sum_e y_e)/dw (the
+    # sum is linear in w), so its optimum is w parallel to G (the dynamic-spectrum matched
+    # filter of the batch's pulses, Section 4), with S/N ||G|| / B (Cauchy-Schwarz).
+    import torch
+    from paper_1301_3968_amd.autograd import matched_filter_loss
+    dd, wl, p, s, n, x, b, d, t = setup
+    B = len(b)
+    g = np.zeros((wl.x.shape[0], s.shape[0], wl.x.shape[2] - int(np.max(s + n)) + 1))
+    np.add.at(g, (b, d, t), 1.0)
+    G = orc.adjoint_w(wl.x, s, n, g, "tap", wl.weights.shape[1])
+    best = np.linalg.norm(G) / B
+    w = torch.from_numpy(wl.weights.copy()).cuda().requires_grad_(True)
+    opt = torch.optim.Adam([w], lr=0.02)
+    snr0 = -float(matched_filter_loss(x, w, p, b, d, t))
+    for _ in range(300):
+        opt.zero_grad()
+        matched_filter_loss(x, w, p, b, d, t).backward()
+        opt.step()
+    snr = -float(matched_filter_loss(x, w, p, b, d, t))
+    wl_ = w.detach().cpu().numpy().astype(np.float64)
+    cos = float(np.sum(wl_ * G) / (np.linalg.norm(wl_) * np.linalg.norm(G)))
+    assert snr0 < snr <= best * (1.0 + 1e-6)
+    assert snr > 0.97 * best and cos > 0.97, (snr0, snr, best, cos)
