@@ -337,6 +337,24 @@ def test_matrix_core_search_shapes(dd, orc, cfg2_dense, tile):
     _check_detect(orc, yo, n, wl.widths, wl.chan_mean, wl.chan_sigma, snr, t, W)
 
 
+@pytest.mark.parametrize("tile", [8, 9, 10, 11])
+def test_matrix_core_short_series_odd_trials(dd, orc, otables, tile):
+    # 37 trials (no DM tile full) and 100 outputs (one partial time tile): every
+    # matrix-core shape, the fused search and the int32 dedispersion.
+    wl = workloads.cfg2(nsamp=3000, ndm=37)
+    p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule="allnonzero")
+    s, n = otables(p, wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, "allnonzero")
+    T = p.max_span + 99
+    x = np.ascontiguousarray(wl.x[:, :T])
+    p.set_tile(tile)
+    yo = orc.dedisperse_u8(x, s, n)
+    y = p.dedisperse(_dev(x)).cpu().numpy()
+    assert np.array_equal(y.astype(np.int64), yo)
+    snr, t, W = p.search(_dev(x), wl.widths, wl.chan_mean, wl.chan_sigma)
+    assert p.last_search_tile() == tile
+    _check_detect(orc, yo.astype(np.float64), n, wl.widths, wl.chan_mean, wl.chan_sigma, snr, t, W)
+
+
 def test_default_search_runs_on_the_matrix_cores(dd, orc, cfg2_mid):
     wl, n, yo = cfg2_mid
     p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule="allnonzero")
