@@ -46,7 +46,8 @@ namespace dd {
   X(0, 4, 2, 2)            \
   X(1, 8, 1, 2)            \
   X(2, 8, 2, 1)            \
-  X(3, 16, 1, 1)
+  X(3, 16, 1, 1)           \
+  X(4, 4, 4, 1)
 struct MfmaCfg {
   int nwd, nwt, wg;
 };

@@ -304,10 +304,10 @@ def cfg2_mid(orc):
     return wl, n, yo
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, -2])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, -2])
 def test_fused_search_every_tile_config(dd, orc, cfg2_mid, tile):
     # Ragged in both DM (100 trials) and time (6755 outputs) for every shape: 0-7 the
-    # packed-add kernel, 8-11 the matrix-core kernel, -2 the unfused path.
+    # packed-add kernel, 8-12 the matrix-core kernel, -2 the unfused path.
     wl, n, yo = cfg2_mid
     p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule="allnonzero")
     p.set_tile(tile)
@@ -325,7 +325,7 @@ def cfg2_dense(orc):
     return wl, n, yo
 
 
-@pytest.mark.parametrize("tile", [8, 9, 10, 11])
+@pytest.mark.parametrize("tile", [8, 9, 10, 11, 12])
 def test_matrix_core_search_shapes(dd, orc, cfg2_dense, tile):
     # 300 trials: three DM tiles of 128 (or five of 64) trials with a ragged last tile,
     # ragged time.
@@ -337,7 +337,7 @@ def test_matrix_core_search_shapes(dd, orc, cfg2_dense, tile):
     _check_detect(orc, yo, n, wl.widths, wl.chan_mean, wl.chan_sigma, snr, t, W)
 
 
-@pytest.mark.parametrize("tile", [8, 9, 10, 11])
+@pytest.mark.parametrize("tile", [8, 9, 10, 11, 12])
 def test_matrix_core_short_series_odd_trials(dd, orc, otables, tile):
     # 37 trials (no DM tile full) and 100 outputs (one partial time tile): every
     # matrix-core shape, the fused search and the int32 dedispersion.
