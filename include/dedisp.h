@@ -46,7 +46,7 @@ typedef enum {
   DEDISP_ERR_OVERFLOW = 3,    /* an int32 sum could exceed 2^31 - 1 */
   DEDISP_ERR_OOM = 4,         /* host or device allocation failed */
   DEDISP_ERR_DEVICE = 5,      /* a HIP call failed (message in dedisp_last_error) */
-  DEDISP_ERR_UNSUPPORTED = 6  /* valid request this build does not implement */
+  DEDISP_ERR_UNSUPPORTED = 6  /* a valid request the library does not implement */
 } dedisp_status;
 
 typedef enum { DEDISP_U8 = 0, DEDISP_F32 = 1, DEDISP_I32 = 2 } dedisp_dtype;
