@@ -71,27 +71,47 @@ def test_cfg2_reduced_all_outputs(dd, orc, otables, rule):
     _check_detect(orc, yo.astype(np.float64), n, wl.widths, wl.chan_mean, wl.chan_sigma, snr, t, W)
 
 
-def test_cfg2_full_size_sampled_trials(dd, orc, otables):
+@pytest.fixture(scope="module")
+def cfg2_full(dd, orc, otables):
     # Full 336 x 65536 block and 1024 trials; the oracle recomputes 6 whole trials.
     wl = workloads.cfg2()
     p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule=wl.rule)
     s, n = otables(p, wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, wl.rule)
-    x = _dev(wl.x)
-    snr, t, W = p.search(x, wl.widths, wl.chan_mean, wl.chan_sigma)
     pick = np.array([0, 1, 257, 512, 1000, 1023])
     yo = orc.dedisperse_u8(wl.x, s[pick], n[pick], tout=wl.x.shape[1] - p.max_span + 1)
+    return wl, p, n, pick, yo
+
+
+# The default shape, the shape the benchmark's autotuner picks on the boxes measured so
+# far, and whatever it picks on this one (the launch configuration the benchmark times).
+@pytest.mark.parametrize("tile", [-1, 12, "autotuned"])
+def test_cfg2_full_size_sampled_trials(dd, orc, cfg2_full, tile):
     import torch
+    wl, p, n, pick, yo = cfg2_full
+    x = _dev(wl.x)
+    mu = torch.as_tensor(wl.chan_mean, dtype=torch.float64).cuda()
+    sg = torch.as_tensor(wl.chan_sigma, dtype=torch.float64).cuda()
+    if tile == "autotuned":
+        p.autotune(x, wl.widths, mu, sg)
+    else:
+        p.set_tile(tile)
+    snr, t, W = p.search(x, wl.widths, mu, sg)
+    if tile == 12:
+        assert p.last_search_tile() == 12
+    elif tile == "autotuned":
+        assert 0 <= p.last_search_tile() <= 12
+    sel = torch.as_tensor(pick).cuda()
     _check_detect(orc, yo.astype(np.float64), n[pick], wl.widths, wl.chan_mean, wl.chan_sigma,
-                  snr[torch.as_tensor(pick).cuda()], t[torch.as_tensor(pick).cuda()],
-                  W[torch.as_tensor(pick).cuda()])
+                  snr[sel], t[sel], W[sel])
     y = p.dedisperse(x)
-    assert np.array_equal(y[torch.as_tensor(pick).cuda()].cpu().numpy().astype(np.int64), yo)
+    assert np.array_equal(y[sel].cpu().numpy().astype(np.int64), yo)
     # The strongest injected pulses are found near their DM.
     sn = snr.cpu().numpy()
     for pl in wl.pulses[:4]:
         d = int(np.argmin(np.abs(wl.dms - pl.dm)))
         lo, hi = max(0, d - 3), min(len(wl.dms), d + 4)
         assert sn[lo:hi].max() > 6.0
+    p.set_tile(-1)
 
 
 def test_cfg3_channel_weights_fp32(dd, orc, otables):
