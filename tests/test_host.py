@@ -132,3 +132,13 @@ def test_errors(dd):
     assert e.value.status == _lib.ERR_UNSUPPORTED
     # The thread-local message describes the failure.
     assert b"ntap" in _lib.lib().dedisp_last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # The benchmark measures one GPU; asked for more it says so and exits before any GPU work.
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
