@@ -135,9 +135,14 @@ __device__ __forceinline__ CandRec boxcar_row(int *Yw, int lane, int64_t t0, int
   for (int k = 0; k < SP + kHalo; ++k) qv[k + 1] = qv[k] + yl[k];
   __builtin_amdgcn_wave_barrier();
   if (tail) {
+    // An opaque copy of the limit, so that the compiler neither folds this branch into
+    // selects run for every row nor hoists the comparisons out of the caller's row loop
+    // (their masks would occupy scalar registers across it)
+    int lt = lim;
+    asm volatile("" : "+v"(lt));
 #pragma unroll
     for (int k = 0; k <= SP + kHalo; ++k)
-      if (k > lim) qv[k] = (INT_MIN / 4) - (k - lim);
+      if (k > lt) qv[k] = (INT_MIN / 4) - (k - lt);
   }
   // Per width: the lane maximum over its starts (made for all 32 widths; the
   // widths not searched are dropped at the S/N step), reduced across the wave
