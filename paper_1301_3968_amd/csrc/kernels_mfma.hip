@@ -304,23 +304,14 @@ __device__ __forceinline__ TileAcc<kNT> mfma_tile(MA &a, int tw, int64_t T0, con
     const int ro = ldc(&a.groups[g].rec_off, 0);
     const int k0 = ldc(a.kbr, (int64_t)kbase + wd), k1 = ldc(a.kbr, (int64_t)kbase + wd + 1);
     const unsigned char *rb = buf + ro + (int64_t)(k0 - kf) * kRecBytes;
-    // the next K block's mask and samples are read while this one's products run
-    uint32_t m16n = 0;
-    v8i wn = {0, 0, 0, 0, 0, 0, 0, 0};   // one 8-register tuple (two 16-byte reads)
-    if (k0 < k1) {
-      m16n = *(const uint16_t *)(rb + 2 * lane);
-      const int32_t ad = *(const int32_t *)(rb + 128 + 4 * (lane >> 4)) + loff;
-      wn = *(const v8i *)(buf + ad);
-    }
-    for (int kb = k0; kb < k1; ++kb) {
-      const uint32_t m16 = m16n;
-      const v8i W = wn;
-      rb += kRecBytes;
-      if (kb + 1 < k1) {
-        m16n = *(const uint16_t *)(rb + 2 * lane);
-        const int32_t ad = *(const int32_t *)(rb + 128 + 4 * (lane >> 4)) + loff;
-        wn = *(const v8i *)(buf + ad);
-      }
+    // K blocks in pairs through two register sets, each block's mask and samples read
+    // while the other block's products run (no copies between the sets)
+    auto load = [&](const unsigned char *r, uint32_t &m, v8i &w) {
+      m = *(const uint16_t *)(r + 2 * lane);
+      const int32_t ad = *(const int32_t *)(r + 128 + 4 * (lane >> 4)) + loff;
+      w = *(const v8i *)(buf + ad);   // one 8-register tuple (two 16-byte reads)
+    };
+    auto products = [&](uint32_t m16, const v8i &W) {
       // 16 mask bytes of lane (trial row lane % 16, segment lane / 16): bit j -> byte j
       v4i mk;
 #pragma unroll
@@ -332,7 +323,19 @@ __device__ __forceinline__ TileAcc<kNT> mfma_tile(MA &a, int tw, int64_t T0, con
       mfma4<1>(acc, mk, W);
       mfma4<2>(acc, mk, W);
       mfma4<3>(acc, mk, W);
+    };
+    uint32_t ma = 0, mb = 0;
+    v8i wa = {0, 0, 0, 0, 0, 0, 0, 0}, wb = {0, 0, 0, 0, 0, 0, 0, 0};
+    int kb = k0;
+    if (kb < k1) load(rb, ma, wa);
+    for (; kb + 1 < k1; kb += 2) {
+      load(rb + kRecBytes, mb, wb);
+      products(ma, wa);
+      if (kb + 2 < k1) load(rb + 2 * kRecBytes, ma, wa);
+      products(mb, wb);
+      rb += 2 * kRecBytes;
     }
+    if (kb < k1) products(ma, wa);
     if (g + 1 < ge) store(lds + (par ^ 1) * a.bufbytes);
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
