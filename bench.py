@@ -87,7 +87,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--rule", default="allnonzero", choices=["allnonzero", "smear"])
-    ap.add_argument("--cpu-sample-trials", type=int, default=48)
+    ap.add_argument("--cpu-sample-trials", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="search",
                     choices=["search", "batch", "weighted", "autograd", "completeness", "dm_error",
