@@ -63,7 +63,7 @@ constexpr int kMfmaBufBytes = 80 * 1024;    // LDS per staging buffer (two per w
 // K-block record: 64 x u16 masks (lane = 16 segment + trial row), then the LDS byte
 // address of each of the 4 segments' aligned bytes (lane 16 g + n reads 32 bytes at
 // address[g] + 16 n)
-constexpr int kRecBytes = 144;
+constexpr int kRecBytes = 160;
 // Staging: one chunk (16 window bytes in all 4 copies) per thread and group, so a
 // group stages at most 64 NW chunks (registers: the chunk's raw bytes are held through
 // the current group's products).
@@ -199,6 +199,7 @@ struct TileAcc {
 };
 
 typedef int32_t v8i __attribute__((ext_vector_type(8)));
+typedef int32_t v2i __attribute__((ext_vector_type(2)));
 
 // Shifted samples: T[k] = the lane's bytes shifted down by S bytes, dword k + O (k < 6;
 // dwords 6, 7 unused).  Block 4 q + S takes dwords q .. q + 3 of the shifted bytes: from
@@ -225,9 +226,10 @@ __device__ __forceinline__ v8i shifted(const v8i &w) {
 
 // The products of blocks S, S + 4, S + 8, S + 12.
 template <int S>
-__device__ __forceinline__ void mfma4(v4i (&acc)[kNT], const v4i &mk, const v8i &w) {
+__device__ __forceinline__ void mfma4(v4i (&acc)[kNT], const v4i &mk, const v8i &w,
+                                      const v8i &w1) {
   const v8i e = S == 0 ? w : shifted<S, 0>(w);
-  const v8i o = shifted<S, 1>(w);
+  const v8i o = S == 0 ? w1 : shifted<S, 1>(w);
   acc[S] = __builtin_amdgcn_mfma_i32_16x16x64_i8(mk, __builtin_shufflevector(e, e, 0, 1, 2, 3),
                                                  acc[S], 0, 0, 0);
   acc[S + 4] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
@@ -306,12 +308,17 @@ __device__ __forceinline__ TileAcc<kNT> mfma_tile(MA &a, int tw, int64_t T0, con
     const unsigned char *rb = buf + ro + (int64_t)(k0 - kf) * kRecBytes;
     // K blocks in pairs through two register sets, each block's mask and samples read
     // while the other block's products run (no copies between the sets)
-    auto load = [&](const unsigned char *r, uint32_t &m, v8i &w) {
+    auto load = [&](const unsigned char *r, uint32_t &m, v8i &w, int32_t &a1) {
       m = *(const uint16_t *)(r + 2 * lane);
       const int32_t ad = *(const int32_t *)(r + 128 + 4 * (lane >> 4)) + loff;
+      a1 = *(const int32_t *)(r + 144 + 4 * (lane >> 4)) + loff;
       w = *(const v8i *)(buf + ad);   // one 8-register tuple (two 16-byte reads)
     };
-    auto products = [&](uint32_t m16, const v8i &W) {
+    auto products = [&](uint32_t m16, const v8i &W, int32_t a1) {
+      // the same bytes from 4 bytes on (dwords 1 .. 6), read in place of copies into
+      // even-aligned registers for the unshifted blocks at odd dword offsets, which go last
+      const v4i lo = *(const v4i *)(buf + a1);
+      const v2i hi = *(const v2i *)(buf + a1 + 16);
       // 16 mask bytes of lane (trial row lane % 16, segment lane / 16): bit j -> byte j
       v4i mk;
 #pragma unroll
@@ -319,23 +326,25 @@ __device__ __forceinline__ TileAcc<kNT> mfma_tile(MA &a, int tw, int64_t T0, con
         mk[k] = (int32_t)((((m16 >> (4 * k)) & 15u) * 0x204081u) & 0x01010101u);
       // Block b = 4 q + s takes bytes b .. b + 15 of the lane's 32: dwords q .. q + 3 of
       // the lane's bytes shifted down by s
-      mfma4<0>(acc, mk, W);
-      mfma4<1>(acc, mk, W);
-      mfma4<2>(acc, mk, W);
-      mfma4<3>(acc, mk, W);
+      mfma4<1>(acc, mk, W, W);
+      mfma4<2>(acc, mk, W, W);
+      mfma4<3>(acc, mk, W, W);
+      const v8i W1 = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], 0, 0};
+      mfma4<0>(acc, mk, W, W1);
     };
     uint32_t ma = 0, mb = 0;
+    int32_t aa = 0, ab = 0;
     v8i wa = {0, 0, 0, 0, 0, 0, 0, 0}, wb = {0, 0, 0, 0, 0, 0, 0, 0};
     int kb = k0;
-    if (kb < k1) load(rb, ma, wa);
+    if (kb < k1) load(rb, ma, wa, aa);
     for (; kb + 1 < k1; kb += 2) {
-      load(rb + kRecBytes, mb, wb);
-      products(ma, wa);
-      if (kb + 2 < k1) load(rb + 2 * kRecBytes, ma, wa);
-      products(mb, wb);
+      load(rb + kRecBytes, mb, wb, ab);
+      products(ma, wa, aa);
+      if (kb + 2 < k1) load(rb + 2 * kRecBytes, ma, wa, aa);
+      products(mb, wb, ab);
       rb += 2 * kRecBytes;
     }
-    if (kb < k1) products(ma, wa);
+    if (kb < k1) products(ma, wa, aa);
     if (g + 1 < ge) store(lds + (par ^ 1) * a.bufbytes);
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
@@ -606,8 +615,9 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
         nseg[w * C + c] = (h[w] - (slo + o) + 15) / 16;
         qmax = std::max(qmax, (o + 16 * (nseg[w * C + c] - 1)) / 16);
       }
-      // lane n of time wave wt reads chunks q + n + 16 wt and q + n + 1 + 16 wt
-      clen[c] = 16 * (qmax + 16 * cf.nwt + 1);
+      // lane n of time wave wt reads chunks q + n + 16 wt and q + n + 1 + 16 wt, and 24
+      // bytes from 4 bytes further on (up to chunk q + n + 2 + 16 wt)
+      clen[c] = 16 * (qmax + 16 * cf.nwt + 2);
       if ((int64_t)kCopies * clen[c] + kRecBytes > BUF || clen[c] / 16 > maxunits) return false;
     }
     int c = 0;
@@ -655,9 +665,13 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
             // padding segments: zero masks, a valid address
             const size_t si = s0 + g < segs.size() ? s0 + g : s0;
             const int cc = segs[si].first, o = segs[si].second;
-            // copy (o / 4) mod 4 holds window byte o at offset 16 (o / 16)
+            // copy (o / 4) mod 4 holds window byte o at offset 16 (o / 16); the second
+            // address is that of byte o + 4
             const int32_t ad = region[cc] + ((o >> 2) & 3) * clen[cc] + 16 * (o >> 4);
+            const int32_t ad1 =
+                region[cc] + (((o + 4) >> 2) & 3) * clen[cc] + 16 * ((o + 4) >> 4);
             std::memcpy(rec.data() + 128 + 4 * g, &ad, 4);
+            std::memcpy(rec.data() + 144 + 4 * g, &ad1, 4);
             if (s0 + g >= segs.size()) continue;
             const int oa = wlo[cc] + o;   // absolute delay of the segment's first byte
             for (int m = 0; m < 16; ++m) {
