@@ -196,6 +196,10 @@ def main() -> int:
                     "kernel_ms": kern_ms, "ops_per_launch": valu_ops,
                     "peak_packed_u16": PACKED_PEAK_OPS / 1e12,
                     "frac_packed_u16": valu_ops / kern_s / PACKED_PEAK_OPS}
+    # the counted HBM bytes of one launch over its measured duration
+    if roofline["traffic"] is not None:
+        rate = roofline["traffic"] / kern_s
+        roofline["traffic_rate"] = {"GB/s": rate / 1e9, "frac_of_hbm_peak": rate / HBM_PEAK_BYTES}
     line = {
         "metric": "DM-trial*channel*sample sums/s", "value": value, "unit": "sums/s",
         "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": ms_step,
