@@ -336,6 +336,9 @@ __device__ __forceinline__ TileAcc<kNT> mfma_tile(MA &a, int tw, int64_t T0, con
     int32_t aa = 0, ab = 0;
     v8i wa = {0, 0, 0, 0, 0, 0, 0, 0}, wb = {0, 0, 0, 0, 0, 0, 0, 0};
     int kb = k0;
+    // products first: while they run, this wave is issued ahead of waves (of the CU's other
+    // workgroup) in their staging or boxcar stage
+    __builtin_amdgcn_s_setprio(1);
     if (kb < k1) load(rb, ma, wa, aa);
     for (; kb + 1 < k1; kb += 2) {
       load(rb + kRecBytes, mb, wb, ab);
@@ -345,6 +348,7 @@ __device__ __forceinline__ TileAcc<kNT> mfma_tile(MA &a, int tw, int64_t T0, con
       rb += 2 * kRecBytes;
     }
     if (kb < k1) products(ma, wa, aa);
+    __builtin_amdgcn_s_setprio(0);
     if (g + 1 < ge) store(lds + (par ^ 1) * a.bufbytes);
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
