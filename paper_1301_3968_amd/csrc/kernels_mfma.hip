@@ -336,8 +336,8 @@ __device__ __forceinline__ TileAcc<kNT> mfma_tile(MA &a, int tw, int64_t T0, con
     int32_t aa = 0, ab = 0;
     v8i wa = {0, 0, 0, 0, 0, 0, 0, 0}, wb = {0, 0, 0, 0, 0, 0, 0, 0};
     int kb = k0;
-    // products first: while they run, this wave is issued ahead of waves (of the CU's other
-    // workgroup) in their staging or boxcar stage
+    // while its products run, this wave is issued ahead of waves in their staging stores or
+    // boxcar stage (of the CU's other workgroup, or of this one)
     __builtin_amdgcn_s_setprio(1);
     if (kb < k1) load(rb, ma, wa, aa);
     for (; kb + 1 < k1; kb += 2) {
