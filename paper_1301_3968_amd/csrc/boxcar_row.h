@@ -18,30 +18,6 @@ struct CandRec {
   int32_t w;
 };
 
-// Earliest start i < SP (of this lane) whose width-W window, qv[i + W] - qv[i], equals
-// b and lies inside the valid outputs (i + W <= lim); -1 if none.
-template <int SP, int W>
-__device__ __forceinline__ int first_start(const int *qv, int b, int lim) {
-  int first = -1;
-#pragma unroll
-  for (int i = SP - 1; i >= 0; --i)
-    if (i + W <= lim && qv[i + W] - qv[i] == b) first = i;
-  return first;
-}
-
-// first_start for a wave-uniform width w in [LO, HI], by a binary tree of uniform
-// branches (register arrays cannot be indexed by a run-time value).
-template <int SP, int LO, int HI>
-__device__ __forceinline__ int first_start_of(int w, const int *qv, int b, int lim) {
-  if constexpr (LO == HI) {
-    return first_start<SP, LO>(qv, b, lim);
-  } else {
-    constexpr int MID = (LO + HI) / 2;
-    if (w <= MID) return first_start_of<SP, LO, MID>(w, qv, b, lim);
-    return first_start_of<SP, MID + 1, HI>(w, qv, b, lim);
-  }
-}
-
 // Lane l's double.
 __device__ __forceinline__ double rl_double(double x, int l) {
   const uint64_t u = __builtin_bit_cast(uint64_t, x);
