@@ -418,16 +418,6 @@ def snr_approx(P0, beta, tau, kTsys, dnu, dt, N_S, bracket) -> float:
     return P0 * beta * tau / (kTsys * math.sqrt(dnu * dt * N_S)) * bracket
 
 
-def snr0(P0, beta, tau, kTsys, bracket) -> float:
-    """eq. snr_0: S/N at infinitely fine resolution without scattering."""
-    return P0 * math.sqrt(beta * tau) / kTsys * bracket
-
-
-def snr0_prime(snr_0, tau, tau_av) -> float:
-    """eq. snr'_0: SNR_0 sqrt(tau / tau'_av)."""
-    return snr_0 * math.sqrt(tau / tau_av)
-
-
 def delta_nu0(freqs_ghz, tau_av_s, dm, kdm=KDM_PAPER) -> float:
     """eq. delta_nu_0: spectral resolution where the mean intra-channel smear equals tau'_av."""
     return tau_av_s / (2.0 * dm * kdm) / mean_inv_cube(freqs_ghz)
