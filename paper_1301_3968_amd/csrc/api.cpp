@@ -25,6 +25,39 @@ static dedisp_status make_widths(const int32_t *widths, int32_t nw, int64_t nout
   return DEDISP_OK;
 }
 
+hipError_t ArgStage::copy(void *d_dst, const void *src, size_t n, hipStream_t s) {
+  if (done) {
+    hipError_t e = hipEventSynchronize(done);
+    if (e != hipSuccess) return e;
+  } else {
+    hipError_t e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  if (n > cap) {
+    if (host) (void)hipHostFree(host);
+    host = nullptr;
+    cap = 0;
+    hipError_t e = hipHostMalloc(&host, n, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    cap = n;
+  }
+  memcpy(host, src, n);
+  hipError_t e = hipMemcpyAsync(d_dst, host, n, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  return hipEventRecord(done, s);
+}
+
+void ArgStage::release() {
+  if (done) {
+    (void)hipEventSynchronize(done);
+    (void)hipEventDestroy(done);
+  }
+  if (host) (void)hipHostFree(host);
+  host = nullptr;
+  done = nullptr;
+  cap = 0;
+}
+
 static int32_t nchunks(int64_t nout) { return (int32_t)((nout + kBoxChunk - 1) / kBoxChunk); }
 
 size_t detect_work_bytes(int32_t ndm, int32_t nw, int64_t nout) {

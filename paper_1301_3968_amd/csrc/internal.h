@@ -199,7 +199,7 @@ size_t mfma_batch_work_bytes(const MfmaBatch *B);
 dedisp_status mfma_batch_enqueue(MfmaBatch *B, const void *const *in, const int64_t *stride,
                                  const double *mu, const double *sigma, double *snr, int32_t *t,
                                  int32_t *w, const std::vector<int64_t> &out_off, void *work,
-                                 hipStream_t s, bool copy_args, KernelTimer *kt);
+                                 hipStream_t s, bool for_graph, KernelTimer *kt);
 dedisp_status mfma_batch_upload(MfmaBatch *B);
 void mfma_batch_free(MfmaBatch *B);
 // zbar[b][c][tau] = sum_d g[b][d][tau - start[d][c]] for tau in [0, nz) on the same
@@ -207,6 +207,18 @@ void mfma_batch_free(MfmaBatch *B);
 dedisp_status run_adjoint_z_tiled(dedisp_plan p, const float *g, int64_t nout, int64_t gstride,
                                   int64_t gbstride, int32_t nbatch, int64_t nz, float *z,
                                   hipStream_t s);
+
+// Pinned host staging for a small argument table that a call copies to the device
+// on its stream.  copy() first waits for the previous copy out of the staging buffer
+// to have executed (not for the rest of that call's work), so the host never
+// overwrites bytes a queued copy has yet to read.
+struct ArgStage {
+  void *host = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  hipError_t copy(void *d_dst, const void *src, size_t n, hipStream_t s);
+  void release();
+};
 
 // Size of one per-chunk detection candidate record in the workspace.
 constexpr size_t kCandBytes = 16;

@@ -903,15 +903,18 @@ struct MfmaBatch {
   std::vector<int32_t> base;                // first block of each beam, then the total
   WidthList wl{};
   size_t work_bytes = 0;
+  size_t args_off = 0;                      // workspace offset of the eager argument table
   int32_t *d_base = nullptr;
-  MfmaSearchArgs *d_args = nullptr;
+  MfmaSearchArgs *d_args_graph = nullptr;   // argument table of the captured graph
   std::vector<MfmaSearchArgs> args;         // argument table of the last enqueue
+  ArgStage stage;                           // pinned staging of the eager table
 };
 
 void mfma_batch_free(MfmaBatch *B) {
   if (!B) return;
+  B->stage.release();
   (void)hipFree(B->d_base);
-  (void)hipFree(B->d_args);
+  (void)hipFree(B->d_args_graph);
   delete B;
 }
 
@@ -973,9 +976,11 @@ dedisp_status mfma_batch_create(const std::vector<dedisp_plan> &plans,
     }
   }
   B->base.push_back((int32_t)blocks);
-  B->work_bytes = off;
+  B->args_off = off;
+  B->work_bytes = off + sizeof(MfmaSearchArgs) * B->nbeam;
   hipError_t e = upload(&B->d_base, B->base);
-  if (e == hipSuccess) e = hipMalloc((void **)&B->d_args, sizeof(MfmaSearchArgs) * B->nbeam);
+  if (e == hipSuccess)
+    e = hipMalloc((void **)&B->d_args_graph, sizeof(MfmaSearchArgs) * B->nbeam);
   if (e != hipSuccess) {
     mfma_batch_free(B);
     return hip_fail(e, "batch setup");
@@ -985,35 +990,40 @@ dedisp_status mfma_batch_create(const std::vector<dedisp_plan> &plans,
 }
 
 template <int NWD, int NWT, int WG>
-static hipError_t launch_batch_mfma_cfg(const MfmaBatch *B, hipStream_t s) {
+static hipError_t launch_batch_mfma_cfg(const MfmaBatch *B, const MfmaSearchArgs *table,
+                                        hipStream_t s) {
   static bool done[64] = {};
   static std::mutex mu;
   hipError_t e = allow_lds_mfma((const void *)k_search_mfma_batch<NWD, NWT, WG>, done, &mu,
                                 2 * (kMfmaBufBytes / WG));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_search_mfma_batch<NWD, NWT, WG>), dim3(B->base.back()),
-                     dim3(64 * NWD * NWT), 2 * (kMfmaBufBytes / WG), s, B->d_args, B->d_base,
+                     dim3(64 * NWD * NWT), 2 * (kMfmaBufBytes / WG), s, table, B->d_base,
                      B->nbeam);
   return hipGetLastError();
 }
 
-static hipError_t launch_batch_mfma(const MfmaBatch *B, hipStream_t s) {
+static hipError_t launch_batch_mfma(const MfmaBatch *B, const MfmaSearchArgs *table,
+                                    hipStream_t s) {
   switch (B->k) {
 #define DD_MFMA_BATCH_CASE(i, x, y, g) \
-  case i: return launch_batch_mfma_cfg<x, y, g>(B, s);
+  case i: return launch_batch_mfma_cfg<x, y, g>(B, table, s);
     DD_MFMA_CONFIGS(DD_MFMA_BATCH_CASE)
 #undef DD_MFMA_BATCH_CASE
     default: return hipErrorInvalidValue;
   }
 }
 
-// Noise tables of every beam, the argument table (copied when copy_args), one launch
-// over every beam's tiles, the per-beam reductions.  Outputs of beam b start at
-// out_off[b].
+// Noise tables of every beam, the argument table, one launch over every beam's tiles,
+// the per-beam reductions.  Outputs of beam b start at out_off[b].  Eager calls
+// (for_graph false) copy the argument table into the caller's workspace through the
+// pinned staging buffer; a captured sequence (for_graph true) reads the batch's own
+// graph table, which mfma_batch_upload fills once the capture has ended.  The two
+// tables are distinct, so eager calls never change what a graph replays.
 dedisp_status mfma_batch_enqueue(MfmaBatch *B, const void *const *in, const int64_t *stride,
                                  const double *mu, const double *sigma, double *snr, int32_t *t,
                                  int32_t *w, const std::vector<int64_t> &out_off, void *work,
-                                 hipStream_t s, bool copy_args, KernelTimer *kt) {
+                                 hipStream_t s, bool for_graph, KernelTimer *kt) {
   B->args.assign(B->nbeam, MfmaSearchArgs{});
   for (int b = 0; b < B->nbeam; ++b) {
     dedisp_plan p = B->plans[b];
@@ -1030,11 +1040,13 @@ dedisp_status mfma_batch_enqueue(MfmaBatch *B, const void *const *in, const int6
     sa.part = (CandRec *)((char *)work + B->off[b] + B->lay[b].off_part);
     DD_HIP(launch_norm(p, B->wl, mu, sigma, M, (double *)sa.S, s));
   }
-  if (copy_args)
-    DD_HIP(hipMemcpyAsync(B->d_args, B->args.data(), sizeof(MfmaSearchArgs) * B->nbeam,
-                          hipMemcpyHostToDevice, s));
+  MfmaSearchArgs *table = B->d_args_graph;
+  if (!for_graph) {
+    table = (MfmaSearchArgs *)((char *)work + B->args_off);
+    DD_HIP(B->stage.copy(table, B->args.data(), sizeof(MfmaSearchArgs) * B->nbeam, s));
+  }
   if (kt) DD_HIP(kt->begin());
-  DD_HIP(launch_batch_mfma(B, s));
+  DD_HIP(launch_batch_mfma(B, table, s));
   if (kt) DD_HIP(kt->end());
   for (int b = 0; b < B->nbeam; ++b) {
     const int64_t o = out_off[b];
@@ -1045,7 +1057,7 @@ dedisp_status mfma_batch_enqueue(MfmaBatch *B, const void *const *in, const int6
 }
 
 dedisp_status mfma_batch_upload(MfmaBatch *B) {
-  DD_HIP(hipMemcpy(B->d_args, B->args.data(), sizeof(MfmaSearchArgs) * B->nbeam,
+  DD_HIP(hipMemcpy(B->d_args_graph, B->args.data(), sizeof(MfmaSearchArgs) * B->nbeam,
                    hipMemcpyHostToDevice));
   return DEDISP_OK;
 }

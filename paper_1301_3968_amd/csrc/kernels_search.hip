@@ -873,7 +873,9 @@ struct dedisp_batch_s {
   std::vector<size_t> u_rel;          // rows offset of each beam inside the shared region
   size_t u_off = 0;
   int32_t *d_tile_begin = nullptr;
-  dd::SearchArgs *d_args = nullptr;
+  dd::SearchArgs *d_args_graph = nullptr;   // argument table of the captured graph
+  size_t args_off = 0;                      // workspace offset of the eager argument table
+  dd::ArgStage stage;                       // pinned staging of the eager table
   // captured graph and the pointers it was captured with
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -885,21 +887,23 @@ struct dedisp_batch_s {
 namespace dd {
 
 template <int DPW, int R2, int NW>
-static hipError_t launch_batch_cfg(const dedisp_batch_s *B, int k, hipStream_t s) {
+static hipError_t launch_batch_cfg(const dedisp_batch_s *B, int k, const SearchArgs *table,
+                                   hipStream_t s) {
   static bool done[64] = {};
   static std::mutex mu;
   hipError_t e = allow_lds((const void *)k_search_batch<DPW, R2, NW>, done, &mu);
   if (e != hipSuccess) return e;
   const int b0 = B->chunk_beam[k], b1 = B->chunk_beam[k + 1];
   hipLaunchKernelGGL((k_search_batch<DPW, R2, NW>), dim3(B->chunk_grid[k]), dim3(64 * NW),
-                     B->chunk_lds[k], s, B->d_args + b0, B->d_tile_begin + B->chunk_tb[k], b1 - b0);
+                     B->chunk_lds[k], s, table + b0, B->d_tile_begin + B->chunk_tb[k], b1 - b0);
   return hipGetLastError();
 }
 
-static hipError_t launch_batch_kernel(const dedisp_batch_s *B, int k, hipStream_t s) {
+static hipError_t launch_batch_kernel(const dedisp_batch_s *B, int k, const SearchArgs *table,
+                                      hipStream_t s) {
   switch (B->ci) {
 #define DD_CFG_CASE(i, d, r, w) \
-  case i: return launch_batch_cfg<d, r, w>(B, k, s);
+  case i: return launch_batch_cfg<d, r, w>(B, k, table, s);
     DD_TILE_CONFIGS(DD_CFG_CASE)
 #undef DD_CFG_CASE
     default: return hipErrorInvalidValue;
@@ -908,16 +912,19 @@ static hipError_t launch_batch_kernel(const dedisp_batch_s *B, int k, hipStream_
 
 // The whole per-call launch sequence: per-beam tables and window rows, the
 // multi-beam search and the per-beam reductions.
-// With copy_args false the argument table is not uploaded (the graph path uploads
-// it outside the capture: it depends only on the pointers the graph is keyed on).
+// Eager calls (for_graph false) copy the argument table into the caller's workspace
+// through the pinned staging buffer; a captured sequence (for_graph true) reads the
+// batch's own graph table, uploaded outside the capture (it depends only on the
+// pointers the graph is keyed on).  The two tables are distinct, so an eager call
+// never changes what a graph replays.
 static dedisp_status batch_enqueue(dedisp_batch_s *B, const void *const *in, const int64_t *stride,
                                    const double *mu, const double *sigma, double *snr, int32_t *t,
-                                   int32_t *w, void *work, hipStream_t s, bool copy_args,
+                                   int32_t *w, void *work, hipStream_t s, bool for_graph,
                                    std::vector<SearchArgs> &args) {
   if (B->mb) {
     KernelTimer kt(B->plans[0], s);
     return mfma_batch_enqueue(B->mb, in, stride, mu, sigma, snr, t, w, B->out_off, work, s,
-                              copy_args, &kt);
+                              for_graph, &kt);
   }
   args.assign(B->nbeam, SearchArgs{});
   uint16_t *urows = (uint16_t *)((char *)work + B->u_off);
@@ -929,9 +936,11 @@ static dedisp_status batch_enqueue(dedisp_batch_s *B, const void *const *in, con
                                     ? fail(st, "a beam's plan cannot use the tiled search")
                                     : st;
   }
-  if (copy_args)
-    DD_HIP(hipMemcpyAsync(B->d_args, args.data(), sizeof(SearchArgs) * B->nbeam,
-                          hipMemcpyHostToDevice, s));
+  SearchArgs *table = B->d_args_graph;
+  if (!for_graph) {
+    table = (SearchArgs *)((char *)work + B->args_off);
+    DD_HIP(B->stage.copy(table, args.data(), sizeof(SearchArgs) * B->nbeam, s));
+  }
   // chunk by chunk: the beams' noise tables and window rows (the rows region is
   // shared by all chunks: stream order keeps a chunk's search ahead of the next
   // chunk's rows), then one search launch over the chunk's tiles
@@ -949,7 +958,7 @@ static dedisp_status batch_enqueue(dedisp_batch_s *B, const void *const *in, con
       if (st != DEDISP_OK) return st;
     }
     if (k == 0) DD_HIP(kt.begin());
-    DD_HIP(launch_batch_kernel(B, k, s));
+    DD_HIP(launch_batch_kernel(B, k, table, s));
   }
   DD_HIP(kt.end());
   for (int b = 0; b < B->nbeam; ++b) {
@@ -1089,10 +1098,11 @@ dedisp_status dedisp_batch_create(dedisp_batch *out, int32_t nbeam, const dedisp
     B->u_off = off;
     off += rows_max;
   }
-  B->work_bytes = off;
+  B->args_off = (off + 255) & ~(size_t)255;
+  B->work_bytes = B->args_off + sizeof(SearchArgs) * nbeam;
   if (st == DEDISP_OK) {
     hipError_t e = upload(&B->d_tile_begin, B->tile_begin);
-    if (e == hipSuccess) e = hipMalloc((void **)&B->d_args, sizeof(SearchArgs) * nbeam);
+    if (e == hipSuccess) e = hipMalloc((void **)&B->d_args_graph, sizeof(SearchArgs) * nbeam);
     if (e != hipSuccess) st = hip_fail(e, "batch setup");
   }
   if (st != DEDISP_OK) {
@@ -1110,8 +1120,9 @@ dedisp_status dedisp_batch_destroy(dedisp_batch B) {
   if (B->cap) (void)hipStreamDestroy(B->cap);
   if (B->ev_in) (void)hipEventDestroy(B->ev_in);
   if (B->ev_out) (void)hipEventDestroy(B->ev_out);
+  B->stage.release();
   (void)hipFree(B->d_tile_begin);
-  (void)hipFree(B->d_args);
+  (void)hipFree(B->d_args_graph);
   dd::mfma_batch_free(B->mb);
   delete B;
   return DEDISP_OK;
@@ -1142,13 +1153,9 @@ dedisp_status dedisp_batch_run(dedisp_batch B, const void *const *d_in, const in
     if (!d_in[b] || in_stride[b] < B->nsamp[b]) return fail(DEDISP_ERR_INVALID_ARG, "bad beam input");
   hipStream_t s = (hipStream_t)stream;
   std::vector<SearchArgs> args;
-  if (!use_graph) {
-    dedisp_status st = batch_enqueue(B, d_in, in_stride, d_chan_mean, d_chan_sigma, d_snr, d_t, d_w,
-                                     d_work, s, true, args);
-    // the copy above reads `args` asynchronously: wait for it before it goes away
-    if (st == DEDISP_OK) DD_HIP(hipStreamSynchronize(s));
-    return st;
-  }
+  if (!use_graph)
+    return batch_enqueue(B, d_in, in_stride, d_chan_mean, d_chan_sigma, d_snr, d_t, d_w, d_work, s,
+                         false, args);
   // Graph path: capture once per set of pointers on a private stream, then replay.
   std::vector<const void *> key(d_in, d_in + B->nbeam);
   for (int b = 0; b < B->nbeam; ++b) key.push_back((const void *)(intptr_t)in_stride[b]);
@@ -1176,7 +1183,7 @@ dedisp_status dedisp_batch_run(dedisp_batch B, const void *const *d_in, const in
     e0.swap(B->plans[0]->ev_start);
     e1.swap(B->plans[0]->ev_stop);
     dedisp_status st = batch_enqueue(B, d_in, in_stride, d_chan_mean, d_chan_sigma, d_snr, d_t, d_w,
-                                     d_work, B->cap, false, args);
+                                     d_work, B->cap, true, args);
     hipGraph_t g = nullptr;
     hipError_t ee = hipStreamEndCapture(B->cap, &g);
     e0.swap(B->plans[0]->ev_start);
@@ -1192,7 +1199,8 @@ dedisp_status dedisp_batch_run(dedisp_batch B, const void *const *d_in, const in
       const dedisp_status su = mfma_batch_upload(B->mb);
       if (su != DEDISP_OK) return su;
     } else {
-      DD_HIP(hipMemcpy(B->d_args, args.data(), sizeof(SearchArgs) * B->nbeam, hipMemcpyHostToDevice));
+      DD_HIP(hipMemcpy(B->d_args_graph, args.data(), sizeof(SearchArgs) * B->nbeam,
+                       hipMemcpyHostToDevice));
     }
     B->key = key;
   }
@@ -1291,14 +1299,27 @@ extern "C" dedisp_status dedisp_autotune(dedisp_plan p, const void *d_in, int64_
     return DEDISP_OK;
   }
   hipStream_t s = (hipStream_t)stream;
-  double *snr = nullptr;
-  int32_t *tt = nullptr, *ww = nullptr;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  DD_HIP(hipMalloc((void **)&snr, sizeof(double) * p->ndm));
-  DD_HIP(hipMalloc((void **)&tt, sizeof(int32_t) * p->ndm));
-  DD_HIP(hipMalloc((void **)&ww, sizeof(int32_t) * p->ndm));
-  DD_HIP(hipEventCreate(&e0));
-  DD_HIP(hipEventCreate(&e1));
+  // scratch outputs and timing events, released on every return path
+  struct Scratch {
+    double *snr = nullptr;
+    int32_t *tt = nullptr, *ww = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Scratch() {
+      (void)hipFree(snr);
+      (void)hipFree(tt);
+      (void)hipFree(ww);
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } sc;
+  DD_HIP(hipMalloc((void **)&sc.snr, sizeof(double) * p->ndm));
+  DD_HIP(hipMalloc((void **)&sc.tt, sizeof(int32_t) * p->ndm));
+  DD_HIP(hipMalloc((void **)&sc.ww, sizeof(int32_t) * p->ndm));
+  DD_HIP(hipEventCreate(&sc.e0));
+  DD_HIP(hipEventCreate(&sc.e1));
+  double *snr = sc.snr;
+  int32_t *tt = sc.tt, *ww = sc.ww;
+  hipEvent_t e0 = sc.e0, e1 = sc.e1;
   int best = -1;
   double best_ms = 1e30;
   // the timed calls must not advance the instrumentation slots
@@ -1329,11 +1350,8 @@ extern "C" dedisp_status dedisp_autotune(dedisp_plan p, const void *d_in, int64_
   }
   es.swap(p->ev_start);
   et.swap(p->ev_stop);
-  (void)hipFree(snr);
-  (void)hipFree(tt);
-  (void)hipFree(ww);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  // the scratch outputs are freed on return; the timed searches must have finished
+  if (st == DEDISP_OK) DD_HIP(hipStreamSynchronize(s));
   if (st != DEDISP_OK) return st;
   if (best < 0) return fail(DEDISP_ERR_UNSUPPORTED, "no tile shape fits this plan");
   p->tile_choice = best;

@@ -138,3 +138,57 @@ def test_autotune_picks_a_working_shape(dd, orc, beams, tmp_path, monkeypatch):
     assert p.autotune(xd, list(range(1, 33)), mu, sg) == ci
     assert (tmp_path / "tune.txt").read_text().count("\n") == 1
     p.set_tile(-1)
+
+
+@pytest.mark.parametrize("kernel", ["matrix", "packed"])
+def test_eager_call_between_graph_replays(dd, orc, beams, kernel):
+    # A graph captured on inputs A, an eager call on other inputs B (own workspace and
+    # outputs), then a replay of the graph after new data were written into A's
+    # buffers: the replay must search A's new data, not B's, and the eager call B's.
+    import torch
+    C, bl = beams
+    widths = list(range(1, 33))
+    if kernel == "packed":
+        bl[0][0].set_tile(4)
+    try:
+        B = dd.Batch([b[0] for b in bl], [b[1].shape[1] for b in bl], widths)
+    finally:
+        bl[0][0].set_tile(-1)
+    rng = np.random.default_rng(777)
+    data_b = [workloads.u8_noise(rng, C, b[1].shape[1]) for b in bl]
+    data_a2 = [workloads.u8_noise(rng, C, b[1].shape[1]) for b in bl]
+    xs_a = [_dev(b[1]) for b in bl]
+    xs_b = [_dev(x) for x in data_b]
+    mu = torch.full((C,), 128.0, dtype=torch.float64, device="cuda")
+    sg = torch.full((C,), 16.0, dtype=torch.float64, device="cuda")
+    work = torch.empty(B.work_bytes, dtype=torch.uint8, device="cuda")
+    outs = (torch.empty(B.total_trials, dtype=torch.float64, device="cuda"),
+            torch.empty(B.total_trials, dtype=torch.int32, device="cuda"),
+            torch.empty(B.total_trials, dtype=torch.int32, device="cuda"))
+    B.run(xs_a, mu, sg, work=work, outputs=outs, graph=True)
+    torch.cuda.synchronize()
+    _check(orc, beams, widths, *[o.cpu().numpy() for o in outs])
+    eager_b = [v.cpu().numpy() for v in B.run(xs_b, mu, sg)]
+    for xa, new in zip(xs_a, data_a2):
+        xa.copy_(_dev(new))
+    for o in outs:
+        o.fill_(-7)
+    B.run(xs_a, mu, sg, work=work, outputs=outs, graph=True)
+    torch.cuda.synchronize()
+    replay = [o.cpu().numpy() for o in outs]
+
+    def with_data(data):
+        out = []
+        for (p, x, n, yo), xn in zip(bl, data):
+            out.append((p, xn, n, orc.dedisperse_u8(xn, *_oracle_tables_of(orc, p, n)).astype(np.float64)))
+        return C, out
+
+    _check(orc, with_data(data_b), widths, *eager_b)
+    _check(orc, with_data(data_a2), widths, *replay)
+
+
+def _oracle_tables_of(orc, p, n):
+    """The oracle's start table for plan p's trial DMs (the tap counts n are the
+    oracle's already) and n."""
+    s = orc.delay_start(p._freq, 0.001, 1e-3, p._dms).astype(np.int32)
+    return s, n
