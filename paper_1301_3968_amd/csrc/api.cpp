@@ -272,10 +272,11 @@ dedisp_status dedisp_dedisperse_backward(dedisp_plan p, const float *d_grad_y, i
   dd::WeightOverride wo(d_weights);
   hipStream_t s = (hipStream_t)stream;
   if (p->wmode == DEDISP_W_TAP) {
-    // zbar = transpose of the one-sample sum; then the FIR transposes.
+    // zbar = transpose of the one-sample sum, in fp64 (the weight gradient formed from
+    // it cancels heavily); then the FIR transposes.
     const int64_t nz = nsamp - p->ktaps + 1;
-    float *z = nullptr;
-    DD_HIP(hipMallocAsync((void **)&z, sizeof(float) * (size_t)nz * p->nchan * nbatch, s));
+    double *z = nullptr;
+    DD_HIP(hipMallocAsync((void **)&z, sizeof(double) * (size_t)nz * p->nchan * nbatch, s));
     hipError_t e = hipSuccess;
     st = p->tile_choice == -2 ? DEDISP_ERR_UNSUPPORTED
                               : dd::run_adjoint_z_tiled(p, d_grad_y, nout, gy_stride, gy_bstride,

@@ -135,12 +135,12 @@ hipError_t launch_boxcar(const dedisp_plan_s *p, const void *y, int32_t y_dtype,
 hipError_t launch_reduce(int32_t ndm, int32_t nchunk, const void *partials, double *snr,
                          int32_t *t, int32_t *w, hipStream_t s);
 hipError_t launch_adjoint_z(const dedisp_plan_s *p, const float *g, int64_t nout, int64_t gstride,
-                            int64_t gbstride, int32_t nbatch, int64_t nz, float *z,
+                            int64_t gbstride, int32_t nbatch, int64_t nz, double *z,
                             hipStream_t s);
-hipError_t launch_grad_w_tap(const dedisp_plan_s *p, const float *z, int64_t nz, const void *x,
+hipError_t launch_grad_w_tap(const dedisp_plan_s *p, const double *z, int64_t nz, const void *x,
                              int32_t in_dtype, int64_t in_stride, int64_t in_bstride,
                              int32_t nbatch, double *gw, hipStream_t s);
-hipError_t launch_grad_x_tap(const dedisp_plan_s *p, const float *z, int64_t nz, int64_t nsamp,
+hipError_t launch_grad_x_tap(const dedisp_plan_s *p, const double *z, int64_t nz, int64_t nsamp,
                              int32_t nbatch, float *gx, int64_t in_stride, int64_t in_bstride,
                              hipStream_t s);
 hipError_t launch_adjoint_direct(const dedisp_plan_s *p, const float *g, int64_t nout,
@@ -203,9 +203,10 @@ dedisp_status mfma_batch_enqueue(MfmaBatch *B, const void *const *in, const int6
 dedisp_status mfma_batch_upload(MfmaBatch *B);
 void mfma_batch_free(MfmaBatch *B);
 // zbar[b][c][tau] = sum_d g[b][d][tau - start[d][c]] for tau in [0, nz) on the same
-// tiled kernel; DEDISP_ERR_UNSUPPORTED (launching nothing) when it does not fit.
+// tiled kernel, every term added in fp64, fp64 output; DEDISP_ERR_UNSUPPORTED
+// (launching nothing) when it does not fit.
 dedisp_status run_adjoint_z_tiled(dedisp_plan p, const float *g, int64_t nout, int64_t gstride,
-                                  int64_t gbstride, int32_t nbatch, int64_t nz, float *z,
+                                  int64_t gbstride, int32_t nbatch, int64_t nz, double *z,
                                   hipStream_t s);
 
 // Pinned host staging for a small argument table that a call copies to the device

@@ -383,11 +383,12 @@ k_reduce(int32_t ndm, int32_t nchunk, const Cand *__restrict__ part, double *__r
 // every output is written by exactly one thread in a fixed summation order.
 // ----------------------------------------------------------------------------------
 
-// zbar[b][c][i] = sum_d g[b][d][i - s[d,c]] over trials whose output index lies in [0, nout).
+// zbar[b][c][i] = sum_d g[b][d][i - s[d,c]] over trials whose output index lies in
+// [0, nout), added and stored in fp64.
 __global__ void __launch_bounds__(kThreads)
 k_adjoint_z(const float *__restrict__ g, int64_t nout, int64_t gstride, int64_t gbstride,
             const int32_t *__restrict__ start, int32_t nchan, int32_t ndm, int64_t nz,
-            float *__restrict__ z) {
+            double *__restrict__ z) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int c = blockIdx.y, b = blockIdx.z;
   if (i >= nz) return;
@@ -397,10 +398,10 @@ k_adjoint_z(const float *__restrict__ g, int64_t nout, int64_t gstride, int64_t 
     const int64_t t = i - start[(int64_t)d * nchan + c];
     if (t >= 0 && t < nout) acc += (double)gb[(int64_t)d * gstride + t];
   }
-  z[((int64_t)b * nchan + c) * nz + i] = (float)acc;
+  z[((int64_t)b * nchan + c) * nz + i] = acc;
 }
 
-// gw[c][k] = sum_b sum_i zbar[b][c][i] x[b][c][i+k] with fp64 products and sums, in
+// gw[c][k] = sum_b sum_i zbar[b][c][i] x[b][c][i+k] (zbar fp64) with fp64 products and sums, in
 // two passes.  Pass 1: one workgroup per (chunk of kGwChunk samples, slice of at most
 // KB taps, channel, batch element).  Piece by piece (kGwPiece samples) the workgroup
 // copies zbar and the x it meets into LDS with coalesced loads; a thread then takes
@@ -413,12 +414,12 @@ constexpr int kGwChunk = kGwPiece * kGwIter, kGwMaxK = 64;
 
 template <typename XT, int KB>
 __global__ void __launch_bounds__(kThreads)
-k_grad_w_tap_part(const float *__restrict__ z, int64_t nz, const XT *__restrict__ x,
+k_grad_w_tap_part(const double *__restrict__ z, int64_t nz, const XT *__restrict__ x,
                   int64_t in_stride, int64_t in_bstride, int32_t nchan, int32_t K,
                   int32_t nslice, double *__restrict__ part) {
   constexpr int XW = (kGwRun + KB - 1 + 3) / 4 * 4;   // x window of a run, whole float4s
   static_assert(KB <= 16 && kGwRun % 4 == 0, "window within the 16-sample pad");
-  __shared__ __attribute__((aligned(16))) float zs[kGwPiece];
+  __shared__ __attribute__((aligned(16))) double zs[kGwPiece];
   __shared__ __attribute__((aligned(16))) float xs[kGwPiece + 16];
   __shared__ double red[KB][kThreads / 64];
   const int sidx = blockIdx.x / nslice, k0 = (blockIdx.x - sidx * nslice) * KB;
@@ -426,19 +427,20 @@ k_grad_w_tap_part(const float *__restrict__ z, int64_t nz, const XT *__restrict_
   const int kl = min(KB, K - k0);   // taps k0 .. k0 + kl - 1
   const int nsplit = gridDim.x / nslice;
   const XT *xr = x + (int64_t)b * in_bstride + (int64_t)c * in_stride + k0;
-  const float *zr = z + ((int64_t)b * nchan + c) * nz;
+  const double *zr = z + ((int64_t)b * nchan + c) * nz;
   const int64_t nx = nz + K - 1 - k0;   // samples of the input row from k0 on
   double acc[KB];
 #pragma unroll
   for (int k = 0; k < KB; ++k) acc[k] = 0.0;
   // the next piece is loaded into registers while the current one is summed
-  float zn[kGwRun], xn[kGwRun], xt = 0.0f;
+  double zn[kGwRun];
+  float xn[kGwRun], xt = 0.0f;
   auto load_piece = [&](int64_t p0) {
     // zbar[p0 + i] (zero past nz) and x[p0 + k0 + i] (zero past the row)
 #pragma unroll
     for (int j = 0; j < kGwRun; ++j) {
       const int i = tid + kThreads * j;
-      zn[j] = p0 + i < nz ? zr[p0 + i] : 0.0f;
+      zn[j] = p0 + i < nz ? zr[p0 + i] : 0.0;
       xn[j] = p0 + i < nx ? (float)xr[p0 + i] : 0.0f;
     }
     if (tid < 16) xt = p0 + kGwPiece + tid < nx ? (float)xr[p0 + kGwPiece + tid] : 0.0f;
@@ -456,16 +458,17 @@ k_grad_w_tap_part(const float *__restrict__ z, int64_t nz, const XT *__restrict_
     if (tid < 16) xs[kGwPiece + tid] = xt;
     __syncthreads();
     if (it + 1 < kGwIter && p0 + kGwPiece < nz) load_piece(p0 + kGwPiece);
-    const float4 *zp = (const float4 *)(zs + kGwRun * tid);
+    const double2 *zp = (const double2 *)(zs + kGwRun * tid);
     const float4 *xp = (const float4 *)(xs + kGwRun * tid);
-    float zv[kGwRun], xv[XW];
+    double zv[kGwRun];
+    float xv[XW];
 #pragma unroll
-    for (int q = 0; q < kGwRun / 4; ++q) *(float4 *)&zv[4 * q] = zp[q];
+    for (int q = 0; q < kGwRun / 2; ++q) *(double2 *)&zv[2 * q] = zp[q];
 #pragma unroll
     for (int q = 0; q < XW / 4; ++q) *(float4 *)&xv[4 * q] = xp[q];
 #pragma unroll
     for (int q = 0; q < kGwRun; ++q) {
-      const double zq = (double)zv[q];
+      const double zq = zv[q];
 #pragma unroll
       for (int k = 0; k < KB; ++k) acc[k] += zq * (double)xv[q + k];   // k >= kl: never stored
     }
@@ -504,19 +507,19 @@ k_grad_w_tap_sum(const double *__restrict__ part, int32_t nparts, int32_t nchan,
   if (lane == 0) gw[idx] = t;
 }
 
-// gx[b][c][i] = sum_k w[c][k] zbar[b][c][i-k].
+// gx[b][c][i] = sum_k w[c][k] zbar[b][c][i-k] (zbar fp64, fp64 sum, fp32 result).
 __global__ void __launch_bounds__(kThreads)
-k_grad_x_tap(const float *__restrict__ z, int64_t nz, const float *__restrict__ w, int32_t K,
+k_grad_x_tap(const double *__restrict__ z, int64_t nz, const float *__restrict__ w, int32_t K,
              int64_t nsamp, int32_t nchan, float *__restrict__ gx, int64_t in_stride,
              int64_t in_bstride) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int c = blockIdx.y, b = blockIdx.z;
   if (i >= nsamp) return;
-  const float *zr = z + ((int64_t)b * nchan + c) * nz;
+  const double *zr = z + ((int64_t)b * nchan + c) * nz;
   double acc = 0.0;
   for (int k = 0; k < K; ++k) {
     const int64_t j = i - k;
-    if (j >= 0 && j < nz) acc += (double)w[(int64_t)c * K + k] * (double)zr[j];
+    if (j >= 0 && j < nz) acc += (double)w[(int64_t)c * K + k] * zr[j];
   }
   gx[(int64_t)b * in_bstride + (int64_t)c * in_stride + i] = (float)acc;
 }
@@ -738,14 +741,14 @@ hipError_t launch_reduce(int32_t ndm, int32_t nchunk, const void *partials, doub
 }
 
 hipError_t launch_adjoint_z(const dedisp_plan_s *p, const float *g, int64_t nout, int64_t gstride,
-                            int64_t gbstride, int32_t nbatch, int64_t nz, float *z,
+                            int64_t gbstride, int32_t nbatch, int64_t nz, double *z,
                             hipStream_t s) {
   hipLaunchKernelGGL(k_adjoint_z, grid3(nz, p->nchan, nbatch), dim3(kThreads), 0, s, g, nout,
                      gstride, gbstride, p->dev.start, p->nchan, p->ndm, nz, z);
   return hipGetLastError();
 }
 
-hipError_t launch_grad_w_tap(const dedisp_plan_s *p, const float *z, int64_t nz, const void *x,
+hipError_t launch_grad_w_tap(const dedisp_plan_s *p, const double *z, int64_t nz, const void *x,
                              int32_t in_dtype, int64_t in_stride, int64_t in_bstride,
                              int32_t nbatch, double *gw, hipStream_t s) {
   const int K = p->ktaps;
@@ -784,7 +787,7 @@ hipError_t launch_grad_w_tap(const dedisp_plan_s *p, const float *z, int64_t nz,
   return e != hipSuccess ? e : e2;
 }
 
-hipError_t launch_grad_x_tap(const dedisp_plan_s *p, const float *z, int64_t nz, int64_t nsamp,
+hipError_t launch_grad_x_tap(const dedisp_plan_s *p, const double *z, int64_t nz, int64_t nsamp,
                              int32_t nbatch, float *gx, int64_t in_stride, int64_t in_bstride,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_grad_x_tap, grid3(nsamp, p->nchan, nbatch), dim3(kThreads), 0, s, z, nz,

@@ -15,18 +15,23 @@
 //      (trial, channel), the R samples l, l + 64, .. of the trial's window (fp32
 //      rows need no second copy: any sample offset is dword-aligned).  Sums over a
 //      group (at most 32 channels) run in fp32; group sums are added in fp64, so the
-//      result is within a few fp32 roundings of the exact sum.
+//      result is within a few fp32 roundings of the exact sum.  The transposed use
+//      below instead adds every term in fp64 and writes fp64 (A64).
 // Long blocks are processed in time segments so that the rows stay within 4 GiB.
 //
 // The same two kernels compute the transpose of the one-sample-per-channel sum (the
 // adjoint needed for per-tap weights): with trials as row channels, channels as
-// outputs and the trial gradients as rows, it is again a sum of shifted rows.
+// outputs and the trial gradients as rows, it is again a sum of shifted rows.  Its
+// terms have mixed signs and the weight gradient formed from it cancels heavily, so
+// there each term is added in fp64 (exact conversion of the fp32 row sample) and the
+// fp64 sum is written out: the transposed sum is then exact to fp64 rounding.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <climits>
 #include <cstring>
 #include <numeric>
+#include <type_traits>
 #include <vector>
 
 #include "internal.h"
@@ -175,7 +180,7 @@ struct F32Args {
   const F32Group *groups;
   const int32_t *group_begin, *jobs, *perm;
   int64_t nout;            // outputs of this segment
-  float *out;              // y of batch element 0 at this segment's first output
+  void *out;               // y of batch element 0 at this segment's first output
   int64_t out_stride, out_bstride;
 };
 
@@ -225,9 +230,12 @@ __device__ __forceinline__ int group_offsets(const F32Args &a, const F32Group &g
   return o;
 }
 
-template <int R, int DPW, int NW>
+// A64 false: fp32 group sums added into fp64, fp32 output.  A64 true: every term
+// added in fp64, fp64 output.
+template <int R, int DPW, int NW, bool A64>
 __global__ void __launch_bounds__(64 * NW)
 k_dedisp_f32(F32Args a) {
+  typedef typename std::conditional<A64, double, float>::type PT;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   constexpr int TY = 64 * R, DT = NW * DPW;
   constexpr int CH = 24 / R;   // channels per chunk: 12 two-address reads in flight
@@ -273,9 +281,9 @@ k_dedisp_f32(F32Args a) {
     const unsigned char *lbase = lds + par * a.bufbytes + lane * 4;
 #pragma unroll
     for (int j = 0; j < DPW; ++j) {
-      float part[R];
+      PT part[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) part[r] = 0.0f;
+      for (int r = 0; r < R; ++r) part[r] = (PT)0;
       const int jb = j * cc;
       int c = 0;
       for (; c + CH <= cc; c += CH) {
@@ -285,12 +293,12 @@ k_dedisp_f32(F32Args a) {
 #pragma unroll
         for (int qq = 0; qq < CH; ++qq)
 #pragma unroll
-          for (int r = 0; r < R; ++r) part[r] += *(const float *)(pc[qq] + 256 * r);
+          for (int r = 0; r < R; ++r) part[r] += (PT)*(const float *)(pc[qq] + 256 * r);
       }
       for (; c < cc; ++c) {
         const unsigned char *pp = lbase + __builtin_amdgcn_readlane(myoff, jb + c);
 #pragma unroll
-        for (int r = 0; r < R; ++r) part[r] += *(const float *)(pp + 256 * r);
+        for (int r = 0; r < R; ++r) part[r] += (PT)*(const float *)(pp + 256 * r);
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) acc[j][r] += (double)part[r];
@@ -300,7 +308,8 @@ k_dedisp_f32(F32Args a) {
     __syncthreads();
     myoff = nextoff;
   }
-  float *ob = a.out + (int64_t)bb * a.out_bstride;
+  typedef typename std::conditional<A64, double, float>::type OT;
+  OT *ob = (OT *)a.out + (int64_t)bb * a.out_bstride;
 #pragma unroll
   for (int j = 0; j < DPW; ++j) {
     const int d = a.perm[td * DT + wave * DPW + j];
@@ -308,7 +317,7 @@ k_dedisp_f32(F32Args a) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int64_t t = t0 + lane + 64 * r;
-      if (t < a.nout) ob[(int64_t)d * a.out_stride + t] = (float)acc[j][r];
+      if (t < a.nout) ob[(int64_t)d * a.out_stride + t] = (OT)acc[j][r];
     }
   }
 }
@@ -485,21 +494,24 @@ static hipError_t allow_lds(const void *fn, bool *done, std::mutex *mu) {
   return e;
 }
 
-template <int R, int DPW, int NW>
+template <int R, int DPW, int NW, bool A64>
 static hipError_t launch_f32_cfg(const F32Args &a, int nbatch, int lds, hipStream_t s) {
   static bool done[64] = {};
   static std::mutex mu;
-  hipError_t e = allow_lds((const void *)k_dedisp_f32<R, DPW, NW>, done, &mu);
+  hipError_t e = allow_lds((const void *)k_dedisp_f32<R, DPW, NW, A64>, done, &mu);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_dedisp_f32<R, DPW, NW>), dim3(a.ntd * a.ntt, nbatch), dim3(64 * NW), lds,
-                     s, a);
+  hipLaunchKernelGGL((k_dedisp_f32<R, DPW, NW, A64>), dim3(a.ntd * a.ntt, nbatch), dim3(64 * NW),
+                     lds, s, a);
   return hipGetLastError();
 }
 
-static hipError_t launch_f32(int ci, const F32Args &a, int nbatch, int lds, hipStream_t s) {
+static hipError_t launch_f32(int ci, bool a64, const F32Args &a, int nbatch, int lds,
+                             hipStream_t s) {
   switch (ci) {
-#define DD_F32_CASE(i, r, d, w) \
-  case i: return launch_f32_cfg<r, d, w>(a, nbatch, lds, s);
+#define DD_F32_CASE(i, r, d, w)                                               \
+  case i:                                                                     \
+    return a64 ? launch_f32_cfg<r, d, w, true>(a, nbatch, lds, s)             \
+               : launch_f32_cfg<r, d, w, false>(a, nbatch, lds, s);
     DD_F32_CONFIGS(DD_F32_CASE)
 #undef DD_F32_CASE
     default: return hipErrorInvalidValue;
@@ -508,11 +520,12 @@ static hipError_t launch_f32(int ci, const F32Args &a, int nbatch, int lds, hipS
 
 // Rows from the input (`lead` zeros in front of it and zeros past its nsamp
 // samples), then the tiled sum into `nout` outputs per output row, segment by segment.
+// out is fp32, or fp64 with every term added in fp64 when a64.
 static dedisp_status run_gather_f32(const F32Tables &T, const F32CfgTables &cfg, int ci,
                                     const void *in, int32_t in_dtype, int64_t nsamp,
                                     int64_t in_stride, int64_t in_bstride, int32_t nbatch,
                                     int32_t nrow_ch, int32_t wmode, int32_t K, const float *w,
-                                    int32_t max_span, float *out, int64_t out_stride,
+                                    int32_t max_span, void *out, bool a64, int64_t out_stride,
                                     int64_t out_bstride, int64_t nout, hipStream_t s,
                                     KernelTimer *kt) {
   const int TY = cfg.ty;
@@ -557,11 +570,11 @@ static dedisp_status run_gather_f32(const F32Tables &T, const F32CfgTables &cfg,
     a.jobs = cfg.d_jobs;
     a.perm = cfg.d_perm;
     a.nout = nseg;
-    a.out = out + o0;
+    a.out = (char *)out + (a64 ? sizeof(double) : sizeof(float)) * o0;
     a.out_stride = out_stride;
     a.out_bstride = out_bstride;
     if (kt && o0 == 0) e = kt->begin();
-    if (e == hipSuccess) e = launch_f32(ci, a, nbatch, cfg.lds_bytes, s);
+    if (e == hipSuccess) e = launch_f32(ci, a64, a, nbatch, cfg.lds_bytes, s);
     if (e == hipSuccess && kt && o0 + seg >= nout) e = kt->end();
   }
   hipError_t e2 = hipFreeAsync(Rrows, s);
@@ -592,17 +605,17 @@ dedisp_status run_dedisperse_f32_tiled(dedisp_plan p, const void *in, int32_t in
   }
   if (!cfg) return DEDISP_ERR_UNSUPPORTED;
   return run_gather_f32(*p->f32, *cfg, ci, in, in_dtype, nsamp, in_stride, in_bstride, nbatch,
-                        p->nchan, p->wmode, p->ktaps, weights_of(p), p->max_span, out, out_stride,
-                        out_bstride, nout, s, kt);
+                        p->nchan, p->wmode, p->ktaps, weights_of(p), p->max_span, out, false,
+                        out_stride, out_bstride, nout, s, kt);
 }
 
 // zbar[b][c][tau] = sum_d g[b][d][tau - start[d][c]] (terms with the index outside
 // [0, nout) are zero) for tau in [0, nz): the transpose of the one-sample-per-channel
-// sum.  It is the same tiled gather with the roles swapped: outputs are channels,
-// row channels are trials, rows are g with smax = max start zeros in front, and the
-// start of (c, d) is smax - start[d][c].
+// sum, every term added in fp64, fp64 output.  It is the same tiled gather with the
+// roles swapped: outputs are channels, row channels are trials, rows are g with
+// smax = max start zeros in front, and the start of (c, d) is smax - start[d][c].
 dedisp_status run_adjoint_z_tiled(dedisp_plan p, const float *g, int64_t nout, int64_t gstride,
-                                  int64_t gbstride, int32_t nbatch, int64_t nz, float *z,
+                                  int64_t gbstride, int32_t nbatch, int64_t nz, double *z,
                                   hipStream_t s) {
   const int C = p->nchan, D = p->ndm;
   const int ci = C >= 256 ? 0 : 1;
@@ -637,8 +650,8 @@ dedisp_status run_adjoint_z_tiled(dedisp_plan p, const float *g, int64_t nout, i
   if (!cfg) return DEDISP_ERR_UNSUPPORTED;
   const F32Tables &T = *p->f32_adj;
   return run_gather_f32(T, *cfg, ci, g, DEDISP_F32, nout, gstride, gbstride, nbatch, D,
-                        DEDISP_W_UNIT, 1, nullptr, T.lead + 1, z, nz, (int64_t)C * nz, nz, s,
-                        nullptr);
+                        DEDISP_W_UNIT, 1, nullptr, T.lead + 1, z, true, nz, (int64_t)C * nz, nz,
+                        s, nullptr);
 }
 
 }  // namespace dd
