@@ -60,3 +60,53 @@ def otables(orc):
         return s, n
 
     return tables
+
+
+def oracle_threads() -> int:
+    """Host threads for oracle loops: the GPU machine's CPU share is 16."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+@pytest.fixture(scope="session")
+def opar(orc):
+    """The oracle's trial-by-trial loops run over disjoint trial ranges in threads (each
+    range is an ordinary oracle call; ctypes releases the GIL while it runs)."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+
+    class Par:
+        @staticmethod
+        def ranges(D, parts=None):
+            parts = parts or oracle_threads()
+            edges = np.linspace(0, D, min(D, parts) + 1).round().astype(int)
+            return [(int(a), int(b)) for a, b in zip(edges[:-1], edges[1:]) if b > a]
+
+        @classmethod
+        def dedisperse_u8(cls, x, s, n, tout):
+            with ThreadPoolExecutor(oracle_threads()) as ex:
+                parts = list(ex.map(lambda r: orc.dedisperse_u8(x, s[r[0]:r[1]], n[r[0]:r[1]],
+                                                                 tout=tout),
+                                    cls.ranges(s.shape[0])))
+            return np.concatenate(parts, axis=0)
+
+        @classmethod
+        def detect(cls, y64, widths, M, S):
+            with ThreadPoolExecutor(oracle_threads()) as ex:
+                parts = list(ex.map(lambda r: orc.boxcar_detect(y64[r[0]:r[1]], widths,
+                                                                M[r[0]:r[1]], S[r[0]:r[1]]),
+                                    cls.ranges(y64.shape[0])))
+            return tuple(np.concatenate([p[i] for p in parts]) for i in range(3))
+
+        @staticmethod
+        def map(fn, items):
+            with ThreadPoolExecutor(oracle_threads()) as ex:
+                return list(ex.map(fn, items))
+
+    return Par
+
+
+@pytest.fixture(scope="session")
+def an():
+    """The package's analyses of Sections 4-5 (run through the library)."""
+    from paper_1301_3968_amd import analyses
+    return analyses
