@@ -1,31 +1,30 @@
 // Dedispersion of uint8 data with unit weights (eq. p_dedisp) on the int8 matrix cores.
 //
-// For a tile of 16 trials and a channel c, the samples a trial adds lie in a short band
-// of delays: trial d takes x[c][t + start[d,c] + k] for k < ntap[d,c], and over the 16
-// trials these delays span [lo_c, lo_c + L_c).  Cutting the band into segments of 16
-// delays, the tile's sums over channel c are
-//     y[d][t] += sum_{segments s} sum_{j<16} mask_s[d][j] * x[c][t + o_s + j],
-// a product of a 16 x 16 0/1 matrix (which delays trial d takes) with a 16 x T Hankel
-// matrix of samples.  Four segments (of one or several channels) make the K = 64 of one
-// v_mfma_i32_16x16x64_i8; the samples enter as int8 x ^ 0x80 = x - 128, and every
-// trial's result is corrected by 128 times its number of samples, so the int32 result
-// is exact.
+// For a group of 4 trials and a channel c, the samples the trials add lie in a short band
+// of delays: trial d takes x[c][t + start[d,c] + k] for k < ntap[d,c].  One
+// v_mfma_i32_16x16x64_i8 product takes 16 rows = 4 trials x 4 output phases u and 16
+// columns = 16 output quads n, so that row (d, u), column n is output t = T + 4 n + u of
+// trial d; its K = 64 are four segments of 16 consecutive samples (of one or several
+// channels), segment g starting at window sample o_g + 4 n for column n.  Then
+//     y[d][T + 4 n + u] += sum_{g, i<16} mask_g[d, u][i] * x[c_g][T + 4 n + o_g + i],
+// where mask_g[d, u][i] = 1 when sample o_g + i - u lies in trial d's run: the 0/1 matrix
+// (which samples each (trial, phase) row takes) is the same for every column and every
+// product of the K block, and the samples a column needs start on a 4-byte boundary.
+// The samples enter as int8 x ^ 0x80 = x - 128, and every trial's result is corrected
+// by 128 times its number of samples, so the int32 result is exact.
 //
-// One wave takes 16 trials x 256 outputs as 16 products (blocks b < 16); column n of
-// block b is output 16 n + b of the wave's run.  So lane n of a segment needs window
-// bytes o + 16 n + b .. o + 16 n + b + 15 for block b: for all 16 blocks, the 32 bytes
-// from o + 16 n, two aligned 16-byte LDS reads when o is a multiple of 16; block b then
-// takes bytes b .. b + 15 of them, a shift by b that is the same for every lane (three
-// byte-align operations per dword, none when b is a multiple of 4).  Segment starts are
-// put on a 4-byte grid (one or two more segments than the band needs, rarely), and each
-// channel's window is staged into LDS as 4 copies shifted by 0, 4, 8 and 12 bytes, so
-// the copy (o / 4) mod 4 holds the segment's bytes at 16-byte alignment.  Channel groups
-// are staged while the previous group is multiplied (two LDS buffers).  The host plans,
-// per group of 4 segments (a K block), a 144-byte record: the 16-bit mask of every
-// (trial, segment) (which of the segment's 16 delays the trial takes) and the LDS
-// address of each segment's aligned bytes; the records of a channel group are copied
-// into LDS with the windows, and every lane forms its 16 mask bytes and its read
-// address from them.
+// Each channel's window is staged into LDS as 4 copies shifted by 0, 4, 8 and 12 bytes,
+// interleaved by 16-byte chunks (chunk j of copy k at byte 64 j + 16 k of the channel's
+// region), so that the 16 window bytes from any multiple of 4, p, sit 16-byte aligned at
+// region + 4 p: a lane's operand of product q is one aligned 16-byte read at its
+// segment's base + 16 n + 256 q, and no byte shifts are needed.  A wave takes 4 trials x
+// NP products of 64 consecutive outputs; segments are put on a 4-byte grid (their band
+// covers start .. start + ntap + 3 for the phases).  Channel groups are staged while the
+// previous group is multiplied (two LDS buffers).  The host plans, per group of 4
+// segments (a K block), a 144-byte record: the 16-bit mask of every (trial, phase) row
+// and segment, and the LDS base address of each segment; the records of a channel group
+// are copied into LDS with the windows, and every lane forms its 16 mask bytes and its
+// read address from them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,30 +39,30 @@
 
 namespace dd {
 
-// Workgroup shapes: NWD waves along DM (16 trials each), NWT along time (256 outputs
+// Workgroup shapes: NWD waves along DM (4 trials each), NWT along time (64 NP outputs
 // each), WG workgroups per CU (each with 1 / WG of the CU's LDS).
+// Every shape keeps 16 waves on a CU (128 registers a lane).
 #define DD_MFMA_CONFIGS(X) \
-  X(0, 4, 2, 2)            \
-  X(1, 8, 1, 2)            \
-  X(2, 8, 2, 1)            \
-  X(3, 16, 1, 1)           \
-  X(4, 4, 4, 1)
+  X(0, 16, 1, 16, 1)       \
+  X(1, 8, 1, 16, 2)        \
+  X(2, 8, 2, 8, 1)         \
+  X(3, 4, 2, 8, 2)         \
+  X(4, 8, 1, 8, 2)
 struct MfmaCfg {
-  int nwd, nwt, wg;
+  int nwd, nwt, np, wg;
 };
-#define DD_MFMA_ENTRY(i, a, b, g) {a, b, g},
+#define DD_MFMA_ENTRY(i, a, b, n, g) {a, b, n, g},
 static const MfmaCfg kMfmaCfgs[] = {DD_MFMA_CONFIGS(DD_MFMA_ENTRY)};
 #undef DD_MFMA_ENTRY
 constexpr int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
-constexpr int kNT = 16;                     // products (blocks) per wave and K block
-constexpr int kTWV = 16 * kNT;              // outputs per wave
+constexpr int kTrialsPerWave = 4;           // trials of a wave (x 4 output phases = 16 rows)
 constexpr int kCopies = 4;                  // dword-shifted copies of each staged window
 constexpr int kMfmaBufBytes = 80 * 1024;    // LDS per staging buffer (two per workgroup) at
                                             // one workgroup per CU
-// K-block record: 64 x u16 masks (lane = 16 segment + trial row), then the LDS byte
-// address of each of the 4 segments' aligned bytes (lane 16 g + n reads 32 bytes at
-// address[g] + 16 n)
-constexpr int kRecBytes = 160;
+// K-block record: 64 x u16 masks (lane = 16 segment + row, row = 4 trial + phase), then
+// the LDS byte address of each of the 4 segments' first window byte (region + 4 o_g;
+// lane 16 g + n reads 16 bytes at address[g] + 16 n + 256 q for product q)
+constexpr int kRecBytes = 144;
 // Staging: one chunk (16 window bytes in all 4 copies) per thread and group, so a
 // group stages at most 64 NW chunks (registers: the chunk's raw bytes are held through
 // the current group's products).
@@ -78,8 +77,8 @@ struct MGroup {
 struct MUnit {
   int32_t c;      // channel
   int32_t src;    // first window sample of the chunk, relative to the tile's first output
-  int32_t dst;    // LDS byte offset of the chunk in copy 0
-  int32_t cs;     // bytes between the copies of the channel's window
+  int32_t dst;    // LDS byte offset of the chunk's 4 interleaved copies (64 bytes)
+  int32_t pad;
 };
 
 struct MfmaCfgTables {
@@ -167,10 +166,10 @@ __device__ __forceinline__ void load_raw(const uint8_t *row, int64_t nsamp, int6
 }
 
 // One staging task: chunk k of the 4 copies of a window (copy p: window bytes 16 k + 4 p
-// .. 16 k + 4 p + 15, as int8 x ^ 0x80), from the raw bytes at the aligned address at or
-// below window byte 16 k.  dst: the chunk's offset in copy 0; cs: bytes between copies.
-__device__ __forceinline__ void store_chunk(unsigned char *buf, int32_t dst, int32_t cs,
-                                            const uint32_t raw[8], int sh) {
+// .. 16 k + 4 p + 15, as int8 x ^ 0x80, stored at dst + 16 p), from the raw bytes at the
+// aligned address at or below window byte 16 k.
+__device__ __forceinline__ void store_chunk(unsigned char *buf, int32_t dst, const uint32_t raw[8],
+                                            int sh) {
   uint32_t e[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k)
@@ -178,7 +177,7 @@ __device__ __forceinline__ void store_chunk(unsigned char *buf, int32_t dst, int
 #pragma unroll
   for (int p = 0; p < kCopies; ++p) {
     const v4i v = {(int32_t)e[p], (int32_t)e[p + 1], (int32_t)e[p + 2], (int32_t)e[p + 3]};
-    *(v4i *)(buf + dst + p * cs) = v;
+    *(v4i *)(buf + dst + 16 * p) = v;
   }
 }
 
@@ -198,62 +197,20 @@ struct TileAcc {
   v4i v[N];
 };
 
-typedef int32_t v8i __attribute__((ext_vector_type(8)));
-typedef int32_t v2i __attribute__((ext_vector_type(2)));
-
-// Shifted samples: T[k] = the lane's bytes shifted down by S bytes, dword k + O (k < 6;
-// dwords 6, 7 unused).  Block 4 q + S takes dwords q .. q + 3 of the shifted bytes: from
-// the O = 0 tuple at offset q for even q, from the O = 1 tuple at offset q - 1 for odd q,
-// so that every operand starts at an even register of its tuple (4-register operands
-// must; an odd start would be copied into place).
-template <int S, int O>
-__device__ __forceinline__ v8i shifted(const v8i &w) {
-  // the O = 1 tuple by byte permutes (bytes S .. S + 3 of the dword pair), the O = 0
-  // tuple by byte aligns: the same values, which the compiler would otherwise compute
-  // once and then copy into the second tuple
-  constexpr uint32_t sel = (uint32_t)S | (uint32_t)(S + 1) << 8 | (uint32_t)(S + 2) << 16 |
-                           (uint32_t)(S + 3) << 24;
-  v8i r;
-#pragma unroll
-  for (int k = 0; k < 6; ++k)
-    r[k] = S == 0 ? w[k + O]
-           : O == 0 ? (int32_t)__builtin_amdgcn_alignbyte((uint32_t)w[k + 1], (uint32_t)w[k], (uint32_t)S)
-                    : (int32_t)__builtin_amdgcn_perm((uint32_t)w[k + 2], (uint32_t)w[k + 1], sel);
-  r[6] = 0;
-  r[7] = 0;
-  return r;
-}
-
-// The products of blocks S, S + 4, S + 8, S + 12.
-template <int S>
-__device__ __forceinline__ void mfma4(v4i (&acc)[kNT], const v4i &mk, const v8i &w,
-                                      const v8i &w1) {
-  const v8i e = S == 0 ? w : shifted<S, 0>(w);
-  const v8i o = S == 0 ? w1 : shifted<S, 1>(w);
-  acc[S] = __builtin_amdgcn_mfma_i32_16x16x64_i8(mk, __builtin_shufflevector(e, e, 0, 1, 2, 3),
-                                                 acc[S], 0, 0, 0);
-  acc[S + 4] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-      mk, __builtin_shufflevector(o, o, 0, 1, 2, 3), acc[S + 4], 0, 0, 0);
-  acc[S + 8] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-      mk, __builtin_shufflevector(e, e, 2, 3, 4, 5), acc[S + 8], 0, 0, 0);
-  acc[S + 12] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-      mk, __builtin_shufflevector(o, o, 2, 3, 4, 5), acc[S + 12], 0, 0, 0);
-}
-
-// The products of DM tile tw over outputs T0 .. T0 + NWT * 256 - 1 (wave (wd, wt):
-// trials 16 wd .. 16 wd + 15 of the tile, outputs T0 + 256 wt + ...; lane l, element r
-// of block b: trial row 4 (l / 16) + r, output 16 (l mod 16) + b).  Ends with a
-// workgroup barrier, after which the LDS is free.
-template <int NWD, int NWT, int WG, typename MA>
-__device__ __forceinline__ TileAcc<kNT> mfma_tile(MA &a, int tw, int64_t T0, const uint8_t *xb,
-                                                  unsigned char *lds) {
+// The products of DM tile tw over outputs T0 .. T0 + NWT * 64 NP - 1.  Wave (wd, wt)
+// takes trials 4 wd .. 4 wd + 3 of the tile and outputs T0 + 64 NP wt + ...; lane l,
+// element e of product q holds trial 4 wd + l / 16 at output 64 NP wt + 64 q + 4 (l mod
+// 16) + e.  Ends with a workgroup barrier, after which the LDS is free.
+template <int NWD, int NWT, int NP, int WG, typename MA>
+__device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, const uint8_t *xb,
+                                                 unsigned char *lds) {
   constexpr int NW = NWD * NWT;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wd = wave % NWD, wt = wave / NWD;
-  v4i acc[kNT];
+  v4i acc[NP];
 #pragma unroll
-  for (int b = 0; b < kNT; ++b) acc[b] = (v4i){0, 0, 0, 0};
+  for (int q = 0; q < NP; ++q) acc[q] = (v4i){0, 0, 0, 0};
 
   const int gb = ldc(a.group_begin, tw), ge = ldc(a.group_begin, tw + 1);
   // copies the K-block records of group g into LDS (buffer-to-LDS loads, 16 bytes a
@@ -273,7 +230,7 @@ __device__ __forceinline__ TileAcc<kNT> mfma_tile(MA &a, int tw, int64_t T0, con
   };
   // staging: thread t takes chunk t of the group
   uint32_t raw[8];
-  int sh = 0, dst = 0, cs = 0;
+  int sh = 0, dst = 0;
   bool has = false;
   auto fetch = [&](int g) {
     const int ub = ldc(&a.groups[g].unit_begin, 0), nu = ldc(&a.groups[g].nunits, 0);
@@ -282,19 +239,18 @@ __device__ __forceinline__ TileAcc<kNT> mfma_tile(MA &a, int tw, int64_t T0, con
       const MUnit u = a.units[ub + tid];
       load_raw(xb + (int64_t)u.c * a.in_stride, a.nsamp, T0 + u.src, raw, &sh);
       dst = u.dst;
-      cs = u.cs;
     }
   };
   auto store = [&](unsigned char *buf) {
-    if (has) store_chunk(buf, dst, cs, raw, sh);
+    if (has) store_chunk(buf, dst, raw, sh);
   };
   stage_recs(gb, lds);
   fetch(gb);
   store(lds);
   __builtin_amdgcn_s_waitcnt(kWaitVm0);
   __syncthreads();
-  // the lane's byte offset within a segment's aligned bytes
-  const int loff = 16 * (lane & 15) + kTWV * wt;
+  // the lane's byte offset from a segment's base: column lane mod 16 of the wave's run
+  const int loff = 16 * (lane & 15) + 4 * 64 * NP * wt;
   for (int g = gb; g < ge; ++g) {
     const int par = (g - gb) & 1;
     unsigned char *buf = lds + par * a.bufbytes;
@@ -306,67 +262,59 @@ __device__ __forceinline__ TileAcc<kNT> mfma_tile(MA &a, int tw, int64_t T0, con
     const int ro = ldc(&a.groups[g].rec_off, 0);
     const int k0 = ldc(a.kbr, (int64_t)kbase + wd), k1 = ldc(a.kbr, (int64_t)kbase + wd + 1);
     const unsigned char *rb = buf + ro + (int64_t)(k0 - kf) * kRecBytes;
-    // K blocks in pairs through two register sets, each block's mask and samples read
-    // while the other block's products run (no copies between the sets)
-    auto load = [&](const unsigned char *r, uint32_t &m, v8i &w, int32_t &a1) {
-      m = *(const uint16_t *)(r + 2 * lane);
-      const int32_t ad = *(const int32_t *)(r + 128 + 4 * (lane >> 4)) + loff;
-      a1 = *(const int32_t *)(r + 144 + 4 * (lane >> 4)) + loff;
-      w = *(const v8i *)(buf + ad);   // one 8-register tuple (two 16-byte reads)
-    };
-    auto products = [&](uint32_t m16, const v8i &W, int32_t a1) {
-      // the same bytes from 4 bytes on (dwords 1 .. 6), read in place of copies into
-      // even-aligned registers for the unshifted blocks at odd dword offsets, which go last
-      const v4i lo = *(const v4i *)(buf + a1);
-      const v2i hi = *(const v2i *)(buf + a1 + 16);
-      // 16 mask bytes of lane (trial row lane % 16, segment lane / 16): bit j -> byte j
+    // while its products run, this wave is issued ahead of waves in their staging stores or
+    // boxcar stage (of the CU's other workgroup, or of this one)
+    __builtin_amdgcn_s_setprio(1);
+    for (int kb = k0; kb < k1; ++kb, rb += kRecBytes) {
+      const uint32_t m16 = *(const uint16_t *)(rb + 2 * lane);
+      const unsigned char *bp = buf + *(const int32_t *)(rb + 128 + 4 * (lane >> 4)) + loff;
+      // 16 mask bytes of lane (row lane % 16, segment lane / 16): bit j -> byte j
       v4i mk;
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         mk[k] = (int32_t)((((m16 >> (4 * k)) & 15u) * 0x204081u) & 0x01010101u);
-      // Block b = 4 q + s takes bytes b .. b + 15 of the lane's 32: dwords q .. q + 3 of
-      // the lane's bytes shifted down by s
-      mfma4<1>(acc, mk, W, W);
-      mfma4<2>(acc, mk, W, W);
-      mfma4<3>(acc, mk, W, W);
-      const v8i W1 = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], 0, 0};
-      mfma4<0>(acc, mk, W, W1);
-    };
-    uint32_t ma = 0, mb = 0;
-    int32_t aa = 0, ab = 0;
-    v8i wa = {0, 0, 0, 0, 0, 0, 0, 0}, wb = {0, 0, 0, 0, 0, 0, 0, 0};
-    int kb = k0;
-    // while its products run, this wave is issued ahead of waves in their staging stores or
-    // boxcar stage (of the CU's other workgroup, or of this one)
-    __builtin_amdgcn_s_setprio(1);
-    if (kb < k1) load(rb, ma, wa, aa);
-    for (; kb + 1 < k1; kb += 2) {
-      load(rb + kRecBytes, mb, wb, ab);
-      products(ma, wa, aa);
-      if (kb + 2 < k1) load(rb + 2 * kRecBytes, ma, wa, aa);
-      products(mb, wb, ab);
-      rb += 2 * kRecBytes;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const v4i bq = *(const v4i *)(bp + 256 * q);
+        acc[q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(mk, bq, acc[q], 0, 0, 0);
+      }
     }
-    if (kb < k1) products(ma, wa, aa);
     __builtin_amdgcn_s_setprio(0);
     if (g + 1 < ge) store(lds + (par ^ 1) * a.bufbytes);
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
   }
-  TileAcc<kNT> r;
+  TileAcc<NP> r;
 #pragma unroll
-  for (int b = 0; b < kNT; ++b) r.v[b] = acc[b];
+  for (int q = 0; q < NP; ++q) r.v[q] = acc[q];
   return r;
+}
+
+// The accumulators of a wave in two passes of 2 trials each: swapping the upper lanes of
+// products q < NP / 2 with the lower lanes of products q + NP / 2 gives every lane, in
+// pass p, trial 2 p + (l / 16) mod 2 of the wave at outputs 64 (q + (NP / 2) (l / 32)) +
+// 4 (l mod 16) + e (q < NP / 2, element e).
+template <int NP>
+__device__ __forceinline__ void split_passes(const TileAcc<NP> &acc, v4i (&ps)[2][NP / 2]) {
+#pragma unroll
+  for (int q = 0; q < NP / 2; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const auto p = __builtin_amdgcn_permlane32_swap(acc.v[q][e], acc.v[q + NP / 2][e], false,
+                                                      false);
+      ps[0][q][e] = (int32_t)p[0];
+      ps[1][q][e] = (int32_t)p[1];
+    }
 }
 
 // WG workgroups per CU (their LDS), so WG NW / 4 waves per SIMD: registers up to 512 /
 // that.
-template <int NWD, int NWT, int WG>
+template <int NWD, int NWT, int NP, int WG>
 __global__ void __launch_bounds__(64 * NWD * NWT)
 __attribute__((amdgpu_waves_per_eu(WG * NWD * NWT / 4, WG * NWD * NWT / 4)))
 k_dedisp_mfma(MfmaArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  constexpr int TW = NWT * kTWV;
+  constexpr int TWV = 64 * NP, TW = NWT * TWV;
   int tt, tw;
   tile_of_block(a.ntw, a.ntt, &tt, &tw);
   const int bb = blockIdx.y;
@@ -374,48 +322,33 @@ k_dedisp_mfma(MfmaArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wd = wave % NWD, wt = wave / NWD;
   const int64_t T0 = (int64_t)tt * TW;
-  const TileAcc<kNT> acc =
-      mfma_tile<NWD, NWT, WG>(a, tw, T0, a.x + (int64_t)bb * a.in_bstride, lds);
-  // Lane l holds, for trial rows 4 (l / 16) + r, the 16 outputs from 16 (l mod 16): the
-  // rows go out through LDS (free after the tile's last barrier; each wave has its own
-  // 8 rows), so that each store instruction writes 256 consecutive bytes of a row.
-  // Swapping the upper lanes of blocks b < 8 with the lower lanes of blocks b + 8 first
-  // gives every lane, in pass p, trial row 8 p + 4 ((l / 16) mod 2) + r at outputs
-  // 16 (l mod 16) + 8 (l / 32) + b, b < 8.
-  constexpr int OROW = kTWV + 4;
-  static_assert(NWD * NWT * 8 * OROW * 4 <= 2 * (kMfmaBufBytes / WG), "output rows fit the LDS");
-  int *R = (int *)lds + wave * 8 * OROW;
-  v4i ps[2][kNT / 2];
-#pragma unroll
-  for (int b = 0; b < kNT / 2; ++b)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const auto p = __builtin_amdgcn_permlane32_swap(acc.v[b][r], acc.v[b + kNT / 2][r], false,
-                                                      false);
-      ps[0][b][r] = (int32_t)p[0];
-      ps[1][b][r] = (int32_t)p[1];
-    }
+  const TileAcc<NP> acc =
+      mfma_tile<NWD, NWT, NP, WG>(a, tw, T0, a.x + (int64_t)bb * a.in_bstride, lds);
+  // The rows go out through LDS (free after the tile's last barrier; each wave has its
+  // own 2 rows), so that each store instruction writes 256 consecutive bytes of a row.
+  constexpr int OROW = TWV + 4;
+  static_assert(NWD * NWT * 2 * OROW * 4 <= 2 * (kMfmaBufBytes / WG), "output rows fit the LDS");
+  int *R = (int *)lds + wave * 2 * OROW;
+  v4i ps[2][NP / 2];
+  split_passes<NP>(acc, ps);
   int32_t *ob = a.out + (int64_t)bb * a.out_bstride;
-  const int64_t t0 = T0 + (int64_t)kTWV * wt;
-  const int col = 16 * (lane & 15) + 8 * (lane >> 5);
+  const int64_t t0 = T0 + (int64_t)TWV * wt;
+  const int col = 4 * (lane & 15) + (TWV / 2) * (lane >> 5);
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
+    int *row = R + ((lane >> 4) & 1) * OROW + col;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int *row = R + (4 * ((lane >> 4) & 1) + r) * OROW + col;
-      *(v4i *)row = (v4i){ps[pass][0][r], ps[pass][1][r], ps[pass][2][r], ps[pass][3][r]};
-      *(v4i *)(row + 4) = (v4i){ps[pass][4][r], ps[pass][5][r], ps[pass][6][r], ps[pass][7][r]};
-    }
+    for (int q = 0; q < NP / 2; ++q) *(v4i *)(row + 64 * q) = ps[pass][q];
     // LDS operations of one wave complete in order: the reads below see the writes
     __builtin_amdgcn_wave_barrier();
 #pragma unroll 1
-    for (int k = 0; k < 8; ++k) {
-      const int d = a.perm[tw * 16 * NWD + 16 * wd + 8 * pass + k];
+    for (int k = 0; k < 2; ++k) {
+      const int d = a.perm[tw * kTrialsPerWave * NWD + kTrialsPerWave * wd + 2 * pass + k];
       if (d < 0) continue;
       const int32_t corr = 128 * a.ntot[d];
       int32_t *o = ob + (int64_t)d * a.out_stride + t0;
 #pragma unroll
-      for (int j = 0; j < kTWV / 64; ++j)
+      for (int j = 0; j < TWV / 64; ++j)
         if (t0 + lane + 64 * j < a.nout) o[lane + 64 * j] = R[k * OROW + lane + 64 * j] + corr;
     }
     __builtin_amdgcn_wave_barrier();
@@ -436,13 +369,13 @@ constexpr int search_step(int sp) { return 64 * sp - ((32 + sp - 1) / sp) * sp; 
 
 // Fused search: the products of one tile (outputs T0 .. T0 + TW - 1, T0 = tt * TT),
 // then the boxcar search of every trial of the tile over starts T0 .. T0 + TT - 1.
-// The series go through LDS in two passes (trial rows 0-7, then 8-15 of every wave),
-// as rows of TW + 36 ints; each wave searches whole rows.
-template <int NWD, int NWT, int WG, typename SA>
+// The series go through LDS in two passes (trials 0-1, then 2-3 of every wave), as rows
+// of TW + 36 ints; each wave searches whole rows.
+template <int NWD, int NWT, int NP, int WG, typename SA>
 __device__ __forceinline__ void search_tile_mfma(SA &sa, int tt, int tw, unsigned char *lds) {
-  constexpr int NW = NWD * NWT, TW = NWT * kTWV, SP = TW / 64;
+  constexpr int NW = NWD * NWT, TWV = 64 * NP, TW = NWT * TWV, SP = TW / 64;
   constexpr int TT = search_step(SP), YROW = TW + kHalo + 4;
-  constexpr int PT = 8;                    // trials of one wave in one pass
+  constexpr int PT = 2;                    // trials of one wave in one pass
   constexpr int ROWS = PT * NWD;           // rows of one pass
   static_assert(TW % 64 == 0 && TT % SP == 0 && TW - TT >= 31, "search tile");
   static_assert(ROWS % NW == 0, "whole rows per wave");
@@ -453,49 +386,29 @@ __device__ __forceinline__ void search_tile_mfma(SA &sa, int tt, int tw, unsigne
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wd = wave % NWD, wt = wave / NWD;
   const int64_t T0 = (int64_t)tt * TT;
-  const TileAcc<kNT> acc = mfma_tile<NWD, NWT, WG>(a, tw, T0, a.x, lds);
-  constexpr int DT = 16 * NWD;
+  const TileAcc<NP> acc = mfma_tile<NWD, NWT, NP, WG>(a, tw, T0, a.x, lds);
+  constexpr int DT = kTrialsPerWave * NWD;
   int *Y = (int *)lds;
-  // A lane's 4 trial rows (4 (l / 16) + r) are those of one pass: lanes 0-31 hold the
-  // first pass's trials, lanes 32-63 the second's.  Swapping the upper lanes of blocks
-  // b < 8 with the lower lanes of blocks b + 8 puts each pass's values into 8
-  // registers (b) per row of every lane, so the second pass's values take 32
-  // registers (not 64) during the first pass's search, and each pass writes its rows
-  // with all lanes.  After the swap, register (b, r) of pass p holds, in lane l, trial
-  // row 4 ((l / 16) mod 2) + r of the pass, output 16 (l mod 16) + 8 (l / 32) + b of
-  // the wave's run.
-  v4i ps[2][kNT / 2];
-#pragma unroll
-  for (int b = 0; b < kNT / 2; ++b)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const auto p = __builtin_amdgcn_permlane32_swap(acc.v[b][r], acc.v[b + kNT / 2][r], false,
-                                                      false);
-      ps[0][b][r] = (int32_t)p[0];
-      ps[1][b][r] = (int32_t)p[1];
-    }
-  const int col = kTWV * wt + 16 * (lane & 15) + 8 * (lane >> 5);
+  v4i ps[2][NP / 2];
+  split_passes<NP>(acc, ps);
+  const int col = TWV * wt + 4 * (lane & 15) + (TWV / 2) * (lane >> 5);
+  const int k = (lane >> 4) & 1;           // trial of the pass this lane holds
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
+    const int d = a.perm[tw * DT + kTrialsPerWave * wd + PT * pass + k];
+    const int32_t corr = d >= 0 ? 128 * a.ntot[d] : 0;
+    int *row = Y + (PT * wd + k) * YROW + col;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int k = 4 * ((lane >> 4) & 1) + r;   // trial row within the pass
-      const int d = a.perm[tw * DT + 16 * wd + PT * pass + k];
-      const int32_t corr = d >= 0 ? 128 * a.ntot[d] : 0;
-      int *row = Y + (PT * wd + k) * YROW + col;
-      *(v4i *)row = (v4i){ps[pass][0][r] + corr, ps[pass][1][r] + corr, ps[pass][2][r] + corr,
-                          ps[pass][3][r] + corr};
-      *(v4i *)(row + 4) = (v4i){ps[pass][4][r] + corr, ps[pass][5][r] + corr,
-                                ps[pass][6][r] + corr, ps[pass][7][r] + corr};
-    }
+    for (int q = 0; q < NP / 2; ++q)
+      *(v4i *)(row + 64 * q) = ps[pass][q] + (v4i){corr, corr, corr, corr};
     __syncthreads();
     // one row at a time, not unrolled: the search code then stays small enough
     // for the instruction cache
 #pragma unroll 1
-    for (int k = 0; k < ROWS / NW; ++k) {
-      const int rw = wave * (ROWS / NW) + k;
-      const int sw = rw / PT, j = rw % PT;   // DM sub-tile, trial row within the pass
-      const int dg = a.perm[tw * DT + 16 * sw + PT * pass + j];
+    for (int r = 0; r < ROWS / NW; ++r) {
+      const int rw = wave * (ROWS / NW) + r;
+      const int sw = rw / PT, j = rw % PT;   // wave along DM, trial of the pass
+      const int dg = a.perm[tw * DT + kTrialsPerWave * sw + PT * pass + j];
       const CandRec rec =
           boxcar_row<SP>(Y + rw * YROW, lane, T0, TT, a.nout, dg, sa.wmask, sa.nw, sa.M, sa.S);
       if (dg >= 0 && lane == 0) sa.part[(int64_t)dg * a.ntt + tt] = rec;
@@ -504,14 +417,14 @@ __device__ __forceinline__ void search_tile_mfma(SA &sa, int tt, int tw, unsigne
   }
 }
 
-template <int NWD, int NWT, int WG>
+template <int NWD, int NWT, int NP, int WG>
 __global__ void __launch_bounds__(64 * NWD * NWT)
 __attribute__((amdgpu_waves_per_eu(WG * NWD * NWT / 4, WG * NWD * NWT / 4)))
 k_search_mfma(MfmaSearchArgs sa) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   int tt, tw;
   tile_of_block(sa.m.ntw, sa.m.ntt, &tt, &tw);
-  search_tile_mfma<NWD, NWT, WG>(sa, tt, tw, lds);
+  search_tile_mfma<NWD, NWT, NP, WG>(sa, tt, tw, lds);
 }
 
 // Multi-beam fused search: one workgroup per (beam, tile).  Beam b owns the blocks
@@ -519,7 +432,7 @@ k_search_mfma(MfmaSearchArgs sa) {
 // block i of a beam runs on XCD i mod 8 and the beam's tiles take the one-beam
 // kernel's XCD-aware order.  Blocks past a beam's tile count exit at once (the whole
 // workgroup, before any barrier).
-template <int NWD, int NWT, int WG>
+template <int NWD, int NWT, int NP, int WG>
 __global__ void __launch_bounds__(64 * NWD * NWT)
 __attribute__((amdgpu_waves_per_eu(WG * NWD * NWT / 4, WG * NWD * NWT / 4)))
 k_search_mfma_batch(const MfmaSearchArgs *__restrict__ beams, const int32_t *__restrict__ base,
@@ -541,7 +454,7 @@ k_search_mfma_batch(const MfmaSearchArgs *__restrict__ beams, const int32_t *__r
   if (k >= q + (xcd < rem ? 1 : 0)) return;
   const int L = xcd * q + min(xcd, rem) + k;
   const int tt = L / sa.m.ntw, tw = L - tt * sa.m.ntw;
-  search_tile_mfma<NWD, NWT, WG>(sa, tt, tw, lds);
+  search_tile_mfma<NWD, NWT, NP, WG>(sa, tt, tw, lds);
 }
 
 }  // namespace
@@ -556,11 +469,12 @@ static hipError_t upload(T **dst, const std::vector<T> &v) {
 }
 
 // Tables of configuration ci: trial order, per DM tile the channel groups with their
-// staging units, and per (group, wave) the K blocks (masks and lane addresses).
+// staging units, and per (group, wave along DM) the K blocks (masks and segment bases).
 static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
   const MfmaCfg cf = kMfmaCfgs[ci];
   const int C = p->nchan, D = p->ndm;
-  const int NWD = cf.nwd, NW = cf.nwd * cf.nwt, TW = cf.nwt * kTWV, DT = 16 * NWD;
+  constexpr int TPW = kTrialsPerWave;
+  const int NWD = cf.nwd, NW = cf.nwd * cf.nwt, TW = cf.nwt * 64 * cf.np, DT = TPW * NWD;
   const int BUF = kMfmaBufBytes / cf.wg;
   const int maxunits = 64 * NW;
   out = MfmaCfgTables();
@@ -582,23 +496,24 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
     out.ntot[d] = (int32_t)s;
   }
   out.group_begin.assign(ntw + 1, 0);
-  // per (sub-tile, channel): first segment (window-relative, a multiple of 4) and count
+  // per (wave along DM, channel): first segment (window-relative, a multiple of 4) and count
   std::vector<int32_t> so(NWD * C), nseg(NWD * C);
-  // per channel: window origin (absolute delay of window byte 0) and copy length
+  // per channel: window origin (absolute delay of window byte 0) and bytes per copy
   std::vector<int32_t> wlo(C), clen(C);
   for (int tw = 0; tw < ntw; ++tw) {
     out.group_begin[tw] = (int)out.groups.size();
     for (int c = 0; c < C; ++c) {
-      int l[64], h[64];
+      std::vector<int> l(NWD), h(NWD);
       int slo = INT32_MAX;
       for (int w = 0; w < NWD; ++w) {
         l[w] = INT32_MAX;
         h[w] = INT32_MIN;
-        for (int m = 0; m < 16; ++m) {
-          const int d = out.perm[(size_t)tw * DT + 16 * w + m];
+        for (int m = 0; m < TPW; ++m) {
+          const int d = out.perm[(size_t)tw * DT + TPW * w + m];
           if (d < 0 || p->ntap[(size_t)d * C + c] == 0) continue;
           l[w] = std::min(l[w], p->start[(size_t)d * C + c]);
-          h[w] = std::max(h[w], p->start[(size_t)d * C + c] + p->ntap[(size_t)d * C + c]);
+          // the phase rows u = 1 .. 3 take the run's samples up to 3 later
+          h[w] = std::max(h[w], p->start[(size_t)d * C + c] + p->ntap[(size_t)d * C + c] + 3);
         }
         slo = std::min(slo, l[w]);
       }
@@ -608,7 +523,7 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
         continue;
       }
       wlo[c] = slo;
-      int qmax = 0;
+      int smax = 0;   // largest segment start
       for (int w = 0; w < NWD; ++w) {
         if (l[w] == INT32_MAX) {
           nseg[w * C + c] = 0;
@@ -617,11 +532,11 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
         const int o = (l[w] - slo) / 4 * 4;   // on the 4-byte grid, at or below the band
         so[w * C + c] = o;
         nseg[w * C + c] = (h[w] - (slo + o) + 15) / 16;
-        qmax = std::max(qmax, (o + 16 * (nseg[w * C + c] - 1)) / 16);
+        smax = std::max(smax, o + 16 * (nseg[w * C + c] - 1));
       }
-      // lane n of time wave wt reads chunks q + n + 16 wt and q + n + 1 + 16 wt, and 24
-      // bytes from 4 bytes further on (up to chunk q + n + 2 + 16 wt)
-      clen[c] = 16 * (qmax + 16 * cf.nwt + 2);
+      // the last lane reads 16 bytes from window byte smax + TW - 4: chunks up to that
+      // byte / 16
+      clen[c] = 16 * ((smax + TW - 4) / 16 + 1);
       if ((int64_t)kCopies * clen[c] + kRecBytes > BUF || clen[c] / 16 > maxunits) return false;
     }
     int c = 0;
@@ -649,7 +564,7 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
         if (!clen[cc]) continue;
         region[cc] = off;
         for (int k = 0; k < clen[cc] / 16; ++k)
-          out.units.push_back(MUnit{cc, wlo[cc] + 16 * k, off + 16 * k, clen[cc]});
+          out.units.push_back(MUnit{cc, wlo[cc] + 16 * k, off + 64 * k, 0});
         off += kCopies * clen[cc];
       }
       gi.nunits = (int)out.units.size() - gi.unit_begin;
@@ -658,8 +573,8 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
       gi.rec_off = off;
       for (int w = 0; w < NWD; ++w) {
         out.kbr.push_back((int32_t)(out.recs.size() / kRecBytes));
-        // segments of this sub-tile in the group (channel, window-relative start), four
-        // per K block
+        // segments of this wave's trials in the group (channel, window-relative start),
+        // four per K block
         std::vector<std::pair<int, int>> segs;
         for (int cc = cbeg; cc < c; ++cc)
           for (int sg = 0; sg < nseg[w * C + cc]; ++sg) segs.push_back({cc, so[w * C + cc] + 16 * sg});
@@ -669,23 +584,22 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
             // padding segments: zero masks, a valid address
             const size_t si = s0 + g < segs.size() ? s0 + g : s0;
             const int cc = segs[si].first, o = segs[si].second;
-            // copy (o / 4) mod 4 holds window byte o at offset 16 (o / 16); the second
-            // address is that of byte o + 4
-            const int32_t ad = region[cc] + ((o >> 2) & 3) * clen[cc] + 16 * (o >> 4);
-            const int32_t ad1 =
-                region[cc] + (((o + 4) >> 2) & 3) * clen[cc] + 16 * ((o + 4) >> 4);
+            // window byte o (a multiple of 4) of the interleaved copies is at region + 4 o
+            const int32_t ad = region[cc] + 4 * o;
             std::memcpy(rec.data() + 128 + 4 * g, &ad, 4);
-            std::memcpy(rec.data() + 144 + 4 * g, &ad1, 4);
             if (s0 + g >= segs.size()) continue;
             const int oa = wlo[cc] + o;   // absolute delay of the segment's first byte
-            for (int m = 0; m < 16; ++m) {
-              const int d = out.perm[(size_t)tw * DT + 16 * w + m];
+            for (int m = 0; m < TPW; ++m) {
+              const int d = out.perm[(size_t)tw * DT + TPW * w + m];
               if (d < 0) continue;
               const int st = p->start[(size_t)d * C + cc], nt = p->ntap[(size_t)d * C + cc];
-              uint16_t bits = 0;
-              for (int j = 0; j < 16; ++j)
-                if (oa + j >= st && oa + j < st + nt) bits |= (uint16_t)(1u << j);
-              std::memcpy(rec.data() + 2 * (16 * g + m), &bits, 2);
+              for (int u = 0; u < 4; ++u) {
+                // row (trial m, phase u) takes byte j when its delay less u is in the run
+                uint16_t bits = 0;
+                for (int j = 0; j < 16; ++j)
+                  if (oa + j - u >= st && oa + j - u < st + nt) bits |= (uint16_t)(1u << j);
+                std::memcpy(rec.data() + 2 * (16 * g + 4 * m + u), &bits, 2);
+              }
             }
           }
           out.recs.insert(out.recs.end(), rec.begin(), rec.end());
@@ -713,22 +627,22 @@ static hipError_t allow_lds_mfma(const void *fn, bool *done, std::mutex *mu, int
   return e;
 }
 
-template <int NWD, int NWT, int WG>
+template <int NWD, int NWT, int NP, int WG>
 static hipError_t launch_mfma_cfg(const MfmaArgs &a, int nbatch, hipStream_t s) {
   static bool done[64] = {};
   static std::mutex mu;
-  hipError_t e = allow_lds_mfma((const void *)k_dedisp_mfma<NWD, NWT, WG>, done, &mu,
+  hipError_t e = allow_lds_mfma((const void *)k_dedisp_mfma<NWD, NWT, NP, WG>, done, &mu,
                                 2 * (kMfmaBufBytes / WG));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_dedisp_mfma<NWD, NWT, WG>), dim3(a.ntw * a.ntt, nbatch),
+  hipLaunchKernelGGL((k_dedisp_mfma<NWD, NWT, NP, WG>), dim3(a.ntw * a.ntt, nbatch),
                      dim3(64 * NWD * NWT), 2 * a.bufbytes, s, a);
   return hipGetLastError();
 }
 
 static hipError_t launch_mfma(int ci, const MfmaArgs &a, int nbatch, hipStream_t s) {
   switch (ci) {
-#define DD_MFMA_CASE(i, x, y, g) \
-  case i: return launch_mfma_cfg<x, y, g>(a, nbatch, s);
+#define DD_MFMA_CASE(i, x, y, n, g) \
+  case i: return launch_mfma_cfg<x, y, n, g>(a, nbatch, s);
     DD_MFMA_CONFIGS(DD_MFMA_CASE)
 #undef DD_MFMA_CASE
     default: return hipErrorInvalidValue;
@@ -820,7 +734,7 @@ struct MfmaSearchLayout {
 
 static MfmaSearchLayout search_layout(const dedisp_plan_s *p, int k, int32_t nw, int64_t nout) {
   const MfmaCfg cf = kMfmaCfgs[k];
-  const int tw = cf.nwt * kTWV, tstep = search_step(tw / 64);
+  const int tw = cf.nwt * 64 * cf.np, tstep = search_step(tw / 64);
   MfmaSearchLayout L;
   L.ntt = (nout + tstep - 1) / tstep;
   L.off_part = (2 * sizeof(double) * (size_t)p->ndm * nw + 255) & ~(size_t)255;
@@ -836,22 +750,22 @@ size_t mfma_search_work_bytes(const dedisp_plan_s *p, int32_t nw, int64_t nout) 
 
 int mfma_search_count() { return kNumMfmaCfgs; }
 
-template <int NWD, int NWT, int WG>
+template <int NWD, int NWT, int NP, int WG>
 static hipError_t launch_search_cfg(const MfmaSearchArgs &sa, hipStream_t s) {
   static bool done[64] = {};
   static std::mutex mu;
-  hipError_t e = allow_lds_mfma((const void *)k_search_mfma<NWD, NWT, WG>, done, &mu,
+  hipError_t e = allow_lds_mfma((const void *)k_search_mfma<NWD, NWT, NP, WG>, done, &mu,
                                 2 * (kMfmaBufBytes / WG));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_search_mfma<NWD, NWT, WG>), dim3(sa.m.ntw * sa.m.ntt),
+  hipLaunchKernelGGL((k_search_mfma<NWD, NWT, NP, WG>), dim3(sa.m.ntw * sa.m.ntt),
                      dim3(64 * NWD * NWT), 2 * sa.m.bufbytes, s, sa);
   return hipGetLastError();
 }
 
 static hipError_t launch_search_mfma(int k, const MfmaSearchArgs &sa, hipStream_t s) {
   switch (k) {
-#define DD_MFMA_SEARCH_CASE(i, x, y, g) \
-  case i: return launch_search_cfg<x, y, g>(sa, s);
+#define DD_MFMA_SEARCH_CASE(i, x, y, n, g) \
+  case i: return launch_search_cfg<x, y, n, g>(sa, s);
     DD_MFMA_CONFIGS(DD_MFMA_SEARCH_CASE)
 #undef DD_MFMA_SEARCH_CASE
     default: return hipErrorInvalidValue;
@@ -989,15 +903,15 @@ dedisp_status mfma_batch_create(const std::vector<dedisp_plan> &plans,
   return DEDISP_OK;
 }
 
-template <int NWD, int NWT, int WG>
+template <int NWD, int NWT, int NP, int WG>
 static hipError_t launch_batch_mfma_cfg(const MfmaBatch *B, const MfmaSearchArgs *table,
                                         hipStream_t s) {
   static bool done[64] = {};
   static std::mutex mu;
-  hipError_t e = allow_lds_mfma((const void *)k_search_mfma_batch<NWD, NWT, WG>, done, &mu,
+  hipError_t e = allow_lds_mfma((const void *)k_search_mfma_batch<NWD, NWT, NP, WG>, done, &mu,
                                 2 * (kMfmaBufBytes / WG));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_search_mfma_batch<NWD, NWT, WG>), dim3(B->base.back()),
+  hipLaunchKernelGGL((k_search_mfma_batch<NWD, NWT, NP, WG>), dim3(B->base.back()),
                      dim3(64 * NWD * NWT), 2 * (kMfmaBufBytes / WG), s, table, B->d_base,
                      B->nbeam);
   return hipGetLastError();
@@ -1006,8 +920,8 @@ static hipError_t launch_batch_mfma_cfg(const MfmaBatch *B, const MfmaSearchArgs
 static hipError_t launch_batch_mfma(const MfmaBatch *B, const MfmaSearchArgs *table,
                                     hipStream_t s) {
   switch (B->k) {
-#define DD_MFMA_BATCH_CASE(i, x, y, g) \
-  case i: return launch_batch_mfma_cfg<x, y, g>(B, table, s);
+#define DD_MFMA_BATCH_CASE(i, x, y, n, g) \
+  case i: return launch_batch_mfma_cfg<x, y, n, g>(B, table, s);
     DD_MFMA_CONFIGS(DD_MFMA_BATCH_CASE)
 #undef DD_MFMA_BATCH_CASE
     default: return hipErrorInvalidValue;

@@ -96,9 +96,9 @@ def _check_detect_all(widths, y64, M, S, det, snr, t, W):
         assert alt == pytest.approx(so[d], rel=1e-12), (d, t[d], W[d], to[d], wo[d])
 
 
-# The default shape, the shape the benchmark's autotuner picks on the boxes measured so
-# far, and whatever it picks on this one (the launch configuration the benchmark times).
-@pytest.mark.parametrize("tile", [-1, 12, "autotuned"])
+# The default shape, every matrix-core shape, and whatever the autotuner picks on this
+# box (the launch configuration the benchmark times).
+@pytest.mark.parametrize("tile", [-1, 8, 9, 10, 11, 12, "autotuned"])
 def test_cfg2_full_size_all_trials(dd, orc, cfg2_full, tile):
     import torch
     wl, p, n, yo, y64, M, S, det = cfg2_full
@@ -110,8 +110,8 @@ def test_cfg2_full_size_all_trials(dd, orc, cfg2_full, tile):
     else:
         p.set_tile(tile)
     snr, t, W = p.search(x, wl.widths, mu, sg)
-    if tile == 12:
-        assert p.last_search_tile() == 12
+    if isinstance(tile, int) and tile >= 0:
+        assert p.last_search_tile() == tile
     elif tile == "autotuned":
         assert 0 <= p.last_search_tile() <= 12
     _check_detect_all(wl.widths, y64, M, S, det, snr, t, W)
