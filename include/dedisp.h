@@ -162,6 +162,29 @@ dedisp_status dedisp_search(dedisp_plan plan, const void *d_in, int32_t in_dtype
                             int32_t *d_t, int32_t *d_w, void *d_work, size_t work_bytes,
                             void *stream);
 
+/* Allocation-free fused search, for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments and results as dedisp_search for uint8 input with unit weights and
+ * widths up to 32, without the workspace: the search runs on the matrix cores with a
+ * library-owned device array of DEDISP_NOALLOC_SCRATCH_BYTES per GPU as its
+ * workspace (held until the process ends), and the call allocates nothing.
+ * Requirements and errors:
+ *   - the plan's device tables must already exist on the current device: run
+ *     dedisp_search (or dedisp_autotune) with the plan once first; otherwise
+ *     INVALID_ARG, with nothing launched;
+ *   - the workspace the block needs (16 B per trial and width for the noise tables,
+ *     16 B per trial and time tile of about 1000 outputs for the candidates) must fit
+ *     the array, else INVALID_ARG; other inputs UNSUPPORTED.
+ * Every call on one GPU uses that GPU's array: calls that overlap on one GPU (on
+ * different streams, or from different threads) race; calls in stream order do not.
+ * The shape is the plan's tuned or forced matrix-core shape, else the default one. */
+#define DEDISP_NOALLOC_SCRATCH_BYTES (16u << 20)
+dedisp_status dedisp_search_noalloc(dedisp_plan plan, const void *d_in, int32_t in_dtype,
+                                    int64_t nsamp, int64_t in_stride, const int32_t *widths,
+                                    int32_t nw, const double *d_chan_mean,
+                                    const double *d_chan_sigma, double *d_snr, int32_t *d_t,
+                                    int32_t *d_w, void *stream);
+
 /* Adjoint of dedisp_dedisperse (the transpose of eq. p_dedisp), for gradients:
  *   grad_w[c][k] += sum_b sum_d sum_t g[b][d][t] x[b][c][t + start + k]   (fp64, device,
  *                   [nchan][K], K = ktaps for TAP weights, 1 otherwise)

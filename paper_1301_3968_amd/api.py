@@ -184,6 +184,21 @@ class Plan:
                                       _ptr(work), work.numel(), _stream()))
         return snr, t, W
 
+    def search_noalloc(self, x: torch.Tensor, widths: Sequence[int], mean: torch.Tensor,
+                       sigma: torch.Tensor, outputs):
+        """The fused search without a workspace (dedisp_search_noalloc): the library
+        allocates nothing; mean, sigma are device fp64 [nchan] and outputs a
+        preallocated device (snr f64, t i32, W i32) triple of [ndm] tensors."""
+        _dev_check(x, "x")
+        C, T = x.shape
+        w = self._widths(widths)
+        snr, t, W = outputs
+        L.check(L.lib().dedisp_search_noalloc(self._h, _ptr(x), _TORCH_DT[x.dtype], T,
+                                              x.stride(0), _ptr(w), len(w), _ptr(mean),
+                                              _ptr(sigma), _ptr(snr), _ptr(t), _ptr(W),
+                                              _stream()))
+        return snr, t, W
+
     # ----------------------------------------------------------------- backward
     def backward(self, grad_y: torch.Tensor, x: torch.Tensor, need_x: bool = True,
                  need_w: bool = True, weights: Optional[torch.Tensor] = None):

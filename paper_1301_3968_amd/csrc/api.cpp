@@ -253,6 +253,23 @@ dedisp_status dedisp_search(dedisp_plan p, const void *d_in, int32_t in_dtype, i
   return DEDISP_OK;
 }
 
+dedisp_status dedisp_search_noalloc(dedisp_plan p, const void *d_in, int32_t in_dtype,
+                                    int64_t nsamp, int64_t in_stride, const int32_t *widths,
+                                    int32_t nw, const double *d_chan_mean,
+                                    const double *d_chan_sigma, double *d_snr, int32_t *d_t,
+                                    int32_t *d_w, void *stream) {
+  int64_t nout = 0;
+  dedisp_status st = dd::check_block(p, d_in, in_dtype, nsamp, in_stride, &nout);
+  if (st != DEDISP_OK) return st;
+  if (in_dtype != DEDISP_U8) return fail(DEDISP_ERR_UNSUPPORTED, "the allocation-free search takes uint8 input");
+  if (!d_chan_mean || !d_chan_sigma || !d_snr || !d_t || !d_w)
+    return fail(DEDISP_ERR_INVALID_ARG, "null argument");
+  dd::WidthList wl;
+  if ((st = dd::make_widths(widths, nw, nout, &wl)) != DEDISP_OK) return st;
+  return dd::run_search_noalloc(p, (const uint8_t *)d_in, nsamp, in_stride, nout, wl, d_chan_mean,
+                                d_chan_sigma, d_snr, d_t, d_w, (hipStream_t)stream);
+}
+
 dedisp_status dedisp_dedisperse_backward(dedisp_plan p, const float *d_grad_y, int64_t nout,
                                          int64_t gy_stride, int64_t gy_bstride, int32_t nbatch,
                                          const void *d_in, int32_t in_dtype, int64_t nsamp,

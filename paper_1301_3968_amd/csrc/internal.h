@@ -188,6 +188,14 @@ dedisp_status run_search_mfma(dedisp_plan p, int k, const uint8_t *x, int64_t ns
                               int64_t in_stride, int64_t nout, const WidthList &wl,
                               const double *mu, const double *sigma, double *snr, int32_t *t,
                               int32_t *w, void *work, hipStream_t s);
+// Fused search of a uint8 block with unit weights on the matrix cores, with the
+// library's per-device scratch array as its workspace (kernels_mfma.hip): allocates
+// nothing; fails when the plan's device tables are not built yet or the workspace
+// would exceed the array.
+dedisp_status run_search_noalloc(dedisp_plan p, const uint8_t *x, int64_t nsamp,
+                                 int64_t in_stride, int64_t nout, const WidthList &wl,
+                                 const double *mu, const double *sigma, double *snr, int32_t *t,
+                                 int32_t *w, hipStream_t s);
 // Multi-beam fused search on the matrix cores (kernels_mfma.hip): one shape for all
 // beams (`prefer` if it takes them all, else the first that does); *out stays null
 // when no shape takes every beam.

@@ -32,6 +32,7 @@
 #include <cstring>
 #include <mutex>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "boxcar_row.h"
@@ -804,6 +805,71 @@ dedisp_status run_search_mfma(dedisp_plan p, int k, const uint8_t *x, int64_t ns
   DD_HIP(kt.end());
   DD_HIP(launch_reduce(p->ndm, (int32_t)L.ntt, sa.part, snr, t, w, s));
   return DEDISP_OK;
+}
+
+// ---- allocation-free fused search -------------------------------------------------
+// The workspace of the fused search (noise tables and per-(trial, time tile)
+// candidates) in a file-scope device array, for callers that cannot allocate.  Host
+// code never passes the array's name to a kernel (a host-side stand-in, not a device
+// address): its device address is taken once per device with hipGetSymbolAddress
+// and kept.  Every call on a device shares that device's array; each call overwrites
+// every byte it reads (k_norm writes the whole noise table, the search kernel a
+// candidate for every trial and time tile), so nothing needs clearing, and calls
+// that overlap on one device race.
+constexpr size_t kNoAllocScratchBytes = (size_t)DEDISP_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static void *g_scratch_ptr[64] = {};
+static std::mutex g_scratch_mu;
+
+static dedisp_status scratch_of_current_device(void **out) {
+  int dev = 0;
+  DD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(DEDISP_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(DEDISP_ERR_DEVICE, "hipGetSymbolAddress(scratch) gave no address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return DEDISP_OK;
+}
+
+dedisp_status run_search_noalloc(dedisp_plan p, const uint8_t *x, int64_t nsamp,
+                                 int64_t in_stride, int64_t nout, const WidthList &wl,
+                                 const double *mu, const double *sigma, double *snr, int32_t *t,
+                                 int32_t *w, hipStream_t s) {
+  if (p->wmode != DEDISP_W_UNIT || wl.w[wl.n - 1] > 32)
+    return fail(DEDISP_ERR_UNSUPPORTED,
+                "the allocation-free search takes unit weights and widths up to 32");
+  // the plan's matrix-core shape: the forced or tuned one, else the default
+  const int k = (p->tile_choice >= 8 && p->tile_choice < 8 + kNumMfmaCfgs) ? p->tile_choice - 8 : 0;
+  int dev = 0;
+  DD_HIP(hipGetDevice(&dev));
+  {
+    // the plan's device tables must exist already: building them would allocate
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!p->uploaded || p->device != dev || !p->mfma || !p->mfma->tried[k])
+      return fail(DEDISP_ERR_INVALID_ARG,
+                  "plan tables are not on this device yet: run dedisp_search (or "
+                  "dedisp_autotune) with this plan once before the allocation-free search");
+    if (!p->mfma->cfg[k].ok)
+      return fail(DEDISP_ERR_UNSUPPORTED, "the plan does not fit the matrix-core search");
+  }
+  const MfmaSearchLayout L = search_layout(p, k, wl.n, nout);
+  if (L.total > kNoAllocScratchBytes)
+    return fail(DEDISP_ERR_INVALID_ARG,
+                "workspace of " + std::to_string(L.total) + " bytes exceeds the " +
+                    std::to_string(kNoAllocScratchBytes) +
+                    "-byte scratch array of the allocation-free search");
+  void *work = nullptr;
+  dedisp_status st = scratch_of_current_device(&work);
+  if (st != DEDISP_OK) return st;
+  st = run_search_mfma(p, k, x, nsamp, in_stride, nout, wl, mu, sigma, snr, t, w, work, s);
+  if (st == DEDISP_OK) p->last_search_tile = 8 + k;
+  return st;
 }
 
 // ---- multi-beam fused search -------------------------------------------------------
