@@ -2,29 +2,31 @@
 //
 // For a group of 4 trials and a channel c, the samples the trials add lie in a short band
 // of delays: trial d takes x[c][t + start[d,c] + k] for k < ntap[d,c].  One
-// v_mfma_i32_16x16x64_i8 product takes 16 rows = 4 trials x 4 output phases u and 16
-// columns = 16 output quads n, so that row (d, u), column n is output t = T + 4 n + u of
-// trial d; its K = 64 are four segments of 16 consecutive samples (of one or several
-// channels), segment g starting at window sample o_g + 4 n for column n.  Then
-//     y[d][T + 4 n + u] += sum_{g, i<16} mask_g[d, u][i] * x[c_g][T + 4 n + o_g + i],
+// v_mfma_i32_32x32x32_i8 product takes 32 rows = 4 trials x 8 output phases u and 32
+// columns = 32 output octets n, so that row (d, u), column n is output t = T + 8 n + u of
+// trial d; its K = 32 are two segments of 16 consecutive samples (of one or two
+// channels), segment g starting at window sample o_g + 8 n for column n.  Then
+//     y[d][T + 8 n + u] += sum_{g, i<16} mask_g[d, u][i] * x[c_g][T + 8 n + o_g + i],
 // where mask_g[d, u][i] = 1 when sample o_g + i - u lies in trial d's run: the 0/1 matrix
 // (which samples each (trial, phase) row takes) is the same for every column and every
-// product of the K block, and the samples a column needs start on a 4-byte boundary.
+// product of the K block, and the samples a column needs start on an 8-byte boundary.
 // The samples enter as int8 x ^ 0x80 = x - 128, and every trial's result is corrected
 // by 128 times its number of samples, so the int32 result is exact.
 //
-// Each channel's window is staged into LDS as 4 copies shifted by 0, 4, 8 and 12 bytes,
-// interleaved by 16-byte chunks (chunk j of copy k at byte 64 j + 16 k of the channel's
-// region), so that the 16 window bytes from any multiple of 4, p, sit 16-byte aligned at
-// region + 4 p: a lane's operand of product q is one aligned 16-byte read at its
-// segment's base + 16 n + 256 q, and no byte shifts are needed.  A wave takes 4 trials x
-// NP products of 64 consecutive outputs; segments are put on a 4-byte grid (their band
-// covers start .. start + ntap + 3 for the phases).  Channel groups are staged while the
-// previous group is multiplied (two LDS buffers).  The host plans, per group of 4
-// segments (a K block), a 144-byte record: the 16-bit mask of every (trial, phase) row
-// and segment, and the LDS base address of each segment; the records of a channel group
-// are copied into LDS with the windows, and every lane forms its 16 mask bytes and its
-// read address from them.
+// Each channel's window is staged into LDS as 2 copies shifted by 0 and 8 bytes,
+// interleaved by 16-byte chunks (chunk j of copy k at byte 32 j + 16 k of the channel's
+// region), so that the 16 window bytes from any multiple of 8, p, sit 16-byte aligned at
+// region + 2 p: a lane's operand of product q is one aligned 16-byte read at its
+// segment's base + 16 n + 512 q, and the 32 lanes of a segment read 512 consecutive
+// bytes (an LDS read of two such halves runs at the full rate whatever their
+// alignment to each other; four quarter-wave runs at different alignments run at about
+// half of it).  A wave takes 4 trials x NP products of 256 consecutive outputs;
+// segments are put on an 8-byte grid (their band covers start .. start + ntap + 7 for
+// the phases).  Channel groups are staged while the previous group is multiplied (two
+// LDS buffers).  The host plans, per pair of segments (a K block), a 144-byte record:
+// the 16-bit mask of every (trial, phase) row and segment, and the LDS base address of
+// each segment; the records of a channel group are copied into LDS with the windows,
+// and every lane forms its 16 mask bytes and its read address from them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,15 +42,15 @@
 
 namespace dd {
 
-// Workgroup shapes: NWD waves along DM (4 trials each), NWT along time (64 NP outputs
+// Workgroup shapes: NWD waves along DM (4 trials each), NWT along time (256 NP outputs
 // each), WG workgroups per CU (each with 1 / WG of the CU's LDS).
 // Every shape keeps 16 waves on a CU (128 registers a lane).
 #define DD_MFMA_CONFIGS(X) \
-  X(0, 16, 1, 16, 1)       \
-  X(1, 8, 1, 16, 2)        \
-  X(2, 8, 2, 8, 1)         \
-  X(3, 4, 2, 8, 2)         \
-  X(4, 8, 1, 8, 2)
+  X(0, 16, 1, 4, 1)        \
+  X(1, 8, 1, 4, 2)         \
+  X(2, 8, 2, 2, 1)         \
+  X(3, 16, 1, 2, 1)        \
+  X(4, 8, 1, 2, 2)
 struct MfmaCfg {
   int nwd, nwt, np, wg;
 };
@@ -56,17 +58,20 @@ struct MfmaCfg {
 static const MfmaCfg kMfmaCfgs[] = {DD_MFMA_CONFIGS(DD_MFMA_ENTRY)};
 #undef DD_MFMA_ENTRY
 constexpr int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
-constexpr int kTrialsPerWave = 4;           // trials of a wave (x 4 output phases = 16 rows)
-constexpr int kCopies = 4;                  // dword-shifted copies of each staged window
+constexpr int kTrialsPerWave = 4;           // trials of a wave (x 8 output phases = 32 rows)
+constexpr int kPhases = 8;                  // output phases (rows per trial)
+constexpr int kOutsPerProduct = 32 * kPhases;
+constexpr int kCopies = 2;                  // 8-byte-shifted copies of each staged window
 constexpr int kMfmaBufBytes = 80 * 1024;    // LDS per staging buffer (two per workgroup) at
                                             // one workgroup per CU
-// K-block record: 64 x u16 masks (lane = 16 segment + row, row = 4 trial + phase), then
-// the LDS byte address of each of the 4 segments' first window byte (region + 4 o_g;
-// lane 16 g + n reads 16 bytes at address[g] + 16 n + 256 q for product q)
+// K-block record: 64 x u16 masks (lane = 32 segment + row, row = 8 trial + phase), then
+// the LDS byte address of each of the 2 segments' first window byte (region + 2 o_g;
+// lane 32 g + n reads 16 bytes at address[g] + 16 n + 512 q for product q), padding
 constexpr int kRecBytes = 144;
-// Staging: one chunk (16 window bytes in all 4 copies) per thread and group, so a
-// group stages at most 64 NW chunks (registers: the chunk's raw bytes are held through
-// the current group's products).
+// Staging: up to kUnitsPerThread chunks (16 window bytes in both copies) per thread and
+// group, so a group stages at most 64 NW kUnitsPerThread chunks (registers: the chunks'
+// raw bytes are held through the current group's products).
+constexpr int kUnitsPerThread = 2;
 
 struct MGroup {
   int32_t unit_begin, nunits;   // staging units (16 window bytes of one channel each)
@@ -166,18 +171,19 @@ __device__ __forceinline__ void load_raw(const uint8_t *row, int64_t nsamp, int6
   }
 }
 
-// One staging task: chunk k of the 4 copies of a window (copy p: window bytes 16 k + 4 p
-// .. 16 k + 4 p + 15, as int8 x ^ 0x80, stored at dst + 16 p), from the raw bytes at the
+// One staging task: chunk k of the 2 copies of a window (copy p: window bytes 16 k + 8 p
+// .. 16 k + 8 p + 15, as int8 x ^ 0x80, stored at dst + 16 p), from the raw bytes at the
 // aligned address at or below window byte 16 k.
 __device__ __forceinline__ void store_chunk(unsigned char *buf, int32_t dst, const uint32_t raw[8],
                                             int sh) {
-  uint32_t e[7];
+  uint32_t e[6];
 #pragma unroll
-  for (int k = 0; k < 7; ++k)
+  for (int k = 0; k < 6; ++k)
     e[k] = __builtin_amdgcn_alignbyte(raw[k + 1], raw[k], (uint32_t)sh) ^ 0x80808080u;
 #pragma unroll
   for (int p = 0; p < kCopies; ++p) {
-    const v4i v = {(int32_t)e[p], (int32_t)e[p + 1], (int32_t)e[p + 2], (int32_t)e[p + 3]};
+    const v4i v = {(int32_t)e[2 * p], (int32_t)e[2 * p + 1], (int32_t)e[2 * p + 2],
+                   (int32_t)e[2 * p + 3]};
     *(v4i *)(buf + dst + 16 * p) = v;
   }
 }
@@ -193,15 +199,18 @@ __device__ __forceinline__ void tile_of_block(int ntw, int ntt, int *tt, int *tw
   *tw = L - *tt * ntw;
 }
 
+typedef int32_t v16i __attribute__((ext_vector_type(16)));
+
 template <int N>
 struct TileAcc {
-  v4i v[N];
+  v16i v[N];
 };
 
-// The products of DM tile tw over outputs T0 .. T0 + NWT * 64 NP - 1.  Wave (wd, wt)
-// takes trials 4 wd .. 4 wd + 3 of the tile and outputs T0 + 64 NP wt + ...; lane l,
-// element e of product q holds trial 4 wd + l / 16 at output 64 NP wt + 64 q + 4 (l mod
-// 16) + e.  Ends with a workgroup barrier, after which the LDS is free.
+// The products of DM tile tw over outputs T0 .. T0 + NWT * 256 NP - 1.  Wave (wd, wt)
+// takes trials 4 wd .. 4 wd + 3 of the tile and outputs T0 + 256 NP wt + ...; lane l,
+// register r of product q holds trial 4 wd + r / 4 at output 256 NP wt + 256 q +
+// 8 (l mod 32) + 4 (l / 32) + r mod 4.  Ends with a workgroup barrier, after which the
+// LDS is free.
 template <int NWD, int NWT, int NP, int WG, typename MA>
 __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, const uint8_t *xb,
                                                  unsigned char *lds) {
@@ -209,9 +218,11 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wd = wave % NWD, wt = wave / NWD;
-  v4i acc[NP];
+  v16i acc[NP];
 #pragma unroll
-  for (int q = 0; q < NP; ++q) acc[q] = (v4i){0, 0, 0, 0};
+  for (int q = 0; q < NP; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[q][r] = 0;
 
   const int gb = ldc(a.group_begin, tw), ge = ldc(a.group_begin, tw + 1);
   // copies the K-block records of group g into LDS (buffer-to-LDS loads, 16 bytes a
@@ -229,29 +240,35 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
                                                  0, 0, 0);
     }
   };
-  // staging: thread t takes chunk t of the group
-  uint32_t raw[8];
-  int sh = 0, dst = 0;
-  bool has = false;
+  // staging: thread t takes chunks t, t + 64 NW, ... of the group
+  uint32_t raw[kUnitsPerThread][8];
+  int sh[kUnitsPerThread] = {}, dst[kUnitsPerThread] = {};
+  bool has[kUnitsPerThread] = {};
   auto fetch = [&](int g) {
     const int ub = ldc(&a.groups[g].unit_begin, 0), nu = ldc(&a.groups[g].nunits, 0);
-    has = tid < nu;
-    if (has) {
-      const MUnit u = a.units[ub + tid];
-      load_raw(xb + (int64_t)u.c * a.in_stride, a.nsamp, T0 + u.src, raw, &sh);
-      dst = u.dst;
+#pragma unroll
+    for (int j = 0; j < kUnitsPerThread; ++j) {
+      const int ui = tid + 64 * NW * j;
+      has[j] = ui < nu;
+      if (has[j]) {
+        const MUnit u = a.units[ub + ui];
+        load_raw(xb + (int64_t)u.c * a.in_stride, a.nsamp, T0 + u.src, raw[j], &sh[j]);
+        dst[j] = u.dst;
+      }
     }
   };
   auto store = [&](unsigned char *buf) {
-    if (has) store_chunk(buf, dst, raw, sh);
+#pragma unroll
+    for (int j = 0; j < kUnitsPerThread; ++j)
+      if (has[j]) store_chunk(buf, dst[j], raw[j], sh[j]);
   };
   stage_recs(gb, lds);
   fetch(gb);
   store(lds);
   __builtin_amdgcn_s_waitcnt(kWaitVm0);
   __syncthreads();
-  // the lane's byte offset from a segment's base: column lane mod 16 of the wave's run
-  const int loff = 16 * (lane & 15) + 4 * 64 * NP * wt;
+  // the lane's byte offset from a segment's base: column lane mod 32 of the wave's run
+  const int loff = 16 * (lane & 31) + 2 * kOutsPerProduct * NP * wt;
   for (int g = gb; g < ge; ++g) {
     const int par = (g - gb) & 1;
     unsigned char *buf = lds + par * a.bufbytes;
@@ -266,18 +283,29 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
     // while its products run, this wave is issued ahead of waves in their staging stores or
     // boxcar stage (of the CU's other workgroup, or of this one)
     __builtin_amdgcn_s_setprio(1);
+    // the next K block's mask and segment base are read while this block's products run
+    uint32_t m_next = 0;
+    int32_t b_next = 0;
+    if (k0 < k1) {
+      m_next = *(const uint16_t *)(rb + 2 * lane);
+      b_next = *(const int32_t *)(rb + 128 + 4 * (lane >> 5));
+    }
     for (int kb = k0; kb < k1; ++kb, rb += kRecBytes) {
-      const uint32_t m16 = *(const uint16_t *)(rb + 2 * lane);
-      const unsigned char *bp = buf + *(const int32_t *)(rb + 128 + 4 * (lane >> 4)) + loff;
-      // 16 mask bytes of lane (row lane % 16, segment lane / 16): bit j -> byte j
+      const uint32_t m16 = m_next;
+      const unsigned char *bp = buf + b_next + loff;
+      if (kb + 1 < k1) {
+        m_next = *(const uint16_t *)(rb + kRecBytes + 2 * lane);
+        b_next = *(const int32_t *)(rb + kRecBytes + 128 + 4 * (lane >> 5));
+      }
+      // 16 mask bytes of lane (row lane % 32, segment lane / 32): bit j -> byte j
       v4i mk;
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         mk[k] = (int32_t)((((m16 >> (4 * k)) & 15u) * 0x204081u) & 0x01010101u);
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        const v4i bq = *(const v4i *)(bp + 256 * q);
-        acc[q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(mk, bq, acc[q], 0, 0, 0);
+        const v4i bq = *(const v4i *)(bp + 2 * kOutsPerProduct * q);
+        acc[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(mk, bq, acc[q], 0, 0, 0);
       }
     }
     __builtin_amdgcn_s_setprio(0);
@@ -291,21 +319,11 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
   return r;
 }
 
-// The accumulators of a wave in two passes of 2 trials each: swapping the upper lanes of
-// products q < NP / 2 with the lower lanes of products q + NP / 2 gives every lane, in
-// pass p, trial 2 p + (l / 16) mod 2 of the wave at outputs 64 (q + (NP / 2) (l / 32)) +
-// 4 (l mod 16) + e (q < NP / 2, element e).
+// The 4 outputs of trial m (of the wave) that lane l holds in product q: registers
+// 4 m .. 4 m + 3, outputs 256 q + 8 (l mod 32) + 4 (l / 32) + 0 .. 3 of the wave's run.
 template <int NP>
-__device__ __forceinline__ void split_passes(const TileAcc<NP> &acc, v4i (&ps)[2][NP / 2]) {
-#pragma unroll
-  for (int q = 0; q < NP / 2; ++q)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const auto p = __builtin_amdgcn_permlane32_swap(acc.v[q][e], acc.v[q + NP / 2][e], false,
-                                                      false);
-      ps[0][q][e] = (int32_t)p[0];
-      ps[1][q][e] = (int32_t)p[1];
-    }
+__device__ __forceinline__ v4i quad_of(const TileAcc<NP> &acc, int q, int m) {
+  return (v4i){acc.v[q][4 * m], acc.v[q][4 * m + 1], acc.v[q][4 * m + 2], acc.v[q][4 * m + 3]};
 }
 
 // WG workgroups per CU (their LDS), so WG NW / 4 waves per SIMD: registers up to 512 /
@@ -315,7 +333,7 @@ __global__ void __launch_bounds__(64 * NWD * NWT)
 __attribute__((amdgpu_waves_per_eu(WG * NWD * NWT / 4, WG * NWD * NWT / 4)))
 k_dedisp_mfma(MfmaArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  constexpr int TWV = 64 * NP, TW = NWT * TWV;
+  constexpr int TWV = kOutsPerProduct * NP, TW = NWT * TWV;
   int tt, tw;
   tile_of_block(a.ntw, a.ntt, &tt, &tw);
   const int bb = blockIdx.y;
@@ -330,16 +348,16 @@ k_dedisp_mfma(MfmaArgs a) {
   constexpr int OROW = TWV + 4;
   static_assert(NWD * NWT * 2 * OROW * 4 <= 2 * (kMfmaBufBytes / WG), "output rows fit the LDS");
   int *R = (int *)lds + wave * 2 * OROW;
-  v4i ps[2][NP / 2];
-  split_passes<NP>(acc, ps);
   int32_t *ob = a.out + (int64_t)bb * a.out_bstride;
   const int64_t t0 = T0 + (int64_t)TWV * wt;
-  const int col = 4 * (lane & 15) + (TWV / 2) * (lane >> 5);
+  const int col = 8 * (lane & 31) + 4 * (lane >> 5);
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
-    int *row = R + ((lane >> 4) & 1) * OROW + col;
 #pragma unroll
-    for (int q = 0; q < NP / 2; ++q) *(v4i *)(row + 64 * q) = ps[pass][q];
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int q = 0; q < NP; ++q)
+        *(v4i *)(R + m * OROW + kOutsPerProduct * q + col) = quad_of<NP>(acc, q, 2 * pass + m);
     // LDS operations of one wave complete in order: the reads below see the writes
     __builtin_amdgcn_wave_barrier();
 #pragma unroll 1
@@ -374,7 +392,7 @@ constexpr int search_step(int sp) { return 64 * sp - ((32 + sp - 1) / sp) * sp; 
 // of TW + 36 ints; each wave searches whole rows.
 template <int NWD, int NWT, int NP, int WG, typename SA>
 __device__ __forceinline__ void search_tile_mfma(SA &sa, int tt, int tw, unsigned char *lds) {
-  constexpr int NW = NWD * NWT, TWV = 64 * NP, TW = NWT * TWV, SP = TW / 64;
+  constexpr int NW = NWD * NWT, TWV = kOutsPerProduct * NP, TW = NWT * TWV, SP = TW / 64;
   constexpr int TT = search_step(SP), YROW = TW + kHalo + 4;
   constexpr int PT = 2;                    // trials of one wave in one pass
   constexpr int ROWS = PT * NWD;           // rows of one pass
@@ -390,18 +408,19 @@ __device__ __forceinline__ void search_tile_mfma(SA &sa, int tt, int tw, unsigne
   const TileAcc<NP> acc = mfma_tile<NWD, NWT, NP, WG>(a, tw, T0, a.x, lds);
   constexpr int DT = kTrialsPerWave * NWD;
   int *Y = (int *)lds;
-  v4i ps[2][NP / 2];
-  split_passes<NP>(acc, ps);
-  const int col = TWV * wt + 4 * (lane & 15) + (TWV / 2) * (lane >> 5);
-  const int k = (lane >> 4) & 1;           // trial of the pass this lane holds
+  const int col = TWV * wt + 8 * (lane & 31) + 4 * (lane >> 5);
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
-    const int d = a.perm[tw * DT + kTrialsPerWave * wd + PT * pass + k];
-    const int32_t corr = d >= 0 ? 128 * a.ntot[d] : 0;
-    int *row = Y + (PT * wd + k) * YROW + col;
 #pragma unroll
-    for (int q = 0; q < NP / 2; ++q)
-      *(v4i *)(row + 64 * q) = ps[pass][q] + (v4i){corr, corr, corr, corr};
+    for (int m = 0; m < PT; ++m) {
+      const int d = a.perm[tw * DT + kTrialsPerWave * wd + PT * pass + m];
+      const int32_t corr = d >= 0 ? 128 * a.ntot[d] : 0;
+      int *row = Y + (PT * wd + m) * YROW + col;
+#pragma unroll
+      for (int q = 0; q < NP; ++q)
+        *(v4i *)(row + kOutsPerProduct * q) =
+            quad_of<NP>(acc, q, PT * pass + m) + (v4i){corr, corr, corr, corr};
+    }
     __syncthreads();
     // one row at a time, not unrolled: the search code then stays small enough
     // for the instruction cache
@@ -475,9 +494,11 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
   const MfmaCfg cf = kMfmaCfgs[ci];
   const int C = p->nchan, D = p->ndm;
   constexpr int TPW = kTrialsPerWave;
-  const int NWD = cf.nwd, NW = cf.nwd * cf.nwt, TW = cf.nwt * 64 * cf.np, DT = TPW * NWD;
+  const int NWD = cf.nwd, NW = cf.nwd * cf.nwt, TW = cf.nwt * kOutsPerProduct * cf.np;
+  const int DT = TPW * NWD;
+  constexpr int SEGS = 2;   // segments per K block
   const int BUF = kMfmaBufBytes / cf.wg;
-  const int maxunits = 64 * NW;
+  const int maxunits = 64 * NW * kUnitsPerThread;
   out = MfmaCfgTables();
   out.tw = TW;
   out.trials = DT;
@@ -497,7 +518,7 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
     out.ntot[d] = (int32_t)s;
   }
   out.group_begin.assign(ntw + 1, 0);
-  // per (wave along DM, channel): first segment (window-relative, a multiple of 4) and count
+  // per (wave along DM, channel): first segment (window-relative, a multiple of 8) and count
   std::vector<int32_t> so(NWD * C), nseg(NWD * C);
   // per channel: window origin (absolute delay of window byte 0) and bytes per copy
   std::vector<int32_t> wlo(C), clen(C);
@@ -513,8 +534,9 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
           const int d = out.perm[(size_t)tw * DT + TPW * w + m];
           if (d < 0 || p->ntap[(size_t)d * C + c] == 0) continue;
           l[w] = std::min(l[w], p->start[(size_t)d * C + c]);
-          // the phase rows u = 1 .. 3 take the run's samples up to 3 later
-          h[w] = std::max(h[w], p->start[(size_t)d * C + c] + p->ntap[(size_t)d * C + c] + 3);
+          // the phase rows u = 1 .. 7 take the run's samples up to 7 later
+          h[w] = std::max(h[w], p->start[(size_t)d * C + c] + p->ntap[(size_t)d * C + c] +
+                                    kPhases - 1);
         }
         slo = std::min(slo, l[w]);
       }
@@ -530,14 +552,14 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
           nseg[w * C + c] = 0;
           continue;
         }
-        const int o = (l[w] - slo) / 4 * 4;   // on the 4-byte grid, at or below the band
+        const int o = (l[w] - slo) / 8 * 8;   // on the 8-byte grid, at or below the band
         so[w * C + c] = o;
         nseg[w * C + c] = (h[w] - (slo + o) + 15) / 16;
         smax = std::max(smax, o + 16 * (nseg[w * C + c] - 1));
       }
-      // the last lane reads 16 bytes from window byte smax + TW - 4: chunks up to that
-      // byte / 16
-      clen[c] = 16 * ((smax + TW - 4) / 16 + 1);
+      // the last lane reads 16 bytes from window byte smax + TW - 8: chunks up to that
+      // byte / 16 (copy 1 of a chunk holds its bytes 8 .. 23)
+      clen[c] = 16 * ((smax + TW - 8) / 16 + 1);
       if ((int64_t)kCopies * clen[c] + kRecBytes > BUF || clen[c] / 16 > maxunits) return false;
     }
     int c = 0;
@@ -549,7 +571,7 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
       int nunits = 0;
       while (c < C && nunits + clen[c] / 16 <= maxunits) {
         int nrec = 0;   // K-block records with channel c added
-        for (int w = 0; w < NWD; ++w) nrec += (segw[w] + nseg[w * C + c] + 3) / 4;
+        for (int w = 0; w < NWD; ++w) nrec += (segw[w] + nseg[w * C + c] + SEGS - 1) / SEGS;
         if ((int64_t)used + (int64_t)kCopies * clen[c] + (int64_t)nrec * kRecBytes > BUF) break;
         for (int w = 0; w < NWD; ++w) segw[w] += nseg[w * C + c];
         used += kCopies * clen[c];
@@ -565,7 +587,7 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
         if (!clen[cc]) continue;
         region[cc] = off;
         for (int k = 0; k < clen[cc] / 16; ++k)
-          out.units.push_back(MUnit{cc, wlo[cc] + 16 * k, off + 64 * k, 0});
+          out.units.push_back(MUnit{cc, wlo[cc] + 16 * k, off + 16 * kCopies * k, 0});
         off += kCopies * clen[cc];
       }
       gi.nunits = (int)out.units.size() - gi.unit_begin;
@@ -575,18 +597,18 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
       for (int w = 0; w < NWD; ++w) {
         out.kbr.push_back((int32_t)(out.recs.size() / kRecBytes));
         // segments of this wave's trials in the group (channel, window-relative start),
-        // four per K block
+        // two per K block
         std::vector<std::pair<int, int>> segs;
         for (int cc = cbeg; cc < c; ++cc)
           for (int sg = 0; sg < nseg[w * C + cc]; ++sg) segs.push_back({cc, so[w * C + cc] + 16 * sg});
-        for (size_t s0 = 0; s0 < segs.size(); s0 += 4) {
+        for (size_t s0 = 0; s0 < segs.size(); s0 += SEGS) {
           std::vector<uint8_t> rec(kRecBytes, 0);
-          for (int g = 0; g < 4; ++g) {
+          for (int g = 0; g < SEGS; ++g) {
             // padding segments: zero masks, a valid address
             const size_t si = s0 + g < segs.size() ? s0 + g : s0;
             const int cc = segs[si].first, o = segs[si].second;
-            // window byte o (a multiple of 4) of the interleaved copies is at region + 4 o
-            const int32_t ad = region[cc] + 4 * o;
+            // window byte o (a multiple of 8) of the interleaved copies is at region + 2 o
+            const int32_t ad = region[cc] + 2 * o;
             std::memcpy(rec.data() + 128 + 4 * g, &ad, 4);
             if (s0 + g >= segs.size()) continue;
             const int oa = wlo[cc] + o;   // absolute delay of the segment's first byte
@@ -594,12 +616,12 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
               const int d = out.perm[(size_t)tw * DT + TPW * w + m];
               if (d < 0) continue;
               const int st = p->start[(size_t)d * C + cc], nt = p->ntap[(size_t)d * C + cc];
-              for (int u = 0; u < 4; ++u) {
+              for (int u = 0; u < kPhases; ++u) {
                 // row (trial m, phase u) takes byte j when its delay less u is in the run
                 uint16_t bits = 0;
                 for (int j = 0; j < 16; ++j)
                   if (oa + j - u >= st && oa + j - u < st + nt) bits |= (uint16_t)(1u << j);
-                std::memcpy(rec.data() + 2 * (16 * g + 4 * m + u), &bits, 2);
+                std::memcpy(rec.data() + 2 * (32 * g + kPhases * m + u), &bits, 2);
               }
             }
           }
@@ -735,7 +757,7 @@ struct MfmaSearchLayout {
 
 static MfmaSearchLayout search_layout(const dedisp_plan_s *p, int k, int32_t nw, int64_t nout) {
   const MfmaCfg cf = kMfmaCfgs[k];
-  const int tw = cf.nwt * 64 * cf.np, tstep = search_step(tw / 64);
+  const int tw = cf.nwt * kOutsPerProduct * cf.np, tstep = search_step(tw / 64);
   MfmaSearchLayout L;
   L.ntt = (nout + tstep - 1) / tstep;
   L.off_part = (2 * sizeof(double) * (size_t)p->ndm * nw + 255) & ~(size_t)255;
