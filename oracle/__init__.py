@@ -36,8 +36,20 @@ KDM_PAPER = 1.0 / (KAPPA * 1e18)          # s GHz^2 cm^3 / pc  (= 4.149378e-3)
 KDM_415 = 4.15e-3                          # the rounded constant, also supported
 
 
-def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so with gcc (no FMA contraction)."""
+_SAN_LIB_PATH = os.path.join(_HERE, "liboracle_san.so")
+
+
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with gcc (no FMA contraction); with sanitize,
+    into liboracle_san.so with clang's AddressSanitizer and UndefinedBehaviorSanitizer
+    (for runs that preload that runtime)."""
+    if sanitize:
+        clang = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "llvm", "bin", "clang")
+        subprocess.check_call([clang, "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off",
+                               "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                               "-shared-libsan", "-fPIC", "-shared", "-o", _SAN_LIB_PATH, _SRC,
+                               "-lm"])
+        return _SAN_LIB_PATH
     if force or not os.path.exists(_LIB_PATH):
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
                                "-o", _LIB_PATH, _SRC, "-lm"])
@@ -50,9 +62,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build(force=True)
-        L = ctypes.CDLL(_LIB_PATH)
+        path = os.environ.get("ORACLE_LIB")   # another build of oracle.c (the sanitized one)
+        if not path:
+            if not os.path.exists(_LIB_PATH):
+                build(force=True)
+            path = _LIB_PATH
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i32, i64, ci = ctypes.c_int32, ctypes.c_int64, ctypes.c_int
         L.oracle_dedisperse_u8.argtypes = [i32, i64, P, i64, i32, P, P, i64, P, i64]

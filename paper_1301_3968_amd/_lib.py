@@ -5,7 +5,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdedisp.so")
+# DEDISP_LIB may name another build of the same library (the host-sanitized one)
+LIB_PATH = os.environ.get("DEDISP_LIB") or os.path.join(_HERE, "libdedisp.so")
 
 OK, ERR_INVALID_ARG, ERR_SHAPE, ERR_OVERFLOW, ERR_OOM, ERR_DEVICE, ERR_UNSUPPORTED = range(7)
 U8, F32, I32 = 0, 1, 2

@@ -27,9 +27,20 @@ COMMON = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer (device code is left as it is);
+# the library then needs the sanitizer runtime preloaded into the process.
+SANITIZE_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+SAN_LIB = os.path.join(HERE, "libdedisp_san.so")
+
+
+def build(verbose: bool = False, jobs: int = 8, sanitize: bool = False) -> str:
+    """Compile every source and link the library; with sanitize, a host-sanitized copy
+    (libdedisp_san.so, for host-side checks on a machine without a GPU)."""
     hipcc = os.path.join(ROCM, "bin", "hipcc")
-    objdir = os.path.join(HERE, "_build")
+    objdir = os.path.join(HERE, "_build_san" if sanitize else "_build")
+    lib_path = SAN_LIB if sanitize else LIB
+    extra = SANITIZE_HOST if sanitize else []
     os.makedirs(objdir, exist_ok=True)
     procs = []
     objs = []
@@ -40,7 +51,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         obj = os.path.join(objdir, src + ".o")
         objs.append(obj)
         lang = ["-x", "hip"]
-        cmd = [hipcc] + lang + COMMON + ["-c", path, "-o", obj]
+        cmd = [hipcc] + lang + COMMON + extra + ["-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -48,16 +59,18 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
             _wait(procs)
             procs = []
     _wait(procs)
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + [
-        "-Wl,--no-undefined", "-L", os.path.join(ROCM, "lib"), "-lamdhip64"]
+    tmp = lib_path + ".tmp"
+    link = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-shared-libsan"] if sanitize else ["-Wl,--no-undefined"]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + link + [
+        "-L", os.path.join(ROCM, "lib"), "-lamdhip64"]
     if verbose:
         print(" ".join(cmd), flush=True)
     out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if out.returncode != 0:
         raise RuntimeError("link failed:\n" + out.stdout)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 def _wait(procs):
@@ -74,4 +87,4 @@ def _wait(procs):
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))

@@ -37,7 +37,7 @@ hipError_t ArgStage::copy(void *d_dst, const void *src, size_t n, hipStream_t s)
     if (host) (void)hipHostFree(host);
     host = nullptr;
     cap = 0;
-    hipError_t e = hipHostMalloc(&host, n, hipHostMallocDefault);
+    hipError_t e = alloc_fails() ? hipErrorOutOfMemory : hipHostMalloc(&host, n, hipHostMallocDefault);
     if (e != hipSuccess) return e;
     cap = n;
   }
@@ -113,7 +113,7 @@ static dedisp_status run_dedisperse(dedisp_plan p, const void *in, int32_t in_dt
       return fail(DEDISP_ERR_OVERFLOW, "block too long for the int32 prefix");
     const int64_t pstride = nsamp + 1;
     int32_t *P = nullptr;
-    DD_HIP(hipMallocAsync((void **)&P, sizeof(int32_t) * (size_t)pstride * p->nchan * nbatch, s));
+    DD_HIP(dev_malloc_async((void **)&P, sizeof(int32_t) * (size_t)pstride * p->nchan * nbatch, s));
     hipError_t e = launch_prefix_u8((const uint8_t *)in, in_stride, in_bstride, p->nchan, nbatch,
                                     nsamp, P, s);
     if (e == hipSuccess && kt) e = kt->begin();
@@ -130,7 +130,7 @@ static dedisp_status run_dedisperse(dedisp_plan p, const void *in, int32_t in_dt
     if (p->wmode == DEDISP_W_TAP) {
       const int64_t nz = nsamp - p->ktaps + 1;
       float *z = nullptr;
-      DD_HIP(hipMallocAsync((void **)&z, sizeof(float) * (size_t)nz * p->nchan * nbatch, s));
+      DD_HIP(dev_malloc_async((void **)&z, sizeof(float) * (size_t)nz * p->nchan * nbatch, s));
       hipError_t e = launch_fir_f32(p, (const float *)in, in_stride, in_bstride, nbatch, nz, z, s);
       if (e == hipSuccess)
         e = launch_dedisp_1tap_f32(p, z, nz, nz * p->nchan, nbatch, nout, (float *)out, out_stride,
@@ -146,6 +146,24 @@ static dedisp_status run_dedisperse(dedisp_plan p, const void *in, int32_t in_dt
   }
   return fail(DEDISP_ERR_UNSUPPORTED, "unsupported input / weight / output combination");
 }
+
+// Predicted int32 overflow of exact uint8 sums (checked before any device work): a
+// trial's output is at most 255 sum_c max_d ntap[d,c], and the search adds up to
+// `span` consecutive outputs in int32 (window sums from a running prefix over a lane's
+// starts and the widths' halo).
+static dedisp_status check_int32_sums(const dedisp_plan_s *p, int32_t in_dtype, int32_t out_dtype,
+                                      int64_t span) {
+  if (in_dtype != DEDISP_U8 || p->wmode != DEDISP_W_UNIT || out_dtype != DEDISP_I32)
+    return DEDISP_OK;
+  if (255.0 * (double)p->sum_max_ntap * (double)span >= 2147483647.0)
+    return fail(DEDISP_ERR_OVERFLOW, span == 1 ? "int32 dedispersion sum could overflow"
+                                               : "int32 boxcar window sum could overflow");
+  return DEDISP_OK;
+}
+
+// Outputs the fused search adds in int32 at most: a lane's starts and the halo of
+// the widths (at most 64).
+constexpr int64_t kSearchSpan = 64;
 
 static dedisp_status check_block(dedisp_plan p, const void *in, int32_t in_dtype, int64_t nsamp,
                                  int64_t in_stride, int64_t *nout) {
@@ -178,6 +196,7 @@ dedisp_status dedisp_dedisperse(dedisp_plan p, const void *d_in, int32_t in_dtyp
     return fail(DEDISP_ERR_INVALID_ARG, "bad output stride");
   if (out_dtype != DEDISP_I32 && out_dtype != DEDISP_F32)
     return fail(DEDISP_ERR_INVALID_ARG, "output dtype must be I32 or F32");
+  if ((st = dd::check_int32_sums(p, in_dtype, out_dtype, 1)) != DEDISP_OK) return st;
   if ((st = dd::ensure_device(p)) != DEDISP_OK) return st;
   dd::WeightOverride wo(d_weights);
   return dd::run_dedisperse(p, d_in, in_dtype, nsamp, in_stride, in_bstride, nbatch, d_out,
@@ -230,6 +249,8 @@ dedisp_status dedisp_search(dedisp_plan p, const void *d_in, int32_t in_dtype, i
   size_t need = 0;
   if ((st = dedisp_work_bytes(p, nsamp, nw, &need)) != DEDISP_OK) return st;
   if (work_bytes < need) return fail(DEDISP_ERR_INVALID_ARG, "workspace too small");
+  if ((st = dd::check_int32_sums(p, in_dtype, DEDISP_I32, dd::kSearchSpan)) != DEDISP_OK)
+    return st;
   if ((st = dd::ensure_device(p)) != DEDISP_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   if (in_dtype == DEDISP_U8 && p->tile_choice != -2 && dd::search_supported(p, wl)) {
@@ -241,7 +262,7 @@ dedisp_status dedisp_search(dedisp_plan p, const void *d_in, int32_t in_dtype, i
   // General path: materialise y in a stream-ordered temporary, then detect.
   const int32_t ydt = (in_dtype == DEDISP_U8 && p->wmode == DEDISP_W_UNIT) ? DEDISP_I32 : DEDISP_F32;
   void *y = nullptr;
-  DD_HIP(hipMallocAsync(&y, 4 * (size_t)nout * p->ndm, s));
+  DD_HIP(dd::dev_malloc_async((void **)&y, 4 * (size_t)nout * p->ndm, s));
   dd::KernelTimer kt(p, s);
   st = dd::run_dedisperse(p, d_in, in_dtype, nsamp, in_stride, 0, 1, y, ydt, nout, 0, nout, s, &kt);
   if (st == DEDISP_OK)
@@ -266,6 +287,8 @@ dedisp_status dedisp_search_noalloc(dedisp_plan p, const void *d_in, int32_t in_
     return fail(DEDISP_ERR_INVALID_ARG, "null argument");
   dd::WidthList wl;
   if ((st = dd::make_widths(widths, nw, nout, &wl)) != DEDISP_OK) return st;
+  if ((st = dd::check_int32_sums(p, in_dtype, DEDISP_I32, dd::kSearchSpan)) != DEDISP_OK)
+    return st;
   return dd::run_search_noalloc(p, (const uint8_t *)d_in, nsamp, in_stride, nout, wl, d_chan_mean,
                                 d_chan_sigma, d_snr, d_t, d_w, (hipStream_t)stream);
 }
@@ -293,7 +316,7 @@ dedisp_status dedisp_dedisperse_backward(dedisp_plan p, const float *d_grad_y, i
     // it cancels heavily); then the FIR transposes.
     const int64_t nz = nsamp - p->ktaps + 1;
     double *z = nullptr;
-    DD_HIP(hipMallocAsync((void **)&z, sizeof(double) * (size_t)nz * p->nchan * nbatch, s));
+    DD_HIP(dd::dev_malloc_async((void **)&z, sizeof(double) * (size_t)nz * p->nchan * nbatch, s));
     hipError_t e = hipSuccess;
     st = p->tile_choice == -2 ? DEDISP_ERR_UNSUPPORTED
                               : dd::run_adjoint_z_tiled(p, d_grad_y, nout, gy_stride, gy_bstride,

@@ -17,6 +17,14 @@ void set_error(const std::string &msg);
 dedisp_status fail(dedisp_status s, const std::string &msg);
 dedisp_status hip_fail(hipError_t e, const char *what);
 
+// Test hook: when the environment variable DEDISP_TEST_FAIL_ALLOC holds k >= 1, the
+// k-th allocation attempt counted from the moment the variable took that value fails
+// (every host or device allocation the library makes goes through this check first).
+bool alloc_fails();
+// hipMalloc and hipMallocAsync behind the test hook.
+hipError_t dev_malloc(void **p, size_t bytes);
+hipError_t dev_malloc_async(void **p, size_t bytes, hipStream_t s);
+
 #define DD_HIP(call)                                            \
   do {                                                          \
     hipError_t e_ = (call);                                     \

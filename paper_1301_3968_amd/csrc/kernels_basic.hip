@@ -761,7 +761,7 @@ hipError_t launch_grad_w_tap(const dedisp_plan_s *p, const double *z, int64_t nz
     return hipErrorInvalidValue;
   double *part = nullptr;
   hipError_t e =
-      hipMallocAsync((void **)&part, sizeof(double) * (size_t)p->nchan * nparts * K, s);
+      dev_malloc_async((void **)&part, sizeof(double) * (size_t)p->nchan * nparts * K, s);
   if (e != hipSuccess) return e;
   const dim3 g((unsigned)(nsplit * nslice), (unsigned)p->nchan, (unsigned)nbatch);
 #define DD_GW_LAUNCH(XT, KB)                                                     \

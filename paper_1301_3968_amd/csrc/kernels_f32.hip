@@ -328,7 +328,7 @@ k_dedisp_f32(F32Args a) {
 template <typename T>
 static hipError_t upload(T **dst, const std::vector<T> &v) {
   if (v.empty()) return hipSuccess;
-  hipError_t e = hipMalloc((void **)dst, sizeof(T) * v.size());
+  hipError_t e = dev_malloc((void **)dst, sizeof(T) * v.size());
   if (e != hipSuccess) return e;
   return hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
 }
@@ -540,7 +540,7 @@ static dedisp_status run_gather_f32(const F32Tables &T, const F32CfgTables &cfg,
   if (ntt * (int64_t)cfg.ntd > INT32_MAX / 2) return DEDISP_ERR_UNSUPPORTED;
   const int64_t tpad = (seg + halo + 3) & ~(int64_t)3;
   float *Rrows = nullptr;
-  DD_HIP(hipMallocAsync((void **)&Rrows, sizeof(float) * (size_t)T.nrows * tpad * nbatch, s));
+  DD_HIP(dev_malloc_async((void **)&Rrows, sizeof(float) * (size_t)T.nrows * tpad * nbatch, s));
   hipError_t e = hipSuccess;
   for (int64_t o0 = 0; o0 < nout && e == hipSuccess; o0 += seg) {
     const int64_t nseg = std::min(seg, nout - o0);

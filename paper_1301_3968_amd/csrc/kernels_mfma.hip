@@ -483,7 +483,7 @@ k_search_mfma_batch(const MfmaSearchArgs *__restrict__ beams, const int32_t *__r
 template <typename T>
 static hipError_t upload(T **dst, const std::vector<T> &v) {
   if (v.empty()) return hipSuccess;
-  hipError_t e = hipMalloc((void **)dst, sizeof(T) * v.size());
+  hipError_t e = dev_malloc((void **)dst, sizeof(T) * v.size());
   if (e != hipSuccess) return e;
   return hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
 }
@@ -982,7 +982,7 @@ dedisp_status mfma_batch_create(const std::vector<dedisp_plan> &plans,
   B->work_bytes = off + sizeof(MfmaSearchArgs) * B->nbeam;
   hipError_t e = upload(&B->d_base, B->base);
   if (e == hipSuccess)
-    e = hipMalloc((void **)&B->d_args_graph, sizeof(MfmaSearchArgs) * B->nbeam);
+    e = dev_malloc((void **)&B->d_args_graph, sizeof(MfmaSearchArgs) * B->nbeam);
   if (e != hipSuccess) {
     mfma_batch_free(B);
     return hip_fail(e, "batch setup");

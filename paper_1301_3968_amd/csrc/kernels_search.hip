@@ -585,7 +585,7 @@ static bool build_cfg_budget(const dedisp_plan_s *p, const TiledTables &T, int c
 
 template <typename T>
 static hipError_t upload(T **dst, const std::vector<T> &v) {
-  hipError_t e = hipMalloc((void **)dst, std::max<size_t>(1, v.size()) * sizeof(T));
+  hipError_t e = dev_malloc((void **)dst, std::max<size_t>(1, v.size()) * sizeof(T));
   if (e != hipSuccess) return e;
   if (v.empty()) return hipSuccess;
   return hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
@@ -1102,7 +1102,7 @@ dedisp_status dedisp_batch_create(dedisp_batch *out, int32_t nbeam, const dedisp
   B->work_bytes = B->args_off + sizeof(SearchArgs) * nbeam;
   if (st == DEDISP_OK) {
     hipError_t e = upload(&B->d_tile_begin, B->tile_begin);
-    if (e == hipSuccess) e = hipMalloc((void **)&B->d_args_graph, sizeof(SearchArgs) * nbeam);
+    if (e == hipSuccess) e = dev_malloc((void **)&B->d_args_graph, sizeof(SearchArgs) * nbeam);
     if (e != hipSuccess) st = hip_fail(e, "batch setup");
   }
   if (st != DEDISP_OK) {
@@ -1312,9 +1312,9 @@ extern "C" dedisp_status dedisp_autotune(dedisp_plan p, const void *d_in, int64_
       if (e1) (void)hipEventDestroy(e1);
     }
   } sc;
-  DD_HIP(hipMalloc((void **)&sc.snr, sizeof(double) * p->ndm));
-  DD_HIP(hipMalloc((void **)&sc.tt, sizeof(int32_t) * p->ndm));
-  DD_HIP(hipMalloc((void **)&sc.ww, sizeof(int32_t) * p->ndm));
+  DD_HIP(dev_malloc((void **)&sc.snr, sizeof(double) * p->ndm));
+  DD_HIP(dev_malloc((void **)&sc.tt, sizeof(int32_t) * p->ndm));
+  DD_HIP(dev_malloc((void **)&sc.ww, sizeof(int32_t) * p->ndm));
   DD_HIP(hipEventCreate(&sc.e0));
   DD_HIP(hipEventCreate(&sc.e1));
   double *snr = sc.snr;

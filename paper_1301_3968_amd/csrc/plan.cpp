@@ -14,6 +14,7 @@
 #include <string>
 #include <tuple>
 
+#include <mutex>
 #include "internal.h"
 
 namespace dd {
@@ -260,6 +261,34 @@ static dedisp_status build_tables(dedisp_plan p) {
   return DEDISP_OK;
 }
 
+bool alloc_fails() {
+  static std::mutex mu;
+  static std::string last;
+  static long count = 0;
+  const char *v = getenv("DEDISP_TEST_FAIL_ALLOC");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!v || !*v) {
+    last.clear();
+    count = 0;
+    return false;
+  }
+  if (last != v) {
+    last = v;
+    count = 0;
+  }
+  return ++count == strtol(v, nullptr, 10);
+}
+
+hipError_t dev_malloc(void **p, size_t bytes) {
+  if (alloc_fails()) return hipErrorOutOfMemory;
+  return hipMalloc(p, bytes);
+}
+
+hipError_t dev_malloc_async(void **p, size_t bytes, hipStream_t s) {
+  if (alloc_fails()) return hipErrorOutOfMemory;
+  return hipMallocAsync(p, bytes, s);
+}
+
 dedisp_status ensure_device(dedisp_plan p) {
   std::lock_guard<std::mutex> lk(p->mu);
   int dev = 0;
@@ -269,12 +298,12 @@ dedisp_status ensure_device(dedisp_plan p) {
     return DEDISP_OK;
   }
   const size_t n = (size_t)p->ndm * p->nchan;
-  DD_HIP(hipMalloc(&p->dev.start, n * sizeof(int32_t)));
-  DD_HIP(hipMalloc(&p->dev.ntap, n * sizeof(int32_t)));
+  DD_HIP(dev_malloc((void **)&p->dev.start, n * sizeof(int32_t)));
+  DD_HIP(dev_malloc((void **)&p->dev.ntap, n * sizeof(int32_t)));
   DD_HIP(hipMemcpy(p->dev.start, p->start.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
   DD_HIP(hipMemcpy(p->dev.ntap, p->ntap.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
   if (!p->weights.empty()) {
-    DD_HIP(hipMalloc(&p->dev.weights, p->weights.size() * sizeof(float)));
+    DD_HIP(dev_malloc((void **)&p->dev.weights, p->weights.size() * sizeof(float)));
     DD_HIP(hipMemcpy(p->dev.weights, p->weights.data(), p->weights.size() * sizeof(float),
                      hipMemcpyHostToDevice));
   }
@@ -328,9 +357,10 @@ dedisp_status dedisp_plan_create(dedisp_plan *out, int32_t nchan, const double *
       pr.scatter_s_1ghz < 0 || !std::isfinite(pr.scatter_index) || !std::isfinite(pr.spectral_index))
     return fail(DEDISP_ERR_INVALID_ARG, "bad pulse-model parameters");
 
-  dedisp_plan p = new (std::nothrow) dedisp_plan_s;
+  dedisp_plan p = dd::alloc_fails() ? nullptr : new (std::nothrow) dedisp_plan_s;
   if (!p) return fail(DEDISP_ERR_OOM, "host allocation failed");
   try {
+    if (dd::alloc_fails()) throw std::bad_alloc();   // the tables' storage
     p->nchan = nchan;
     p->ndm = ndm;
     p->chan_bw = chan_bw_ghz;

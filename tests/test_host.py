@@ -142,3 +142,64 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU only" in r.stderr and r.stdout == ""
+
+
+def _raw_call(dd, fn, *args):
+    """Call a C-ABI entry point directly; returns (status, last error text)."""
+    from paper_1301_3968_amd import _lib
+    st = getattr(_lib.lib(), fn)(*args)
+    return st, _lib.lib().dedisp_last_error().decode()
+
+
+def test_overflow_predicted_before_device_work(dd):
+    from paper_1301_3968_amd import _lib
+    # 1000 channels of 9000-sample runs: 255 x 9e6 > 2^31 for one output
+    C, D, n = 1000, 2, 9000
+    f = workloads.channel_centres(1.2, 0.3, C)
+    start = np.zeros((D, C), np.int32)
+    ntap = np.full((D, C), n, np.int32)
+    p = dd.Plan(f, 0.3 / C, 1e-3, [0.0, 1.0], rule="explicit", start=start, ntap=ntap)
+    fake = ctypes.c_void_p(0x1000)     # never dereferenced: the check precedes device work
+    T = n + 10
+    st, msg = _raw_call(dd, "dedisp_dedisperse", p.handle, fake, _lib.U8, T, T, 0, 1, fake,
+                        _lib.I32, 11, 0, None, None)
+    assert st == _lib.ERR_OVERFLOW and "overflow" in msg
+    # the same plan's fp32 output cannot overflow: the check lets it through (and the call
+    # then needs a device, which this host may not have)
+    # a plan whose single outputs fit but whose boxcar windows (64 outputs) would not
+    ntap2 = np.full((D, C), 200, np.int32)    # 255 x 2e5 = 5.1e7 per output, x 64 > 2^31
+    p2 = dd.Plan(f, 0.3 / C, 1e-3, [0.0, 1.0], rule="explicit", start=start, ntap=ntap2)
+    w = np.arange(1, 33, dtype=np.int32)
+    mu = np.full(C, 128.0)
+    T2 = 5000
+    wb = p2.work_bytes(T2, 32)
+    st, msg = _raw_call(dd, "dedisp_search", p2.handle, fake, _lib.U8, T2, T2,
+                        w.ctypes.data_as(ctypes.c_void_p), 32, fake, fake, fake, fake, fake,
+                        fake, ctypes.c_size_t(wb), None)
+    assert st == _lib.ERR_OVERFLOW and "window" in msg
+    st, msg = _raw_call(dd, "dedisp_search_noalloc", p2.handle, fake, _lib.U8, T2, T2,
+                        w.ctypes.data_as(ctypes.c_void_p), 32, fake, fake, fake, fake, fake, None)
+    assert st == _lib.ERR_OVERFLOW
+    # a delay beyond int32 samples is refused when the plan is made
+    with pytest.raises(dd.DedispError) as e:
+        dd.Plan(f, 0.3 / C, 1e-9, [1e6], rule="smear")
+    assert e.value.status == _lib.ERR_OVERFLOW
+
+
+def test_forced_allocation_failure(dd, monkeypatch):
+    from paper_1301_3968_amd import _lib
+    f = workloads.channel_centres(1.2, 0.3, 64)
+    dms = np.arange(32) * 10.0
+    # the first allocation (the plan), then the second (its tables), fail with OOM
+    for k in ("1", "2"):
+        monkeypatch.setenv("DEDISP_TEST_FAIL_ALLOC", k)
+        with pytest.raises(dd.DedispError) as e:
+            dd.Plan(f, 0.3 / 64, 1e-3, dms, rule="smear")
+        assert e.value.status == _lib.ERR_OOM and "allocation" in str(e.value)
+    # a count past the allocations a plan needs: the plan is made
+    monkeypatch.setenv("DEDISP_TEST_FAIL_ALLOC", "3")
+    p = dd.Plan(f, 0.3 / 64, 1e-3, dms, rule="smear")
+    assert p.ndm == 32
+    monkeypatch.delenv("DEDISP_TEST_FAIL_ALLOC")
+    p2 = dd.Plan(f, 0.3 / 64, 1e-3, dms, rule="smear")
+    assert np.array_equal(p.tables()[1], p2.tables()[1])
