@@ -230,7 +230,10 @@ dedisp_status dedisp_trial_dms(double dm0, double dm_max, double eps, int32_t nc
                                double *out, int32_t *n_out);
 
 /* Batched search over many beams, each with its own plan (own DM grid) and
- * block length, as one launch over every beam's tiles.  plans[nbeam] must share nchan and
+ * block length (Section 5.3 grids per beam), as one launch over every beam's tiles: on
+ * the matrix cores a persistent launch whose workgroups claim (beam, tile) work items
+ * from a device counter (the environment variable DEDISP_BATCH_LAUNCH=grid, read at
+ * create, selects one workgroup per tile instead).  plans[nbeam] must share nchan and
  * use UNIT weights with uint8 input.  widths host [nw]. */
 dedisp_status dedisp_batch_create(dedisp_batch *out, int32_t nbeam, const dedisp_plan *plans,
                                   const int64_t *nsamp, const int32_t *widths, int32_t nw);

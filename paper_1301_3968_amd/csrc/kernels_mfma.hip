@@ -64,6 +64,8 @@ constexpr int kOutsPerProduct = 32 * kPhases;
 constexpr int kCopies = 2;                  // 8-byte-shifted copies of each staged window
 constexpr int kMfmaBufBytes = 80 * 1024;    // LDS per staging buffer (two per workgroup) at
                                             // one workgroup per CU
+constexpr int kSlotBytes = 16;              // the end of the second buffer, never staged into:
+                                            // the persistent batch's item broadcast
 // K-block record: 64 x u16 masks (lane = 32 segment + row, row = 8 trial + phase), then
 // the LDS byte address of each of the 2 segments' first window byte (region + 2 o_g;
 // lane 32 g + n reads 16 bytes at address[g] + 16 n + 512 q for product q), padding
@@ -398,7 +400,8 @@ __device__ __forceinline__ void search_tile_mfma(SA &sa, int tt, int tw, unsigne
   constexpr int ROWS = PT * NWD;           // rows of one pass
   static_assert(TW % 64 == 0 && TT % SP == 0 && TW - TT >= 31, "search tile");
   static_assert(ROWS % NW == 0, "whole rows per wave");
-  static_assert(ROWS * YROW * 4 <= 2 * (kMfmaBufBytes / WG), "rows of one pass fit the LDS");
+  static_assert(ROWS * YROW * 4 <= 2 * (kMfmaBufBytes / WG) - kSlotBytes,
+                "rows of one pass fit the LDS (less the item slot)");
   static_assert(YROW % 4 == 0, "16-byte aligned rows");
   auto &a = sa.m;
   const int lane = threadIdx.x & 63;
@@ -476,6 +479,36 @@ k_search_mfma_batch(const MfmaSearchArgs *__restrict__ beams, const int32_t *__r
   const int tt = L / sa.m.ntw, tw = L - tt * sa.m.ntw;
   search_tile_mfma<NWD, NWT, NP, WG>(sa, tt, tw, lds);
 }
+
+// Persistent multi-beam search: a grid that fills the GPU once; each workgroup claims
+// work items (beam, tile) from a device counter until the list is exhausted.  Thread 0
+// claims an item and passes it to the workgroup through the LDS slot at the end of the
+// second staging buffer (never staged into); the exit is uniform over the workgroup, so
+// every wave reaches it.  The counter is zeroed by k_reset_counter before the launch.
+template <int NWD, int NWT, int NP, int WG>
+__global__ void __launch_bounds__(64 * NWD * NWT)
+__attribute__((amdgpu_waves_per_eu(WG * NWD * NWT / 4, WG * NWD * NWT / 4)))
+k_search_mfma_persist(const MfmaSearchArgs *__restrict__ beams, const int2 *__restrict__ items,
+                      int32_t nitems, int32_t *__restrict__ counter) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  int32_t *slot = (int32_t *)(lds + 2 * (kMfmaBufBytes / WG) - kSlotBytes);
+  typedef const __attribute__((address_space(4))) MfmaSearchArgs CArgs;
+  for (;;) {
+    if (threadIdx.x == 0)
+      *slot = __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(*slot);
+    if (it >= nitems) return;   // the same for every thread of the workgroup
+    const int2 w = items[it];
+    const int b = __builtin_amdgcn_readfirstlane(w.x), L = __builtin_amdgcn_readfirstlane(w.y);
+    CArgs &sa = ((CArgs *)beams)[b];
+    const int tt = L / sa.m.ntw, tw = L - tt * sa.m.ntw;
+    // the tile ends with a workgroup barrier, after which thread 0 may claim the next item
+    search_tile_mfma<NWD, NWT, NP, WG>(sa, tt, tw, lds);
+  }
+}
+
+__global__ void k_reset_counter(int32_t *counter) { *counter = 0; }
 
 }  // namespace
 
@@ -560,7 +593,8 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
       // the last lane reads 16 bytes from window byte smax + TW - 8: chunks up to that
       // byte / 16 (copy 1 of a chunk holds its bytes 8 .. 23)
       clen[c] = 16 * ((smax + TW - 8) / 16 + 1);
-      if ((int64_t)kCopies * clen[c] + kRecBytes > BUF || clen[c] / 16 > maxunits) return false;
+      if ((int64_t)kCopies * clen[c] + kRecBytes > BUF - kSlotBytes || clen[c] / 16 > maxunits)
+        return false;
     }
     int c = 0;
     while (c < C) {
@@ -572,7 +606,9 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
       while (c < C && nunits + clen[c] / 16 <= maxunits) {
         int nrec = 0;   // K-block records with channel c added
         for (int w = 0; w < NWD; ++w) nrec += (segw[w] + nseg[w * C + c] + SEGS - 1) / SEGS;
-        if ((int64_t)used + (int64_t)kCopies * clen[c] + (int64_t)nrec * kRecBytes > BUF) break;
+        if ((int64_t)used + (int64_t)kCopies * clen[c] + (int64_t)nrec * kRecBytes >
+            BUF - kSlotBytes)
+          break;
         for (int w = 0; w < NWD; ++w) segw[w] += nseg[w * C + c];
         used += kCopies * clen[c];
         nunits += clen[c] / 16;
@@ -910,6 +946,11 @@ struct MfmaBatch {
   MfmaSearchArgs *d_args_graph = nullptr;   // argument table of the captured graph
   std::vector<MfmaSearchArgs> args;         // argument table of the last enqueue
   ArgStage stage;                           // pinned staging of the eager table
+  // persistent launch: work items (beam, tile) in beam order, their counter, grid size
+  bool persistent = false;
+  int2 *d_items = nullptr;
+  int32_t nitems = 0, pgrid = 0;
+  int32_t *d_counter = nullptr;
 };
 
 void mfma_batch_free(MfmaBatch *B) {
@@ -917,6 +958,8 @@ void mfma_batch_free(MfmaBatch *B) {
   B->stage.release();
   (void)hipFree(B->d_base);
   (void)hipFree(B->d_args_graph);
+  (void)hipFree(B->d_items);
+  (void)hipFree(B->d_counter);
   delete B;
 }
 
@@ -978,11 +1021,32 @@ dedisp_status mfma_batch_create(const std::vector<dedisp_plan> &plans,
     }
   }
   B->base.push_back((int32_t)blocks);
+  // the persistent launch (the default; DEDISP_BATCH_LAUNCH=grid selects one workgroup
+  // per tile instead): every (beam, tile) as a work item, beam by beam, each beam's
+  // tiles in time-major order
+  const char *lm = getenv("DEDISP_BATCH_LAUNCH");
+  B->persistent = !(lm && std::string(lm) == "grid");
+  std::vector<int2> items;
+  if (B->persistent) {
+    for (int b = 0; b < B->nbeam; ++b) {
+      const int64_t nb = (int64_t)plans[b]->mfma->cfg[chosen].ntw * B->lay[b].ntt;
+      for (int64_t L = 0; L < nb; ++L) items.push_back(make_int2(b, (int)L));
+    }
+    B->nitems = (int32_t)items.size();
+  }
   B->args_off = off;
   B->work_bytes = off + sizeof(MfmaSearchArgs) * B->nbeam;
   hipError_t e = upload(&B->d_base, B->base);
   if (e == hipSuccess)
     e = dev_malloc((void **)&B->d_args_graph, sizeof(MfmaSearchArgs) * B->nbeam);
+  if (e == hipSuccess && B->persistent) {
+    e = upload(&B->d_items, items);
+    if (e == hipSuccess) e = dev_malloc((void **)&B->d_counter, sizeof(int32_t));
+    int dev = 0, ncu = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    B->pgrid = ncu * kMfmaCfgs[chosen].wg;   // one wave of resident workgroups
+  }
   if (e != hipSuccess) {
     mfma_batch_free(B);
     return hip_fail(e, "batch setup");
@@ -994,6 +1058,19 @@ dedisp_status mfma_batch_create(const std::vector<dedisp_plan> &plans,
 template <int NWD, int NWT, int NP, int WG>
 static hipError_t launch_batch_mfma_cfg(const MfmaBatch *B, const MfmaSearchArgs *table,
                                         hipStream_t s) {
+  if (B->persistent) {
+    static bool pdone[64] = {};
+    static std::mutex pmu;
+    hipError_t e = allow_lds_mfma((const void *)k_search_mfma_persist<NWD, NWT, NP, WG>, pdone,
+                                  &pmu, 2 * (kMfmaBufBytes / WG));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, B->d_counter);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_search_mfma_persist<NWD, NWT, NP, WG>), dim3(B->pgrid),
+                       dim3(64 * NWD * NWT), 2 * (kMfmaBufBytes / WG), s, table, B->d_items,
+                       B->nitems, B->d_counter);
+    return hipGetLastError();
+  }
   static bool done[64] = {};
   static std::mutex mu;
   hipError_t e = allow_lds_mfma((const void *)k_search_mfma_batch<NWD, NWT, NP, WG>, done, &mu,

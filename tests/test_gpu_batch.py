@@ -64,14 +64,17 @@ def _check(orc, beams_, widths, snr, t, W):
         off += D
 
 
-@pytest.mark.parametrize("kernel", ["matrix", "packed"])
-def test_batch_eager_and_graph_replays(dd, orc, beams, kernel):
+@pytest.mark.parametrize("kernel", ["matrix", "matrix-grid", "packed"])
+def test_batch_eager_and_graph_replays(dd, orc, beams, kernel, monkeypatch):
     import torch
     C, bl = beams
     widths = list(range(1, 33))
-    # the batch takes the matrix-core kernel unless the first plan forces a packed-add shape
+    # the batch takes the matrix-core kernel unless the first plan forces a packed-add shape;
+    # the matrix-core batch runs as a persistent launch unless one workgroup per tile is asked
     if kernel == "packed":
         bl[0][0].set_tile(4)
+    if kernel == "matrix-grid":
+        monkeypatch.setenv("DEDISP_BATCH_LAUNCH", "grid")
     try:
         B = dd.Batch([b[0] for b in bl], [b[1].shape[1] for b in bl], widths)
     finally:
