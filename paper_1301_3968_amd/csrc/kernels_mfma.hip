@@ -85,7 +85,7 @@ struct MGroup {
 struct MUnit {
   int32_t c;      // channel
   int32_t src;    // first window sample of the chunk, relative to the tile's first output
-  int32_t dst;    // LDS byte offset of the chunk's 4 interleaved copies (64 bytes)
+  int32_t dst;    // LDS byte offset of the chunk's 2 interleaved copies (32 bytes)
   int32_t pad;
 };
 
@@ -190,15 +190,22 @@ __device__ __forceinline__ void store_chunk(unsigned char *buf, int32_t dst, con
   }
 }
 
-// XCD-aware tile order (blocks b = x mod 8 run on XCD x): XCD x takes a contiguous
-// run of tiles in time-major order, so the DM tiles of one time tile share its L2.
+// XCD-aware tile order (block b runs on XCD b mod 8): XCD x takes a contiguous run of
+// tiles in an order that walks the time tiles in groups of kTimeGroup, DM tile by DM tile
+// within a group.  The tiles an XCD runs at once are then a few DM tiles of the group's
+// time tiles, and the next DM tiles read the group's windows again from the XCD's L2
+// while they are still there (every DM tile of one time tile at once, the order before,
+// fetched 3.8 times as many bytes from beyond the L2 and ran 2-3 % slower).
+constexpr int kTimeGroup = 8;
 __device__ __forceinline__ void tile_of_block(int ntw, int ntt, int *tt, int *tw) {
   const int nb = ntw * ntt;
   const int bi = blockIdx.x;
   const int xcd = bi & 7, kk = bi >> 3, q = nb >> 3, rem = nb & 7;
   const int L = xcd * q + min(xcd, rem) + kk;
-  *tt = L / ntw;
-  *tw = L - *tt * ntw;
+  const int grp = L / (kTimeGroup * ntw), in = L - grp * kTimeGroup * ntw;
+  const int gs = min(kTimeGroup, ntt - grp * kTimeGroup);   // time tiles in this group
+  *tw = in / gs;
+  *tt = grp * kTimeGroup + (in - *tw * gs);
 }
 
 typedef int32_t v16i __attribute__((ext_vector_type(16)));
