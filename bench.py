@@ -15,6 +15,7 @@ import hashlib
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -134,14 +135,16 @@ def main() -> int:
                     help="headline only: skip the batch and autograd ratio measurements")
     ap.add_argument("--workload", default="search",
                     choices=["search", "batch", "weighted", "autograd", "completeness", "dm_error",
-                             "resolution", "detectors"],
+                             "resolution", "detectors", "lds"],
                     help="search: the headline fused search (default); batch: 36 beams in one "
                          "launch; weighted: 4096-channel fp32-weighted dedispersion; "
                          "autograd: forward / adjoint timing of the 8-tap learnable profile; "
                          "completeness: largest S/N over the trial DMs against a test pulse's DM; "
                          "dm_error: S/N attenuation with DM error about one trial DM; "
                          "resolution: peak S/N against the time and frequency resolution; "
-                         "detectors: matched filters and boxcar against the greedy detector")
+                         "detectors: matched filters and boxcar against the greedy detector; "
+                         "lds: LDS read rate of the lane address patterns of the matrix-core "
+                         "operand reads (the probe_lds program, run as a child process)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (the reference kernel "
                          "for scaling HBM byte counters) and exit")
@@ -150,6 +153,22 @@ def main() -> int:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU layout "
               "is described in the design notes and not run here.", file=sys.stderr)
         return 2
+
+    if args.workload == "lds":
+        # a child process of its own, started before this process touches the GPU
+        probe = os.path.join(ROOT, "paper_1301_3968_amd", "probe_lds")
+        if not os.path.exists(probe):
+            print("probe_lds is not built (run the package's build first)", file=sys.stderr)
+            return 1
+        out = subprocess.run([probe], stdout=subprocess.PIPE, text=True)
+        if out.returncode != 0:
+            print(f"probe_lds failed with status {out.returncode}", file=sys.stderr)
+            return out.returncode
+        rates = [json.loads(ln) for ln in out.stdout.splitlines() if ln.startswith("{")]
+        print(json.dumps({"metric": "LDS read bytes per clock per CU (16-byte lane reads)",
+                          "unit": "B/clk/CU", "n_gpus": 1, "higher_is_better": True,
+                          "data": "synthetic", "patterns": rates}))
+        return 0
 
     import numpy as np
     import torch

@@ -73,6 +73,22 @@ def build(verbose: bool = False, jobs: int = 8, sanitize: bool = False) -> str:
     return lib_path
 
 
+PROBE_SRC = os.path.join(CSRC, "probe_lds.hip")
+PROBE_BIN = os.path.join(HERE, "probe_lds")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """Compile the LDS read-rate measurement program (not part of the library)."""
+    hipcc = os.path.join(ROCM, "bin", "hipcc")
+    cmd = [hipcc, "-x", "hip"] + [f for f in COMMON if f != "-fPIC"] + [PROBE_SRC, "-o", PROBE_BIN]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if out.returncode != 0:
+        raise RuntimeError("probe build failed:\n" + out.stdout)
+    return PROBE_BIN
+
+
 def _wait(procs):
     errs = []
     for src, p in procs:
