@@ -66,6 +66,7 @@ struct dedisp_plan_s {
   int32_t min_start = 0;
   int32_t max_ntap = 0;
   int64_t sum_max_ntap = 0;             // sum_c max_d ntap[d,c]
+  int64_t window_rows = 0;              // sum_c (max_d ntap[d,c] - min_d ntap[d,c] + 1)
   int32_t tile_choice = -1;             // forced / tuned tile configuration (-2: general path)
   int32_t last_search_tile = -1;        // tile configuration of the last search (-1: general)
 

@@ -653,23 +653,9 @@ static Layout layout(const dedisp_plan_s *p, int ci, int32_t nw, int64_t nout, i
   return L;
 }
 
-static int64_t count_rows(const dedisp_plan_s *p) {
-  const int C = p->nchan, D = p->ndm;
-  int64_t r = 0;
-  for (int c = 0; c < C; ++c) {
-    int lo = INT32_MAX, hi = 0;
-    for (int d = 0; d < D; ++d) {
-      lo = std::min(lo, p->ntap[(size_t)d * C + c]);
-      hi = std::max(hi, p->ntap[(size_t)d * C + c]);
-    }
-    r += hi - lo + 1;
-  }
-  return r;
-}
-
 size_t search_work_bytes(const dedisp_plan_s *p, int32_t nw, int64_t nout) {
   if (p->wmode != DEDISP_W_UNIT) return 0;
-  const int64_t nrows = count_rows(p);
+  const int64_t nrows = p->window_rows;
   size_t best = mfma_search_work_bytes(p, nw, nout);
   for (int ci = 0; ci < kNumCfgs; ++ci) best = std::max(best, layout(p, ci, nw, nout, nrows).total);
   return best;

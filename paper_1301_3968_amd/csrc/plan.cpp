@@ -237,22 +237,25 @@ static dedisp_status build_tables(dedisp_plan p) {
   for (size_t i = 0; i < p->ntap.size(); ++i)
     if (p->ntap[i] == 0) p->start[i] = 0;
   int32_t span = 0, nmax = 0, smin = INT32_MAX;
-  int64_t summax = 0;
+  int64_t summax = 0, rows = 0;
   for (int32_t c = 0; c < C; ++c) {
-    int32_t cm = 0;
+    int32_t cm = 0, cl = INT32_MAX;
     for (int32_t d = 0; d < D; ++d) {
       const int32_t s = p->start[(size_t)d * C + c], n = p->ntap[(size_t)d * C + c];
       if (n > 0) span = std::max(span, s + n);
       smin = std::min(smin, s);
       cm = std::max(cm, n);
+      cl = std::min(cl, n);
     }
     nmax = std::max(nmax, cm);
     summax += cm;
+    rows += cm - cl + 1;
   }
   p->max_span = std::max(span, 1);
   p->max_ntap = nmax;
   p->min_start = smin;
   p->sum_max_ntap = summax;
+  p->window_rows = rows;
   if (p->wmode == DEDISP_W_TAP) {
     for (size_t i = 0; i < p->ntap.size(); ++i)
       if (p->ntap[i] != p->ktaps)
