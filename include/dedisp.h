@@ -243,7 +243,9 @@ dedisp_status dedisp_batch_work_bytes(dedisp_batch batch, size_t *bytes);
  * (row stride in_stride[b]); d_chan_mean/sigma device fp64 [nchan] shared by all
  * beams; outputs device, concatenated over beams in beam order (sum of ndm_b).
  * If use_graph != 0 the launch sequence is captured once into a hipGraph and
- * replayed on later calls with the same pointers. */
+ * replayed on later calls with the same pointers.  Calls on one batch share its
+ * work-item counter and graph argument table: they must not overlap in time (issue
+ * them on one stream, or order the streams). */
 dedisp_status dedisp_batch_run(dedisp_batch batch, const void *const *d_in, const int64_t *in_stride,
                                const double *d_chan_mean, const double *d_chan_sigma,
                                double *d_snr, int32_t *d_t, int32_t *d_w, void *d_work,
