@@ -1030,14 +1030,18 @@ dedisp_status mfma_batch_create(const std::vector<dedisp_plan> &plans,
   B->base.push_back((int32_t)blocks);
   // the persistent launch (the default; DEDISP_BATCH_LAUNCH=grid selects one workgroup
   // per tile instead): every (beam, tile) as a work item, beam by beam, each beam's
-  // tiles in time-major order
+  // tiles in the one-plan kernel's order (time tiles in groups of kTimeGroup, DM tile
+  // by DM tile within a group; 0.5-1 % faster than time-major order on 36 beams)
   const char *lm = getenv("DEDISP_BATCH_LAUNCH");
   B->persistent = !(lm && std::string(lm) == "grid");
   std::vector<int2> items;
   if (B->persistent) {
     for (int b = 0; b < B->nbeam; ++b) {
-      const int64_t nb = (int64_t)plans[b]->mfma->cfg[chosen].ntw * B->lay[b].ntt;
-      for (int64_t L = 0; L < nb; ++L) items.push_back(make_int2(b, (int)L));
+      const int64_t ntw = plans[b]->mfma->cfg[chosen].ntw, ntt = B->lay[b].ntt;
+      for (int64_t g0 = 0; g0 < ntt; g0 += kTimeGroup)
+        for (int64_t tw = 0; tw < ntw; ++tw)
+          for (int64_t tt = g0; tt < std::min(ntt, g0 + kTimeGroup); ++tt)
+            items.push_back(make_int2(b, (int)(tt * ntw + tw)));
     }
     B->nitems = (int32_t)items.size();
   }
