@@ -25,6 +25,11 @@
  *   - A plan holds only immutable tables (host copies and lazily uploaded
  *     device copies); calls on different streams may share it provided each
  *     has its own workspace.
+ *   - Environment: DEDISP_LOG (set, not "0") prints one line on stderr per plan
+ *     created and whenever a plan's search runs in another shape than the last
+ *     one printed; DEDISP_TEST_FAIL_ALLOC=k makes the k-th host or device
+ *     allocation (counted from when the variable took that value) fail with
+ *     DEDISP_ERR_OOM, for tests of the failure paths.
  */
 #ifndef DEDISP_H
 #define DEDISP_H

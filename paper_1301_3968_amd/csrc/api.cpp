@@ -2,6 +2,7 @@
 // the launch sequences.  Kernels live in kernels_basic.hip / kernels_search.hip.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -161,6 +162,17 @@ static dedisp_status check_int32_sums(const dedisp_plan_s *p, int32_t in_dtype, 
   return DEDISP_OK;
 }
 
+// Under DEDISP_LOG, a line whenever a plan's search runs in another configuration than
+// the last one reported for it.
+static void log_search(dedisp_plan p, int64_t nout, int32_t nw) {
+  if (!log_enabled() || p->last_search_tile == p->logged_tile) return;
+  p->logged_tile = p->last_search_tile;
+  fprintf(stderr,
+          "dedisp: search on plan %p: shape %d of the candidate list (-1: unfused path), "
+          "%lld outputs, %d widths\n",
+          (const void *)p, p->last_search_tile, (long long)nout, nw);
+}
+
 // Outputs the fused search adds in int32 at most: a lane's starts and the halo of
 // the widths (at most 64).
 constexpr int64_t kSearchSpan = 64;
@@ -256,9 +268,13 @@ dedisp_status dedisp_search(dedisp_plan p, const void *d_in, int32_t in_dtype, i
   if (in_dtype == DEDISP_U8 && p->tile_choice != -2 && dd::search_supported(p, wl)) {
     st = dd::run_search_tiled(p, (const uint8_t *)d_in, nsamp, in_stride, nout, wl, d_chan_mean,
                               d_chan_sigma, d_snr, d_t, d_w, d_work, s);
-    if (st != DEDISP_ERR_UNSUPPORTED) return st;   // unsupported shapes fall through
+    if (st != DEDISP_ERR_UNSUPPORTED) {   // unsupported shapes fall through
+      if (st == DEDISP_OK) dd::log_search(p, nout, wl.n);
+      return st;
+    }
   }
   p->last_search_tile = -1;
+  dd::log_search(p, nout, wl.n);
   // General path: materialise y in a stream-ordered temporary, then detect.
   const int32_t ydt = (in_dtype == DEDISP_U8 && p->wmode == DEDISP_W_UNIT) ? DEDISP_I32 : DEDISP_F32;
   void *y = nullptr;

@@ -21,6 +21,10 @@ dedisp_status hip_fail(hipError_t e, const char *what);
 // k-th allocation attempt counted from the moment the variable took that value fails
 // (every host or device allocation the library makes goes through this check first).
 bool alloc_fails();
+// DEDISP_LOG set (and not "0"): one line per plan created and per change of a plan's
+// search configuration, on stderr.
+bool log_enabled();
+void log_plan(const dedisp_plan_s *p);
 // hipMalloc and hipMallocAsync behind the test hook.
 hipError_t dev_malloc(void **p, size_t bytes);
 hipError_t dev_malloc_async(void **p, size_t bytes, hipStream_t s);
@@ -69,6 +73,7 @@ struct dedisp_plan_s {
   int64_t window_rows = 0;              // sum_c (max_d ntap[d,c] - min_d ntap[d,c] + 1)
   int32_t tile_choice = -1;             // forced / tuned tile configuration (-2: general path)
   int32_t last_search_tile = -1;        // tile configuration of the last search (-1: general)
+  int32_t logged_tile = INT32_MIN;      // search configuration last reported under DEDISP_LOG
 
   // Device copies, uploaded on first use (per plan, on the current device).
   std::mutex mu;

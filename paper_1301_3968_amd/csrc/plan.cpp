@@ -282,6 +282,25 @@ bool alloc_fails() {
   return ++count == strtol(v, nullptr, 10);
 }
 
+bool log_enabled() {
+  const char *v = getenv("DEDISP_LOG");
+  return v && *v && strcmp(v, "0") != 0;
+}
+
+void log_plan(const dedisp_plan_s *p) {
+  static const char *const kRules[] = {"smear", "allnonzero", "greedy", "explicit", "fixed"};
+  static const char *const kWeights[] = {"unit", "channel", "tap"};
+  const int rule = p->prof.rule >= 0 && p->prof.rule <= DEDISP_RULE_FIXED ? p->prof.rule : 0;
+  const int wm = p->wmode >= 0 && p->wmode <= DEDISP_W_TAP ? p->wmode : 0;
+  int32_t nmin = INT32_MAX;
+  for (int32_t n : p->ntap) nmin = std::min(nmin, n);
+  fprintf(stderr,
+          "dedisp: plan %p: %d trials x %d channels, DM %.6g..%.6g, rule %s, weights %s, "
+          "samples per channel %d..%d, longest run %d samples (outputs = block length - %d)\n",
+          (const void *)p, p->ndm, p->nchan, p->dm.front(), p->dm.back(), kRules[rule],
+          kWeights[wm], p->ntap.empty() ? 0 : nmin, p->max_ntap, p->max_span, p->max_span - 1);
+}
+
 hipError_t dev_malloc(void **p, size_t bytes) {
   if (alloc_fails()) return hipErrorOutOfMemory;
   return hipMalloc(p, bytes);
@@ -399,6 +418,7 @@ dedisp_status dedisp_plan_create(dedisp_plan *out, int32_t nchan, const double *
     delete p;
     return fail(DEDISP_ERR_OOM, "host allocation failed");
   }
+  if (dd::log_enabled()) dd::log_plan(p);
   *out = p;
   return DEDISP_OK;
 }

@@ -203,3 +203,23 @@ def test_forced_allocation_failure(dd, monkeypatch):
     monkeypatch.delenv("DEDISP_TEST_FAIL_ALLOC")
     p2 = dd.Plan(f, 0.3 / 64, 1e-3, dms, rule="smear")
     assert np.array_equal(p.tables()[1], p2.tables()[1])
+
+
+def test_plan_log_line():
+    # DEDISP_LOG=1 prints one summary line per plan on stderr; without it nothing.
+    import subprocess
+    import sys
+    code = ("import numpy as np, paper_1301_3968_amd as dd; "
+            "f = 1.2 + 0.3 * (np.arange(64) + 0.5) / 64; "
+            "dd.Plan(f, 0.3 / 64, 1e-3, np.arange(32) * 10.0, rule='smear')")
+    env = dict(os.environ, DEDISP_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
+                       cwd=ROOT, env=env)
+    assert r.returncode == 0, r.stderr
+    lines = [ln for ln in r.stderr.splitlines() if ln.startswith("dedisp: plan")]
+    assert len(lines) == 1
+    assert "32 trials x 64 channels" in lines[0] and "rule smear" in lines[0]
+    env.pop("DEDISP_LOG")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
+                       cwd=ROOT, env=env)
+    assert r.returncode == 0 and "dedisp:" not in r.stderr
