@@ -139,6 +139,22 @@ dedisp_status dedisp_dedisperse(dedisp_plan plan, const void *d_in, int32_t in_d
                                 int32_t nbatch, void *d_out, int32_t out_dtype, int64_t out_stride,
                                 int64_t out_bstride, const float *d_weights, void *stream);
 
+/* Streaming (Section 2.1's detector runs on data as they arrive): a block of a
+ * stream searched by dedisp_search or dedisp_detect gives each trial's best window
+ * of that block (starts relative to the block's first output).  This merges such a
+ * result into a running best over the stream: for every trial d < ndm whose block
+ * candidate holds a window (d_t_b[d] >= 0), the candidate (d_snr_b, d_t_b + t_offset,
+ * d_w_b) replaces (d_snr, d_t, d_w) when d_t[d] < 0 or it ranks above it in the
+ * search's order (larger S/N, then smaller W, then smaller start).  Block candidate
+ * arrays are device f64 / i32 / i32 [ndm]; the running best device f64 / i64 / i32
+ * [ndm], initialised by the caller to (-inf, -1, 0).  t_offset >= 0 is the stream
+ * index of the block's first output.  A block that overlaps the previous one by
+ * max_span - 1 + W_max - 1 samples searches every window of the stream at least once,
+ * and the running best then equals the search of the whole stream. */
+dedisp_status dedisp_merge_candidates(int32_t ndm, const double *d_snr_b, const int32_t *d_t_b,
+                                      const int32_t *d_w_b, int64_t t_offset, double *d_snr,
+                                      int64_t *d_t, int32_t *d_w, void *stream);
+
 /* Workspace (device bytes) needed by dedisp_detect / dedisp_search for nsamp
  * samples and nw widths. */
 dedisp_status dedisp_work_bytes(dedisp_plan plan, int64_t nsamp, int32_t nw, size_t *bytes);

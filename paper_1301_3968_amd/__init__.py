@@ -10,5 +10,6 @@ from ._lib import DedispError
 _lib.lib()  # fail at import time when the HIP library is missing
 
 from .api import Batch, Plan, trial_dms  # noqa: E402
+from .stream import StreamDedisperser, StreamSearch  # noqa: E402
 
-__all__ = ["Batch", "Plan", "trial_dms", "DedispError"]
+__all__ = ["Batch", "Plan", "StreamDedisperser", "StreamSearch", "trial_dms", "DedispError"]

@@ -246,6 +246,19 @@ dedisp_status dedisp_detect(dedisp_plan p, const void *d_y, int32_t y_dtype, int
                         d_w, d_work, (hipStream_t)stream);
 }
 
+dedisp_status dedisp_merge_candidates(int32_t ndm, const double *d_snr_b, const int32_t *d_t_b,
+                                      const int32_t *d_w_b, int64_t t_offset, double *d_snr,
+                                      int64_t *d_t, int32_t *d_w, void *stream) {
+  if (ndm <= 0) return fail(DEDISP_ERR_INVALID_ARG, "ndm must be > 0");
+  if (!d_snr_b || !d_t_b || !d_w_b || !d_snr || !d_t || !d_w)
+    return fail(DEDISP_ERR_INVALID_ARG, "null argument");
+  if (t_offset < 0 || t_offset > INT64_MAX - INT32_MAX)
+    return fail(DEDISP_ERR_INVALID_ARG, "bad t_offset");
+  DD_HIP(dd::launch_merge_cand(ndm, d_snr_b, d_t_b, d_w_b, t_offset, d_snr, d_t, d_w,
+                               (hipStream_t)stream));
+  return DEDISP_OK;
+}
+
 dedisp_status dedisp_search(dedisp_plan p, const void *d_in, int32_t in_dtype, int64_t nsamp,
                             int64_t in_stride, const int32_t *widths, int32_t nw,
                             const double *d_chan_mean, const double *d_chan_sigma, double *d_snr,

@@ -148,6 +148,9 @@ hipError_t launch_boxcar(const dedisp_plan_s *p, const void *y, int32_t y_dtype,
                          void *partials, int32_t nchunk, hipStream_t s);
 hipError_t launch_reduce(int32_t ndm, int32_t nchunk, const void *partials, double *snr,
                          int32_t *t, int32_t *w, hipStream_t s);
+hipError_t launch_merge_cand(int32_t ndm, const double *snr_b, const int32_t *t_b,
+                             const int32_t *w_b, int64_t t_offset, double *snr, int64_t *t,
+                             int32_t *w, hipStream_t s);
 hipError_t launch_adjoint_z(const dedisp_plan_s *p, const float *g, int64_t nout, int64_t gstride,
                             int64_t gbstride, int32_t nbatch, int64_t nz, double *z,
                             hipStream_t s);

@@ -378,6 +378,31 @@ k_reduce(int32_t ndm, int32_t nchunk, const Cand *__restrict__ part, double *__r
   }
 }
 
+// Per trial, the block's best candidate (start t_b + t_offset in the stream) replaces
+// the running best when it ranks above it (the ranking of the search: larger S/N, then
+// smaller width, then earlier start; a candidate with t < 0 holds no window).
+__global__ void __launch_bounds__(kThreads)
+k_merge_cand(int32_t ndm, const double *__restrict__ snr_b, const int32_t *__restrict__ t_b,
+             const int32_t *__restrict__ w_b, int64_t t_offset, double *__restrict__ snr,
+             int64_t *__restrict__ t, int32_t *__restrict__ w) {
+  const int d = blockIdx.x * kThreads + threadIdx.x;
+  if (d >= ndm || t_b[d] < 0) return;
+  const int64_t tb = t_b[d] + t_offset;
+  const double sb = snr_b[d];
+  const int wb = w_b[d];
+  bool take = t[d] < 0;
+  if (!take) {
+    if (sb != snr[d]) take = sb > snr[d];
+    else if (wb != w[d]) take = wb < w[d];
+    else take = tb < t[d];
+  }
+  if (take) {
+    snr[d] = sb;
+    t[d] = tb;
+    w[d] = wb;
+  }
+}
+
 // ----------------------------------------------------------------------------------
 // Adjoint kernels (transposes of the dedispersion sum), all in gather form so that
 // every output is written by exactly one thread in a fixed summation order.
@@ -737,6 +762,14 @@ hipError_t launch_reduce(int32_t ndm, int32_t nchunk, const void *partials, doub
                          int32_t *t, int32_t *w, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce, dim3(ndm), dim3(kThreads), 0, s, ndm, nchunk,
                      (const Cand *)partials, snr, t, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_cand(int32_t ndm, const double *snr_b, const int32_t *t_b,
+                             const int32_t *w_b, int64_t t_offset, double *snr, int64_t *t,
+                             int32_t *w, hipStream_t s) {
+  hipLaunchKernelGGL(k_merge_cand, dim3((unsigned)((ndm + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, ndm, snr_b, t_b, w_b, t_offset, snr, t, w);
   return hipGetLastError();
 }
 
