@@ -120,6 +120,88 @@ def cpu_baseline(wl, rule: str, ndm_single: int, ndm_threads: int):
                                         f"{dt1:.1f} s"}}
 
 
+def _oracle_threads(jobs):
+    """Run the oracle jobs (callables, each on its own part of a sample) on the host's
+    cores; returns (seconds, threads)."""
+    from concurrent.futures import ThreadPoolExecutor
+    _, ncpu = _host_cpu()
+    nth = max(1, min(ncpu, len(jobs)))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(nth) as ex:
+        list(ex.map(lambda f: f(), jobs))
+    return time.perf_counter() - t0, nth
+
+
+def _oracle_line(sums, seconds, nth, sample):
+    model, ncpu = _host_cpu()
+    return {"value": sums / seconds, "unit": "sums/s", "cores": nth, "kind": "oracle",
+            "sample": f"{sample}, {nth} threads, {seconds:.1f} s", "host_cpu": model,
+            "host_logical_cpus": ncpu}
+
+
+def cpu_baseline_weighted(wl, ntrials: int = 16):
+    """The oracle's fp64 channel-weighted sum on ntrials evenly spaced trials of the
+    4096-channel block, one trial per thread."""
+    import oracle
+    start = oracle.delay_start(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms).astype(np.int32)
+    ntap = oracle.taps_smear(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms).astype(np.int32)
+    tout = wl.x.shape[1] - int(np.max(start + ntap)) + 1
+    pick = np.linspace(0, len(wl.dms) - 1, ntrials).round().astype(int)
+    jobs = [lambda d=d: oracle.dedisperse_f64(wl.x, start[d:d + 1], ntap[d:d + 1], "channel",
+                                              wl.weights, tout=tout) for d in pick]
+    sec, nth = _oracle_threads(jobs)
+    return _oracle_line(ntrials * wl.x.shape[0] * tout, sec, nth,
+                        f"{ntrials} of {len(wl.dms)} trials (evenly spaced), full "
+                        f"{wl.x.shape[0]}x{wl.x.shape[1]} block, fp64 channel-weighted sum")
+
+
+def cpu_baseline_batch(beams, widths, ntrials: int = 128):
+    """The oracle's dedispersion + noise tables + detection on ntrials evenly spaced trials
+    of each sampled beam (beams: list of (x, freqs, dms)), one (beam, trial range) per
+    thread."""
+    import oracle
+    jobs, sums, desc = [], 0, []
+    for x, f, dms in beams:
+        start = oracle.delay_start(f, 0.001, 1e-3, dms).astype(np.int32)
+        ntap = oracle.taps_allnonzero(f, 0.001, 1e-3, dms).astype(np.int32)
+        tout = x.shape[1] - int(np.max(start + ntap)) + 1
+        pick = np.linspace(0, len(dms) - 1, ntrials).round().astype(int)
+        C = x.shape[0]
+        mu, sg = np.full(C, 128.0), np.full(C, 16.0)
+        for part in np.array_split(pick, 4):
+            def job(x=x, s=start[part], n=ntap[part], tout=tout, mu=mu, sg=sg):
+                y = oracle.dedisperse_u8(x, s, n, tout=tout)
+                M, S = oracle.boxcar_norm(n, widths, mu, sg)
+                oracle.boxcar_detect(y.astype(np.float64), widths, M, S)
+            jobs.append(job)
+        sums += ntrials * C * tout
+        desc.append(f"{x.shape[1]}")
+    sec, nth = _oracle_threads(jobs)
+    return _oracle_line(sums, sec, nth,
+                        f"{ntrials} evenly spaced trials of each of {len(beams)} beams "
+                        f"(lengths {', '.join(desc)}), dedisperse+norm+detect")
+
+
+def cpu_baseline_taps(wl, nbatch: int = 16, ntrials: int = 32):
+    """The oracle's fp64 tap-weighted forward sum on nbatch pulses' blocks x ntrials
+    evenly spaced trials of the 64-pulse batch, one (block, trial range) per thread."""
+    import oracle
+    start = oracle.delay_start(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms).astype(np.int32)
+    K = wl.extra["ktaps"]
+    ntap = np.full_like(start, K)
+    tout = wl.x.shape[2] - int(np.max(start + ntap)) + 1
+    pick = np.linspace(0, len(wl.dms) - 1, ntrials).round().astype(int)
+    jobs = []
+    for b in range(nbatch):
+        for part in np.array_split(pick, 4):
+            jobs.append(lambda b=b, part=part: oracle.dedisperse_f64(
+                wl.x[b], start[part], ntap[part], "tap", wl.weights, tout=tout))
+    sec, nth = _oracle_threads(jobs)
+    return _oracle_line(nbatch * ntrials * wl.x.shape[1] * tout, sec, nth,
+                        f"{nbatch} of {wl.x.shape[0]} pulse blocks x {ntrials} of "
+                        f"{len(wl.dms)} trials, fp64 {K}-tap forward sum")
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,10 +399,15 @@ def _other_workload(args, dd, workloads) -> int:
     base = {"n_gpus": 1, "steps": K, "warmup": W, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "data": "synthetic"}
     if args.workload == "batch":
-        m = measure_batch(dd, workloads, K, W, single=True)
+        m = measure_batch(dd, workloads, K, W, single=True,
+                          keep_host=() if args.no_cpu_baseline else (0, 9, 18, 27))
+        host = m.pop("host_beams", [])
         line = dict(base, metric="DM-trial*channel*sample sums/s (36-beam batch)",
                     value=m["sums_per_s"], unit="sums/s", ms_per_step=m["ms_per_call"],
                     dtype="int32", config=m)
+        if host:
+            print("timing the oracle on a sample", file=sys.stderr, flush=True)
+            line["cpu_baseline"] = cpu_baseline_batch(host, list(range(1, 33)))
     elif args.workload == "completeness":
         line = dict(base, **_completeness(dd, workloads, K, W))
     elif args.workload == "dm_error":
@@ -343,19 +430,26 @@ def _other_workload(args, dd, workloads) -> int:
                     value=sums / t, unit="sums/s", ms_per_step=t * 1e3, dtype="fp32",
                     config={"workload": "4096 ch x 262144 samples uint8, 4096 trial DMs, "
                                         "weights (f/1.35 GHz)^-1.5", "nout": nout})
+        if not args.no_cpu_baseline:
+            print("timing the oracle on a sample", file=sys.stderr, flush=True)
+            line["cpu_baseline"] = cpu_baseline_weighted(wl)
     else:
         m = measure_autograd(dd, workloads, K, W, train=True)
         line = dict(base, metric="DM-trial*channel*sample sums/s (8-tap fp32 forward)",
                     value=m["forward_sums_per_s"], unit="sums/s", ms_per_step=m["ms_forward"],
                     dtype="fp32", config=m)
+        if not args.no_cpu_baseline:
+            print("timing the oracle on a sample", file=sys.stderr, flush=True)
+            line["cpu_baseline"] = cpu_baseline_taps(workloads.cfg5())
     print(json.dumps(line), flush=True)
     return 0
 
 
-def measure_batch(dd, workloads, K, W, single=False):
+def measure_batch(dd, workloads, K, W, single=False, keep_host=()):
     """The 36-beam batch (336 ch, lengths U{16384..131072}, trial-DM grids of 300-1200
     trials at 0.8 of optimal) searched in one call replayed from a HIP graph; eager
-    calls and (single) the beams searched one plan at a time beside it."""
+    calls and (single) the beams searched one plan at a time beside it.  The host data
+    of the beams in keep_host are returned under "host_beams" (for the oracle's timing)."""
     import math
 
     import torch
@@ -363,13 +457,15 @@ def measure_batch(dd, workloads, K, W, single=False):
     C = 336
     f = workloads.channel_centres(1.2, 0.336, C)
     eps = math.sqrt(0.8 ** -4 - 1.0) / 2.0       # spacing one DM error apart, 0.8 of optimal
-    plans, xs = [], []
+    plans, xs, host = [], [], []
     print("generating 36 beams", file=sys.stderr, flush=True)
     for b in range(len(spec["nsamp"])):
         dms = dd.trial_dms(0.0, 1e9, eps, f, 0.001, 1e-3, cap=int(spec["ntrial"][b]))
         x, _ = workloads.cfg4_beam_data(b, int(spec["nsamp"][b]), float(dms[0]), float(dms[-1]))
         plans.append(dd.Plan(f, 0.001, 1e-3, dms, rule="allnonzero"))
         xs.append(torch.from_numpy(x).cuda())
+        if b in keep_host:
+            host.append((x, f, np.asarray(dms)))
     widths = list(range(1, 33))
     B = dd.Batch(plans, [int(v) for v in spec["nsamp"]], widths)
     mu = torch.full((C,), 128.0, dtype=torch.float64, device="cuda")
@@ -392,6 +488,8 @@ def measure_batch(dd, workloads, K, W, single=False):
         t_single = _timed(lambda: [p_.search(x, widths, mu, sg, work=w_) for p_, x, w_ in
                                    zip(plans, xs, pw)], K, W)
         out["ms_one_plan_at_a_time"] = t_single * 1e3
+    if host:
+        out["host_beams"] = host
     return out
 
 
