@@ -63,7 +63,7 @@ def otables(orc):
 
 
 def oracle_threads() -> int:
-    """Host threads for oracle loops: the GPU machine's CPU share is 16."""
+    """Host threads for oracle loops: the host cores, at most 16."""
     return max(1, min(16, os.cpu_count() or 1))
 
 
