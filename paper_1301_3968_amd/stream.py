@@ -74,14 +74,14 @@ class StreamSearch:
     device tensors; (-inf, -1, 0) for a trial with no window yet), which equals the
     search of the whole stream so far."""
 
-    def __init__(self, plan: Plan, widths: Sequence[int], mean: torch.Tensor,
-                 sigma: torch.Tensor):
+    def __init__(self, plan: Plan, widths: Sequence[int], mean, sigma):
         self.plan = plan
         self.widths = [int(w) for w in widths]
-        self.mean, self.sigma = mean, sigma
+        dev = mean.device if isinstance(mean, torch.Tensor) else torch.device("cuda")
+        self.mean = torch.as_tensor(mean, dtype=torch.float64, device=dev).contiguous()
+        self.sigma = torch.as_tensor(sigma, dtype=torch.float64, device=dev).contiguous()
         self.wmax = max(self.widths)
         self._tail = _Tail(plan.max_span - 1 + self.wmax - 1)
-        dev = mean.device
         self._snr = torch.full((plan.ndm,), float("-inf"), dtype=torch.float64, device=dev)
         self._t = torch.full((plan.ndm,), -1, dtype=torch.int64, device=dev)
         self._w = torch.zeros(plan.ndm, dtype=torch.int32, device=dev)
