@@ -410,3 +410,32 @@ def test_fused_search_sparse_widths(dd, orc, cfg2_mid):
     snr, t, W = p.search(_dev(wl.x), widths, wl.chan_mean, wl.chan_sigma)
     assert p.last_search_tile() >= 0
     _check_detect(orc, yo, n, sorted(widths), wl.chan_mean, wl.chan_sigma, snr, t, W)
+
+
+@pytest.mark.parametrize("ntap,fused", [(80, True), (90, False)])
+def test_extreme_samples_near_int32_limits(dd, orc, opar, ntap, fused):
+    # Saturated and alternating-extreme uint8 blocks on a plan whose sums come close to
+    # the int32 limits the fused search accepts (255 * sum_c ntap * 49 < 2^30): 1024
+    # channels of 80 samples (fused search, both int8 extremes through the x - 128
+    # correction) and of 90 samples (beyond the fused search's limit: the unfused path),
+    # against the oracle bit for bit.
+    rng = np.random.default_rng(5150 + ntap)
+    C, D = 1024, 64
+    f = workloads.channel_centres(1.2, 0.3, C)
+    s = np.sort(rng.integers(0, 40, size=(D, C)), axis=0).astype(np.int32)
+    n = np.full((D, C), ntap, dtype=np.int32)
+    p = dd.Plan(f, 0.3 / C, 1e-3, np.arange(D, dtype=np.float64), rule="explicit", start=s,
+                ntap=n)
+    span = int(np.max(s + n))
+    T = span + 600
+    widths = list(range(1, 33))
+    mu, sg = np.full(C, 127.5), np.full(C, 40.0)
+    blocks = [np.full((C, T), 255, np.uint8), np.zeros((C, T), np.uint8),
+              np.where(rng.random((C, T)) < 0.5, 0, 255).astype(np.uint8)]
+    for x in blocks:
+        xd = _dev(x)
+        yo = opar.dedisperse_u8(x, s, n, tout=T - span + 1)
+        assert np.array_equal(p.dedisperse(xd).cpu().numpy().astype(np.int64), yo)
+        snr, t, W = p.search(xd, widths, mu, sg)
+        assert (p.last_search_tile() >= 0) == fused
+        _check_detect(orc, yo.astype(np.float64), n, widths, mu, sg, snr, t, W)
