@@ -1312,26 +1312,58 @@ extern "C" dedisp_status dedisp_autotune(dedisp_plan p, const void *d_in, int64_
   std::vector<hipEvent_t> es, et;
   es.swap(p->ev_start);
   et.swap(p->ev_stop);
+  // milliseconds of 3 searches in shape ci (after one untimed call when warm is set)
+  auto time3 = [&](int ci, bool warm, float *ms) -> dedisp_status {
+    dedisp_status r = DEDISP_OK;
+    if (warm) {
+      r = search_ci(p, ci, (const uint8_t *)d_in, nsamp, in_stride, nout, wl, d_chan_mean,
+                    d_chan_sigma, snr, tt, ww, d_work, s);
+      if (r != DEDISP_OK) return r;
+    }
+    hipError_t e = hipEventRecord(e0, s);
+    for (int k = 0; k < 3 && e == hipSuccess && r == DEDISP_OK; ++k)
+      r = search_ci(p, ci, (const uint8_t *)d_in, nsamp, in_stride, nout, wl, d_chan_mean,
+                    d_chan_sigma, snr, tt, ww, d_work, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    if (e != hipSuccess && r == DEDISP_OK) r = hip_fail(e, "autotune timing");
+    return r;
+  };
+  std::vector<double> first(num_candidates(), -1.0);
   for (int ci = 0; ci < num_candidates() && st == DEDISP_OK; ++ci) {
-    st = search_ci(p, ci, (const uint8_t *)d_in, nsamp, in_stride, nout, wl, d_chan_mean,
-                   d_chan_sigma, snr, tt, ww, d_work, s);
+    float ms = 0;
+    st = time3(ci, true, &ms);
     if (st == DEDISP_ERR_UNSUPPORTED) {
       st = DEDISP_OK;
       continue;
     }
     if (st != DEDISP_OK) break;
-    hipError_t e = hipEventRecord(e0, s);
-    for (int r = 0; r < 3 && e == hipSuccess && st == DEDISP_OK; ++r)
-      st = search_ci(p, ci, (const uint8_t *)d_in, nsamp, in_stride, nout, wl, d_chan_mean,
-                     d_chan_sigma, snr, tt, ww, d_work, s);
-    if (e == hipSuccess) e = hipEventRecord(e1, s);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float ms = 0;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e != hipSuccess) st = hip_fail(e, "autotune timing");
-    if (st == DEDISP_OK && ms < best_ms) {
+    first[ci] = ms;
+    if (ms < best_ms) {
       best_ms = ms;
       best = ci;
+    }
+  }
+  // the shapes within 3 % of the fastest are timed again, interleaved, twice more (so
+  // that a drift of the clocks during the first pass does not decide between them)
+  std::vector<int> close;
+  for (int ci = 0; ci < num_candidates() && st == DEDISP_OK; ++ci)
+    if (first[ci] >= 0 && first[ci] <= 1.03 * best_ms) close.push_back(ci);
+  if (st == DEDISP_OK && close.size() > 1) {
+    std::vector<double> tot(close.size(), 0.0);
+    for (int round = 0; round < 2 && st == DEDISP_OK; ++round)
+      for (size_t i = 0; i < close.size() && st == DEDISP_OK; ++i) {
+        float ms = 0;
+        st = time3(close[i], false, &ms);
+        tot[i] += ms;
+      }
+    if (st == DEDISP_OK) {
+      size_t bi = 0;
+      for (size_t i = 1; i < close.size(); ++i)
+        if (tot[i] < tot[bi]) bi = i;
+      best = close[bi];
+      best_ms = tot[bi] / 2.0;
     }
   }
   es.swap(p->ev_start);
