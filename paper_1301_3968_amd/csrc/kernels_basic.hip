@@ -180,7 +180,8 @@ __device__ __forceinline__ void norm_terms(int wmode, int K, const float *__rest
   }
 }
 
-// Noise statistics of every (trial, width).  One workgroup per kNormTrials trials;
+// Noise statistics of every (trial, width), for tap weights or widths above 63 (the
+// bucketed kernel below takes the rest).  One workgroup per kNormTrials trials;
 // per trial, 32 width lanes (each taking widths j and j + 32) times kNormSplit
 // channel residues.  The trials' tap counts and the channel statistics are staged
 // in LDS a chunk of channels at a time; the kNormSplit partial sums of a (trial,
@@ -275,6 +276,103 @@ k_norm(const int32_t *__restrict__ ntap, int32_t nchan, int32_t ndm, int32_t wmo
     M[(int64_t)d * wl.n + j] = mm;
     S[(int64_t)d * wl.n + j] = sqrt(vv);
   }
+}
+
+// Noise statistics for unit or per-channel weights and widths up to kBucketMaxW, by
+// tap-count buckets.  For a channel taking n samples, the length-W boxcar of the
+// dedispersed series weights its samples by the n-box convolved with the W-box, whose
+// sum of squares is q(W, n) = L^2 H + b(L) with L = min(W, n), H = max(W, n) and
+// b(L) = L^2 - L^3 + (L - 1) L (2L - 1) / 3 (the same for either order).  So
+//     M[W] = W sum_c m_c n_c,   S[W]^2 = sum_c v_c q(W, n_c),
+// with m_c = w_c mu_c, v_c = (w_c sigma_c)^2, and the channels with equal n < 64 can be
+// summed first; those with n >= 64 exceed every width (q = W^2 n + b(W)) and enter
+// through sum v_c n_c and sum v_c.  One workgroup per trial, its 4 waves taking a
+// quarter of the channels each, a chunk at a time: the lanes first take one channel
+// each (m_c n_c and the n >= 64 sums, and (n_c, v_c) into LDS), then lane k adds v_c
+// over the chunk's channels with n_c = k.  Every sum runs in a fixed order, so results
+// do not vary between runs.
+constexpr int kBucketMaxW = 63, kBucketWaves = 4, kBucketChunk = 256;
+
+__device__ __forceinline__ int bucket_q(int W, int n) {   // q(W, n) for W, n <= 63
+  const int L = min(W, n), H = max(W, n);
+  return L * L * H + L * L - L * L * L + (L - 1) * L * (2 * L - 1) / 3;
+}
+
+__device__ __forceinline__ double wave_sum(double x) {   // fixed butterfly order
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+  return x;
+}
+
+__global__ void __launch_bounds__(64 * kBucketWaves)
+k_norm_buckets(const int32_t *__restrict__ ntap, int32_t nchan, int32_t wmode,
+               const float *__restrict__ w, const double *__restrict__ mu,
+               const double *__restrict__ sigma, WidthList wl, double *__restrict__ M,
+               double *__restrict__ S) {
+  __shared__ double cv[kBucketWaves][kBucketChunk];
+  __shared__ int32_t cn[kBucketWaves][kBucketChunk];
+  __shared__ double sv[kBucketWaves][64];
+  __shared__ double sd[kBucketWaves][3];
+  const int lane = threadIdx.x & 63;
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int d = blockIdx.x;
+  const int32_t *nrow = ntap + (int64_t)d * nchan;
+  const int per = (nchan + kBucketWaves - 1) / kBucketWaves;
+  const int cb = min(nchan, q * per), ce = min(nchan, cb + per);
+  double smn = 0.0, svn = 0.0, sv0 = 0.0, bv = 0.0;
+  for (int c0 = cb; c0 < ce; c0 += kBucketChunk) {
+    const int len = min(kBucketChunk, ce - c0);
+    for (int i = lane; i < len; i += 64) {
+      const int c = c0 + i, n = nrow[c];
+      const double wc = wmode == DEDISP_W_CHANNEL ? (double)w[c] : 1.0;
+      const double sg = sigma[c] * wc, v = sg * sg;
+      smn += mu[c] * wc * (double)n;
+      if (n >= 64) {
+        svn += v * (double)n;
+        sv0 += v;
+      }
+      cv[q][i] = v;
+      cn[q][i] = n;
+    }
+    // LDS operations of one wave complete in order: the reads below see the writes
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll 8
+    for (int i = 0; i < len; ++i) bv += (cn[q][i] == lane && lane != 0) ? cv[q][i] : 0.0;
+    __builtin_amdgcn_wave_barrier();
+  }
+  smn = wave_sum(smn);
+  svn = wave_sum(svn);
+  sv0 = wave_sum(sv0);
+  sv[q][lane] = bv;
+  if (lane == 0) {
+    sd[q][0] = smn;
+    sd[q][1] = svn;
+    sd[q][2] = sv0;
+  }
+  __syncthreads();
+  if (q != 0) return;
+  double tot = 0.0, msum = 0.0, vn = 0.0, v0 = 0.0;
+#pragma unroll
+  for (int r = 0; r < kBucketWaves; ++r) {
+    tot += sv[r][lane];
+    msum += sd[r][0];
+    vn += sd[r][1];
+    v0 += sd[r][2];
+  }
+  __builtin_amdgcn_wave_barrier();
+  sv[0][lane] = tot;   // bucket totals (wave 0 alone reads and writes row 0 now)
+  __builtin_amdgcn_wave_barrier();
+  // the highest tap count below 64 that any channel takes (buckets above it are empty)
+  const uint64_t used = __ballot(lane != 0 && tot != 0.0);
+  const int kmax = used ? 63 - __builtin_clzll(used) : 0;
+  // lane j takes width j (the list has at most 64 entries)
+  if (lane >= wl.n) return;
+  const int W = wl.w[lane];
+  const int bW = W * W - W * W * W + (W - 1) * W * (2 * W - 1) / 3;
+  double v = (double)(W * W) * vn + (double)bW * v0;
+  for (int k = 1; k <= kmax; ++k) v += (double)bucket_q(W, k) * sv[0][k];
+  M[(int64_t)d * wl.n + lane] = (double)W * msum;
+  S[(int64_t)d * wl.n + lane] = sqrt(v);
 }
 
 struct Cand {
@@ -739,6 +837,13 @@ hipError_t launch_dedisp_1tap_f32(const dedisp_plan_s *p, const float *z, int64_
 
 hipError_t launch_norm(const dedisp_plan_s *p, const WidthList &wl, const double *mu,
                        const double *sigma, double *M, double *S, hipStream_t s) {
+  int wmax = 0;
+  for (int i = 0; i < wl.n; ++i) wmax = wl.w[i] > wmax ? wl.w[i] : wmax;
+  if (p->wmode != DEDISP_W_TAP && wmax <= kBucketMaxW) {
+    hipLaunchKernelGGL(k_norm_buckets, dim3((unsigned)p->ndm), dim3(64 * kBucketWaves), 0, s,
+                       p->dev.ntap, p->nchan, p->wmode, weights_of(p), mu, sigma, wl, M, S);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_norm, dim3((unsigned)((p->ndm + kNormTrials - 1) / kNormTrials)), dim3(kNormThreads), 0, s,
                      p->dev.ntap, p->nchan, p->ndm, p->wmode, p->ktaps, weights_of(p), mu, sigma,
                      wl, M, S);

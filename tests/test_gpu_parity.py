@@ -439,3 +439,42 @@ def test_extreme_samples_near_int32_limits(dd, orc, opar, ntap, fused):
         snr, t, W = p.search(xd, widths, mu, sg)
         assert (p.last_search_tile() >= 0) == fused
         _check_detect(orc, yo.astype(np.float64), n, widths, mu, sg, snr, t, W)
+
+
+@pytest.mark.parametrize("wmode,widths", [("unit", [1, 2, 7, 63]), ("unit", [1, 5, 64, 100, 250]),
+                                          ("channel", list(range(1, 33))),
+                                          ("tap", [1, 3, 8, 17])])
+def test_detect_noise_tables_every_weight_mode(dd, orc, wmode, widths):
+    # Detection of a given dedispersed series under every weight mode and width range
+    # (the noise tables by tap-count buckets for unit and channel weights up to width 63,
+    # the general ones for tap weights and wider boxcars): the GPU's series is handed to
+    # the oracle's detector with the oracle's noise tables.
+    rng = np.random.default_rng(909)
+    C, D, T = 48, 24, 1500
+    f = workloads.channel_centres(1.2, 0.048, C)
+    dms = np.linspace(0.0, 300.0, D)
+    w = None
+    if wmode == "tap":
+        K = 4
+        w = (1.0 + 0.2 * rng.standard_normal((C, K))).astype(np.float32)
+        p = dd.Plan(f, 0.001, 1e-3, dms, rule="fixed", ktaps=K, wmode="tap", weights=w)
+    elif wmode == "channel":
+        w = ((f / 1.2) ** -1.5).astype(np.float32)
+        p = dd.Plan(f, 0.001, 1e-3, dms, rule="smear", wmode="channel", weights=w)
+    else:
+        p = dd.Plan(f, 0.001, 1e-3, dms, rule="allnonzero")
+    s, n = p.tables()
+    x = rng.integers(0, 256, size=(C, T), dtype=np.uint8)
+    y = p.dedisperse(_dev(x))
+    mu = 100.0 + 10.0 * rng.random(C)
+    sg = 10.0 + 5.0 * rng.random(C)
+    snr, t, W = p.detect(y, widths, mu, sg)
+    y64 = y.cpu().numpy().astype(np.float64)
+    M, S = orc.boxcar_norm(n, widths, mu, sg, wmode, w)
+    so, to, wo = orc.boxcar_detect(y64, widths, M, S)
+    snr, t, W = snr.cpu().numpy(), t.cpu().numpy(), W.cpu().numpy()
+    assert np.allclose(snr, so, rtol=1e-9, atol=0)
+    for d in np.nonzero((t != to) | (W != wo))[0]:
+        j = list(widths).index(int(W[d]))
+        B = float(np.sum(y64[d, t[d]:t[d] + W[d]]))
+        assert (B - M[d, j]) / S[d, j] == pytest.approx(so[d], rel=1e-9)
