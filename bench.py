@@ -205,8 +205,8 @@ def cpu_baseline_taps(wl, nbatch: int = 16, ntrials: int = 32):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--rule", default="allnonzero", choices=["allnonzero", "smear"])
     ap.add_argument("--cpu-sample-trials", type=int, default=64,
                     help="trials of the single-threaded oracle sample")
@@ -321,7 +321,7 @@ def main() -> int:
     # sum.  The fraction is taken against the peak of the unit the kernel runs on: the
     # dense int8 matrix-core rate for the matrix-core kernel, the int32 vector lane-op
     # rate for the packed-add kernel.
-    fused = os.environ.get("DEDISP_BENCH_UNFUSED") is None and _fused(plan)
+    fused = _fused(plan)
     ops = sums + (2.0 * D * nout * nw if fused else 0.0)
     kern_s = kern_ms * 1e-3
     mfma = fused and tile >= NUM_PACKED_SHAPES
