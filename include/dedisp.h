@@ -150,7 +150,8 @@ dedisp_status dedisp_dedisperse(dedisp_plan plan, const void *d_in, int32_t in_d
  * [ndm], initialised by the caller to (-inf, -1, 0).  t_offset >= 0 is the stream
  * index of the block's first output.  A block that overlaps the previous one by
  * max_span - 1 + W_max - 1 samples searches every window of the stream at least once,
- * and the running best then equals the search of the whole stream. */
+ * and the running best then equals the search of the whole stream.  Enqueued on
+ * `stream`; DEDISP_ERR_INVALID_ARG for ndm <= 0, a null array or a negative t_offset. */
 dedisp_status dedisp_merge_candidates(int32_t ndm, const double *d_snr_b, const int32_t *d_t_b,
                                       const int32_t *d_w_b, int64_t t_offset, double *d_snr,
                                       int64_t *d_t, int32_t *d_w, void *stream);
