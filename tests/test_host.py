@@ -223,3 +223,15 @@ def test_plan_log_line():
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
                        cwd=ROOT, env=env)
     assert r.returncode == 0 and "dedisp:" not in r.stderr
+
+
+def test_merge_candidates_rejects_bad_arguments():
+    # Argument checks of the stream merge run on the host, before anything is enqueued.
+    import ctypes
+    from paper_1301_3968_amd import _lib
+    L = _lib.lib()
+    p = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails its checks
+    assert L.dedisp_merge_candidates(0, p, p, p, 0, p, p, p, None) == _lib.ERR_INVALID_ARG
+    assert L.dedisp_merge_candidates(4, None, p, p, 0, p, p, p, None) == _lib.ERR_INVALID_ARG
+    assert L.dedisp_merge_candidates(4, p, p, p, -1, p, p, p, None) == _lib.ERR_INVALID_ARG
+    assert b"t_offset" in L.dedisp_last_error()
