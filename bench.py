@@ -247,7 +247,7 @@ def main() -> int:
             print(f"probe_lds failed with status {out.returncode}", file=sys.stderr)
             return out.returncode
         rates = [json.loads(ln) for ln in out.stdout.splitlines() if ln.startswith("{")]
-        print(json.dumps({"metric": "LDS read bytes per clock per CU (16-byte lane reads)",
+        print(json.dumps({"metric": "LDS read bytes per clock per CU (16- and 8-byte lane reads)",
                           "unit": "B/clk/CU", "n_gpus": 1, "higher_is_better": True,
                           "data": "synthetic", "patterns": rates}))
         return 0

@@ -1,6 +1,7 @@
 // LDS read rate of the lane address patterns the matrix-core search's operand reads can
-// take: every lane reads 16 bytes (ds_read_b128), 8 reads in flight per wave, 8 waves
-// per workgroup, 2 workgroups per CU, all addresses inside a 64 KiB shared array.
+// take: every lane reads 16 bytes (ds_read_b128; the last pattern 8 bytes, ds_read_b64),
+// 8 reads in flight per wave, 8 waves per workgroup, 2 workgroups per CU, all addresses
+// inside a 64 KiB shared array.
 // Prints one JSON line per pattern: bytes per clock per CU, taking the 2.4 GHz engine
 // clock.  A measurement program (not part of the library): built beside it, run by the
 // benchmark's "lds" workload.
@@ -11,8 +12,9 @@
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v2i __attribute__((ext_vector_type(2)));
 
-constexpr int kPatterns = 6;
+constexpr int kPatterns = 7;
 const char *const kPatternText[kPatterns] = {
     "1 KiB contiguous (lane l at 16 l)",
     "two 512-byte halves 16 bytes out of step (lane 32 g + n at 16 n + 1040 g)",
@@ -21,6 +23,7 @@ const char *const kPatternText[kPatterns] = {
     "16 ((5 g + 3) mod 16))",
     "four 256-byte quarters in step (lane 16 g + n at 16 n + 1024 g)",
     "64-byte lane stride (lane l at 64 l)",
+    "8-byte reads, 512 bytes contiguous (lane l at 8 l)",
 };
 
 __device__ __forceinline__ int lane_offset(int pat, int lane) {
@@ -31,7 +34,8 @@ __device__ __forceinline__ int lane_offset(int pat, int lane) {
     case 2: return 16 * n32 + 1024 * g2;
     case 3: return 16 * n16 + 1024 * g4 + 16 * ((5 * g4 + 3) & 15);
     case 4: return 16 * n16 + 1024 * g4;
-    default: return 64 * lane;
+    case 5: return 64 * lane;
+    default: return 8 * lane;
   }
 }
 
@@ -44,14 +48,29 @@ __global__ void __launch_bounds__(512) k_lds_rate(int pat, int iters, int *sink)
   const int lane = threadIdx.x & 63;
   const int a = lane_offset(pat, lane) + 8192 * ((threadIdx.x >> 6) & 1) + 16384;
   v4i acc = {0, 0, 0, 0};
-  for (int it = 0; it < iters; ++it) {
-    int ai = a;
-    asm volatile("" : "+v"(ai));   // the address is opaque, so every iteration reads
-    v4i v[8];
+  if (pat == kPatterns - 1) {   // 8-byte reads
+    v2i acc2 = {0, 0};
+    for (int it = 0; it < iters; ++it) {
+      int ai = a;
+      asm volatile("" : "+v"(ai));
+      v2i v[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = *(const v4i *)(lds + ai + 4096 * j);
+      for (int j = 0; j < 8; ++j) v[j] = *(const v2i *)(lds + ai + 4096 * j);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc += v[j];
+      for (int j = 0; j < 8; ++j) acc2 += v[j];
+    }
+    acc[0] = acc2[0];
+    acc[1] = acc2[1];
+  } else {
+    for (int it = 0; it < iters; ++it) {
+      int ai = a;
+      asm volatile("" : "+v"(ai));   // the address is opaque, so every iteration reads
+      v4i v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = *(const v4i *)(lds + ai + 4096 * j);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc += v[j];
+    }
   }
   if (acc[0] == 12345 && acc[1] == 678) sink[threadIdx.x] = acc[2];   // keeps the reads
 }
@@ -73,7 +92,7 @@ int main() {
     if (hipEventRecord(e1) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return 1;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return 1;
-    const double bytes = (double)blocks * 512 * 16 * 8 * iters;
+    const double bytes = (double)blocks * 512 * (pat == kPatterns - 1 ? 8 : 16) * 8 * iters;
     printf("{\"pattern\": %d, \"lanes\": \"%s\", \"ms\": %.4f, \"bytes_per_clk_per_cu\": %.1f}\n",
            pat, kPatternText[pat], ms, bytes / (ms * 1e-3) / cus / 2.4e9);
   }
