@@ -23,10 +23,11 @@
 // half of it).  A wave takes 4 trials x NP products of 256 consecutive outputs;
 // segments are put on an 8-byte grid (their band covers start .. start + ntap + 7 for
 // the phases).  Channel groups are staged while the previous group is multiplied (two
-// LDS buffers).  The host plans, per pair of segments (a K block), a 144-byte record:
-// the 16-bit mask of every (trial, phase) row and segment, and the LDS base address of
-// each segment; the records of a channel group are copied into LDS with the windows,
-// and every lane forms its 16 mask bytes and its read address from them.
+// LDS buffers).  The host plans, per pair of segments (a K block), a 48-byte record:
+// per segment and trial a 32-bit run mask (bit j set when window byte o_g - 8 + j lies in
+// the trial's run; phase u takes bits 8 - u .. 23 - u), and the LDS base address of each
+// segment; the records of a channel group are copied into LDS with the windows, and every
+// lane forms its 16 mask bytes and its read address from them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -66,10 +67,13 @@ constexpr int kMfmaBufBytes = 80 * 1024;    // LDS per staging buffer (two per w
                                             // one workgroup per CU
 constexpr int kSlotBytes = 16;              // the end of the second buffer, never staged into:
                                             // the persistent batch's item broadcast
-// K-block record: 64 x u16 masks (lane = 32 segment + row, row = 8 trial + phase), then
-// the LDS byte address of each of the 2 segments' first window byte (region + 2 o_g;
-// lane 32 g + n reads 16 bytes at address[g] + 16 n + 512 q for product q), padding
-constexpr int kRecBytes = 144;
+// K-block record: 8 x u32 run masks (index 4 g + trial for segment g; bit j: window byte
+// o_g - 8 + j is in the trial's run), then the LDS byte address of each of the 2 segments'
+// first window byte (region + 2 o_g; lane 32 g + n reads 16 bytes at address[g] + 16 n +
+// 512 q for product q), padding to a multiple of 16 bytes
+constexpr int kRecBytes = 48;
+constexpr int kRecBase = 32;                // byte offset of the segment addresses
+static_assert(kRecBytes % 16 == 0 && kRecBase + 8 <= kRecBytes, "records copied in 16-byte chunks");
 // Staging: up to kUnitsPerThread chunks (16 window bytes in both copies) per thread and
 // group, so a group stages at most 64 NW kUnitsPerThread chunks (registers: the chunks'
 // raw bytes are held through the current group's products).
@@ -278,6 +282,10 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
   __syncthreads();
   // the lane's byte offset from a segment's base: column lane mod 32 of the wave's run
   const int loff = 16 * (lane & 31) + 2 * kOutsPerProduct * NP * wt;
+  // the lane's run mask in a record (segment lane / 32, trial (lane mod 32) / 8) and the
+  // bit of it that is mask byte 0 (8 - phase)
+  const int moff = 16 * (lane >> 5) + 4 * ((lane & 31) >> 3);
+  const uint32_t msh = 8 - (lane & 7);
   for (int g = gb; g < ge; ++g) {
     const int par = (g - gb) & 1;
     unsigned char *buf = lds + par * a.bufbytes;
@@ -296,21 +304,22 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
     uint32_t m_next = 0;
     int32_t b_next = 0;
     if (k0 < k1) {
-      m_next = *(const uint16_t *)(rb + 2 * lane);
-      b_next = *(const int32_t *)(rb + 128 + 4 * (lane >> 5));
+      m_next = *(const uint32_t *)(rb + moff);
+      b_next = *(const int32_t *)(rb + kRecBase + 4 * (lane >> 5));
     }
     for (int kb = k0; kb < k1; ++kb, rb += kRecBytes) {
-      const uint32_t m16 = m_next;
+      const uint32_t m32 = m_next;
       const unsigned char *bp = buf + b_next + loff;
       if (kb + 1 < k1) {
-        m_next = *(const uint16_t *)(rb + kRecBytes + 2 * lane);
-        b_next = *(const int32_t *)(rb + kRecBytes + 128 + 4 * (lane >> 5));
+        m_next = *(const uint32_t *)(rb + kRecBytes + moff);
+        b_next = *(const int32_t *)(rb + kRecBytes + kRecBase + 4 * (lane >> 5));
       }
-      // 16 mask bytes of lane (row lane % 32, segment lane / 32): bit j -> byte j
+      // 16 mask bytes of lane (row lane % 32 = trial 8 m + phase u, segment lane / 32):
+      // byte j is bit 8 - u + j of the run mask
       v4i mk;
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        mk[k] = (int32_t)((((m16 >> (4 * k)) & 15u) * 0x204081u) & 0x01010101u);
+        mk[k] = (int32_t)((__builtin_amdgcn_ubfe(m32, msh + 4 * k, 4) * 0x204081u) & 0x01010101u);
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
         const v4i bq = *(const v4i *)(bp + 2 * kOutsPerProduct * q);
@@ -652,20 +661,19 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
             const int cc = segs[si].first, o = segs[si].second;
             // window byte o (a multiple of 8) of the interleaved copies is at region + 2 o
             const int32_t ad = region[cc] + 2 * o;
-            std::memcpy(rec.data() + 128 + 4 * g, &ad, 4);
+            std::memcpy(rec.data() + kRecBase + 4 * g, &ad, 4);
             if (s0 + g >= segs.size()) continue;
             const int oa = wlo[cc] + o;   // absolute delay of the segment's first byte
             for (int m = 0; m < TPW; ++m) {
               const int d = out.perm[(size_t)tw * DT + TPW * w + m];
               if (d < 0) continue;
               const int st = p->start[(size_t)d * C + cc], nt = p->ntap[(size_t)d * C + cc];
-              for (int u = 0; u < kPhases; ++u) {
-                // row (trial m, phase u) takes byte j when its delay less u is in the run
-                uint16_t bits = 0;
-                for (int j = 0; j < 16; ++j)
-                  if (oa + j - u >= st && oa + j - u < st + nt) bits |= (uint16_t)(1u << j);
-                std::memcpy(rec.data() + 2 * (32 * g + kPhases * m + u), &bits, 2);
-              }
+              // bit j: delay oa - 8 + j is in the run (row (m, u) takes byte i when delay
+              // oa + i - u is, i.e. bit i + 8 - u)
+              uint32_t bits = 0;
+              for (int j = 0; j < 32; ++j)
+                if (oa - 8 + j >= st && oa - 8 + j < st + nt) bits |= 1u << j;
+              std::memcpy(rec.data() + 4 * (4 * g + m), &bits, 4);
             }
           }
           out.recs.insert(out.recs.end(), rec.begin(), rec.end());
