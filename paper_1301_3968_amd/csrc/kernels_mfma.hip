@@ -416,6 +416,8 @@ __device__ __forceinline__ void search_tile_mfma(SA &sa, int tt, int tw, unsigne
   constexpr int ROWS = PT * NWD;           // rows of one pass
   static_assert(TW % 64 == 0 && TT % SP == 0 && TW - TT >= 31, "search tile");
   static_assert(ROWS % NW == 0, "whole rows per wave");
+  constexpr bool kOwnRows = NWT == 1 && ROWS / NW == PT;   // wave w searches rows PT w ..
+  static_assert(!kOwnRows || NW == NWD, "one wave along time");
   static_assert(ROWS * YROW * 4 <= 2 * (kMfmaBufBytes / WG) - kSlotBytes,
                 "rows of one pass fit the LDS (less the item slot)");
   static_assert(YROW % 4 == 0, "16-byte aligned rows");
@@ -440,7 +442,11 @@ __device__ __forceinline__ void search_tile_mfma(SA &sa, int tt, int tw, unsigne
         *(v4i *)(row + kOutsPerProduct * q) =
             quad_of<NP>(acc, q, PT * pass + m) + (v4i){corr, corr, corr, corr};
     }
-    __syncthreads();
+    // With one wave along time each wave searches the rows it wrote (rows PT wd ..
+    // PT wd + PT - 1), so only its own LDS operations, which complete in order, need
+    // to be ordered; rows of several time waves need the workgroup barrier.
+    if constexpr (kOwnRows) __builtin_amdgcn_wave_barrier();
+    else __syncthreads();
     // one row at a time, not unrolled: the search code then stays small enough
     // for the instruction cache
 #pragma unroll 1
@@ -452,7 +458,10 @@ __device__ __forceinline__ void search_tile_mfma(SA &sa, int tt, int tw, unsigne
           boxcar_row<SP>(Y + rw * YROW, lane, T0, TT, a.nout, dg, sa.wmask, sa.nw, sa.M, sa.S);
       if (dg >= 0 && lane == 0) sa.part[(int64_t)dg * a.ntt + tt] = rec;
     }
-    __syncthreads();
+    // the LDS is free for the next pass's rows (or the next tile) once every wave that
+    // reads these rows is done
+    if (kOwnRows && pass == 0) __builtin_amdgcn_wave_barrier();
+    else __syncthreads();
   }
 }
 
