@@ -141,8 +141,20 @@ hipError_t launch_fir_f32(const dedisp_plan_s *p, const float *x, int64_t in_str
 hipError_t launch_dedisp_1tap_f32(const dedisp_plan_s *p, const float *z, int64_t zstride,
                                   int64_t zbstride, int32_t nbatch, int64_t nout, float *y,
                                   int64_t out_stride, int64_t out_bstride, hipStream_t s);
+// The converted block the matrix-core search's direct staging reads: xs[c][t] =
+// x[c][t] ^ 0x80 for t < nsamp, 0x80 up to the row length xs_stride (a multiple of 16).
+struct ConvertJob {
+  const uint8_t *x;
+  int64_t in_stride, nsamp;
+  uint8_t *xs;
+  int64_t xs_stride;
+  int32_t nchan;
+};
+// Noise tables M, S [ndm][nw]; with cv, the same launch (extra workgroups) also writes
+// the converted block.
 hipError_t launch_norm(const dedisp_plan_s *p, const WidthList &wl, const double *mu,
-                       const double *sigma, double *M, double *S, hipStream_t s);
+                       const double *sigma, double *M, double *S, hipStream_t s,
+                       const ConvertJob *cv = nullptr);
 hipError_t launch_boxcar(const dedisp_plan_s *p, const void *y, int32_t y_dtype, int64_t nout,
                          int64_t y_stride, const WidthList &wl, const double *M, const double *S,
                          void *partials, int32_t nchunk, hipStream_t s);
@@ -204,7 +216,7 @@ size_t mfma_search_work_bytes(const dedisp_plan_s *p, int32_t nw, int64_t nout);
 dedisp_status run_search_mfma(dedisp_plan p, int k, const uint8_t *x, int64_t nsamp,
                               int64_t in_stride, int64_t nout, const WidthList &wl,
                               const double *mu, const double *sigma, double *snr, int32_t *t,
-                              int32_t *w, void *work, hipStream_t s);
+                              int32_t *w, void *work, hipStream_t s, bool dma = true);
 // Fused search of a uint8 block with unit weights on the matrix cores, with the
 // library's per-device scratch array as its workspace (kernels_mfma.hip): allocates
 // nothing; fails when the plan's device tables are not built yet or the workspace

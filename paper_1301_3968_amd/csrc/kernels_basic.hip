@@ -304,11 +304,51 @@ __device__ __forceinline__ double wave_sum(double x) {   // fixed butterfly orde
   return x;
 }
 
+// Workgroup j of the conversion (256 threads, 16 bytes each): row j / per_row, bytes
+// 4096 (j mod per_row) .. of the converted block.
+constexpr int kConvThreads = 256;
+__device__ __forceinline__ void convert_block(const ConvertJob &cv, int64_t j, int64_t per_row) {
+  const int64_t c = j / per_row;
+  const int64_t p = 16 * ((j - c * per_row) * kConvThreads + threadIdx.x);
+  if (p >= cv.xs_stride) return;
+  const uint8_t *row = cv.x + c * cv.in_stride;
+  uint32_t v[4];
+  if (p + 16 <= cv.nsamp && ((uintptr_t)(row + p) & 3) == 0) {
+    const __attribute__((address_space(1))) uint32_t *r =
+        (const __attribute__((address_space(1))) uint32_t *)(row + p);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = r[k] ^ 0x80808080u;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      uint32_t u = 0;
+      for (int i = 0; i < 4; ++i) {
+        const int64_t q = p + 4 * k + i;
+        u |= (uint32_t)((q < cv.nsamp ? row[q] : 0) ^ 0x80) << (8 * i);
+      }
+      v[k] = u;
+    }
+  }
+  typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+  *(v4u *)(cv.xs + c * cv.xs_stride + p) = (v4u){v[0], v[1], v[2], v[3]};
+}
+
+__global__ void __launch_bounds__(kConvThreads) k_convert_u8(ConvertJob cv, int64_t per_row) {
+  convert_block(cv, blockIdx.x, per_row);
+}
+
+// Workgroups 0 .. ndm - 1: the noise tables of trial blockIdx.x; workgroups from ndm on
+// (when cv.xs is set): the conversion, workgroup ndm + j taking conversion block j.
 __global__ void __launch_bounds__(64 * kBucketWaves)
 k_norm_buckets(const int32_t *__restrict__ ntap, int32_t nchan, int32_t wmode,
                const float *__restrict__ w, const double *__restrict__ mu,
                const double *__restrict__ sigma, WidthList wl, double *__restrict__ M,
-               double *__restrict__ S) {
+               double *__restrict__ S, int32_t ndm, ConvertJob conv, int64_t per_row) {
+  static_assert(64 * kBucketWaves == kConvThreads, "one workgroup shape for both roles");
+  if ((int)blockIdx.x >= ndm) {   // the whole workgroup, before any barrier
+    convert_block(conv, (int64_t)blockIdx.x - ndm, per_row);
+    return;
+  }
   __shared__ double cv[kBucketWaves][kBucketChunk];
   __shared__ int32_t cn[kBucketWaves][kBucketChunk];
   __shared__ double sv[kBucketWaves][64];
@@ -836,17 +876,32 @@ hipError_t launch_dedisp_1tap_f32(const dedisp_plan_s *p, const float *z, int64_
 }
 
 hipError_t launch_norm(const dedisp_plan_s *p, const WidthList &wl, const double *mu,
-                       const double *sigma, double *M, double *S, hipStream_t s) {
+                       const double *sigma, double *M, double *S, hipStream_t s,
+                       const ConvertJob *cv) {
   int wmax = 0;
   for (int i = 0; i < wl.n; ++i) wmax = wl.w[i] > wmax ? wl.w[i] : wmax;
+  ConvertJob conv{};
+  int64_t per_row = 1, nconv = 0;
+  if (cv) {
+    conv = *cv;
+    per_row = (conv.xs_stride / 16 + kConvThreads - 1) / kConvThreads;
+    nconv = per_row * conv.nchan;
+    if (nconv + p->ndm > 0x7fffffff) return hipErrorInvalidValue;
+  }
   if (p->wmode != DEDISP_W_TAP && wmax <= kBucketMaxW) {
-    hipLaunchKernelGGL(k_norm_buckets, dim3((unsigned)p->ndm), dim3(64 * kBucketWaves), 0, s,
-                       p->dev.ntap, p->nchan, p->wmode, weights_of(p), mu, sigma, wl, M, S);
+    hipLaunchKernelGGL(k_norm_buckets, dim3((unsigned)(p->ndm + nconv)), dim3(64 * kBucketWaves),
+                       0, s, p->dev.ntap, p->nchan, p->wmode, weights_of(p), mu, sigma, wl, M, S,
+                       p->ndm, conv, per_row);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_norm, dim3((unsigned)((p->ndm + kNormTrials - 1) / kNormTrials)), dim3(kNormThreads), 0, s,
                      p->dev.ntap, p->nchan, p->ndm, p->wmode, p->ktaps, weights_of(p), mu, sigma,
                      wl, M, S);
+  if (nconv > 0) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_convert_u8, dim3((unsigned)nconv), dim3(kConvThreads), 0, s, conv, per_row);
+  }
   return hipGetLastError();
 }
 

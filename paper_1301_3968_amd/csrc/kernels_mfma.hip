@@ -22,8 +22,14 @@
 // alignment to each other; four quarter-wave runs at different alignments run at about
 // half of it).  A wave takes 4 trials x NP products of 256 consecutive outputs;
 // segments are put on an 8-byte grid (their band covers start .. start + ntap + 7 for
-// the phases).  Channel groups are staged while the previous group is multiplied (two
-// LDS buffers).  The host plans, per pair of segments (a K block), a 48-byte record:
+// the phases; a channel's window starts at a multiple of 8 of the delay).  Channel groups
+// are staged while the previous group is multiplied (two LDS buffers): in the fused
+// search from a converted copy of the block (x ^ 0x80, written by the noise-table launch)
+// with buffer-to-LDS loads, 16 bytes a lane, so that piece m of a region (its 16 bytes
+// at region + 16 m) is one load of window bytes 8 m .. 8 m + 15; in the dedispersion and
+// the multi-beam search from x through registers (aligned loads, byte shifts, the
+// conversion, two LDS stores).  The host plans, per pair of segments (a K block), a
+// 48-byte record:
 // per segment and trial a 32-bit run mask (bit j set when window byte o_g - 8 + j lies in
 // the trial's run; phase u takes bits 8 - u .. 23 - u), and the LDS base address of each
 // segment; the records of a channel group are copied into LDS with the windows, and every
@@ -84,13 +90,23 @@ struct MGroup {
   int32_t kb_base;              // index into the per-wave K-block ranges
   int32_t kb_first, nkb;        // the group's K blocks (all waves): first and count
   int32_t rec_off;              // LDS byte offset of their records in the buffer
-  int32_t pad0, pad1;
+  int32_t block_begin, nblocks; // copy blocks (up to 1 KiB of one channel's region each)
 };
 struct MUnit {
   int32_t c;      // channel
   int32_t src;    // first window sample of the chunk, relative to the tile's first output
   int32_t dst;    // LDS byte offset of the chunk's 2 interleaved copies (32 bytes)
   int32_t pad;
+};
+// A copy block of the direct staging: up to 64 consecutive 16-byte pieces of a channel's
+// region (piece m holds window bytes 8 m .. 8 m + 15), one buffer-to-LDS load of 16 bytes
+// a lane from the converted block.
+struct MBlock {
+  int32_t c;      // channel
+  int32_t src;    // window sample of the block's first byte, relative to the tile's first
+                  // output (a multiple of 8)
+  int32_t dst;    // LDS byte offset of the block
+  int32_t nl;     // pieces (lanes), 1 .. 64
 };
 
 struct MfmaCfgTables {
@@ -99,11 +115,15 @@ struct MfmaCfgTables {
   std::vector<int32_t> perm, ntot, group_begin, kbr;
   std::vector<MGroup> groups;
   std::vector<MUnit> units;
+  std::vector<MBlock> blocks;
+  int64_t xspan = 0;              // bytes of a converted row a tile's copy blocks reach past
+                                  // the tile's first output
   int bufbytes = 0;               // LDS bytes of one staging buffer
   std::vector<uint8_t> recs;      // [kb][kRecBytes]
   int32_t *d_perm = nullptr, *d_ntot = nullptr, *d_group_begin = nullptr, *d_kbr = nullptr;
   MGroup *d_groups = nullptr;
   MUnit *d_units = nullptr;
+  MBlock *d_blocks = nullptr;
   uint8_t *d_recs = nullptr;
 };
 struct MfmaTables {
@@ -120,6 +140,7 @@ void free_mfma(MfmaTables *t) {
     (void)hipFree(c.d_kbr);
     (void)hipFree(c.d_groups);
     (void)hipFree(c.d_units);
+    (void)hipFree(c.d_blocks);
     (void)hipFree(c.d_recs);
   }
   delete t;
@@ -140,6 +161,9 @@ struct MfmaArgs {
   const int32_t *group_begin, *kbr, *perm, *ntot;
   const MGroup *groups;
   const MUnit *units;
+  const MBlock *blocks;
+  const uint8_t *xs;      // converted block (x ^ 0x80, rows of xs_stride bytes) for the
+  int64_t xs_stride;      // direct staging
   const uint8_t *recs;
   int32_t *out;
   int64_t out_stride, out_bstride, nout;
@@ -223,8 +247,9 @@ struct TileAcc {
 // takes trials 4 wd .. 4 wd + 3 of the tile and outputs T0 + 256 NP wt + ...; lane l,
 // register r of product q holds trial 4 wd + r / 4 at output 256 NP wt + 256 q +
 // 8 (l mod 32) + 4 (l / 32) + r mod 4.  Ends with a workgroup barrier, after which the
-// LDS is free.
-template <int NWD, int NWT, int NP, int WG, typename MA>
+// LDS is free.  DMA: the windows come from the converted block a.xs by buffer-to-LDS
+// loads (copy blocks), else from x through registers (staging units).
+template <int NWD, int NWT, int NP, int WG, bool DMA, typename MA>
 __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, const uint8_t *xb,
                                                  unsigned char *lds) {
   constexpr int NW = NWD * NWT;
@@ -275,9 +300,29 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
     for (int j = 0; j < kUnitsPerThread; ++j)
       if (has[j]) store_chunk(buf, dst[j], raw[j], sh[j]);
   };
+  // direct staging: wave w takes copy blocks w, w + NW, ... of the group; lane l of a
+  // block loads the 16 converted bytes from window byte 8 l of the block into LDS at
+  // the block's offset + 16 l (the loads land in LDS without registers and are waited
+  // for with the other vector-memory loads before the group's barrier)
+  auto dma_stage = [&](int g, unsigned char *buf) {
+    const int bb = ldc(&a.groups[g].block_begin, 0), nb = ldc(&a.groups[g].nblocks, 0);
+    for (int b = wave; b < nb; b += NW) {
+      const int c = ldc(&a.blocks[bb + b].c, 0), src = ldc(&a.blocks[bb + b].src, 0);
+      const int dst = ldc(&a.blocks[bb + b].dst, 0), nl = ldc(&a.blocks[bb + b].nl, 0);
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)(a.xs + (int64_t)c * a.xs_stride), (short)0, (int)a.xs_stride, kBufWord3);
+      if (lane < nl)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void *)(buf + dst), 16,
+                                                 (int)(T0 + src) + 8 * lane, 0, 0, 0);
+    }
+  };
   stage_recs(gb, lds);
-  fetch(gb);
-  store(lds);
+  if constexpr (DMA) {
+    dma_stage(gb, lds);
+  } else {
+    fetch(gb);
+    store(lds);
+  }
   __builtin_amdgcn_s_waitcnt(kWaitVm0);
   __syncthreads();
   // the lane's byte offset from a segment's base: column lane mod 32 of the wave's run
@@ -291,7 +336,8 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
     unsigned char *buf = lds + par * a.bufbytes;
     if (g + 1 < ge) {
       stage_recs(g + 1, lds + (par ^ 1) * a.bufbytes);
-      fetch(g + 1);
+      if constexpr (DMA) dma_stage(g + 1, lds + (par ^ 1) * a.bufbytes);
+      else fetch(g + 1);
     }
     const int kbase = ldc(&a.groups[g].kb_base, 0), kf = ldc(&a.groups[g].kb_first, 0);
     const int ro = ldc(&a.groups[g].rec_off, 0);
@@ -327,7 +373,9 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
       }
     }
     __builtin_amdgcn_s_setprio(0);
-    if (g + 1 < ge) store(lds + (par ^ 1) * a.bufbytes);
+    if constexpr (!DMA) {
+      if (g + 1 < ge) store(lds + (par ^ 1) * a.bufbytes);
+    }
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
   }
@@ -360,7 +408,7 @@ k_dedisp_mfma(MfmaArgs a) {
   const int wd = wave % NWD, wt = wave / NWD;
   const int64_t T0 = (int64_t)tt * TW;
   const TileAcc<NP> acc =
-      mfma_tile<NWD, NWT, NP, WG>(a, tw, T0, a.x + (int64_t)bb * a.in_bstride, lds);
+      mfma_tile<NWD, NWT, NP, WG, false>(a, tw, T0, a.x + (int64_t)bb * a.in_bstride, lds);
   // The rows go out through LDS (free after the tile's last barrier; each wave has its
   // own 2 rows), so that each store instruction writes 256 consecutive bytes of a row.
   constexpr int OROW = TWV + 4;
@@ -408,7 +456,7 @@ constexpr int search_step(int sp) { return 64 * sp - ((32 + sp - 1) / sp) * sp; 
 // then the boxcar search of every trial of the tile over starts T0 .. T0 + TT - 1.
 // The series go through LDS in two passes (trials 0-1, then 2-3 of every wave), as rows
 // of TW + 36 ints; each wave searches whole rows.
-template <int NWD, int NWT, int NP, int WG, typename SA>
+template <int NWD, int NWT, int NP, int WG, bool DMA, typename SA>
 __device__ __forceinline__ void search_tile_mfma(SA &sa, int tt, int tw, unsigned char *lds) {
   constexpr int NW = NWD * NWT, TWV = kOutsPerProduct * NP, TW = NWT * TWV, SP = TW / 64;
   constexpr int TT = search_step(SP), YROW = TW + kHalo + 4;
@@ -426,7 +474,7 @@ __device__ __forceinline__ void search_tile_mfma(SA &sa, int tt, int tw, unsigne
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wd = wave % NWD, wt = wave / NWD;
   const int64_t T0 = (int64_t)tt * TT;
-  const TileAcc<NP> acc = mfma_tile<NWD, NWT, NP, WG>(a, tw, T0, a.x, lds);
+  const TileAcc<NP> acc = mfma_tile<NWD, NWT, NP, WG, DMA>(a, tw, T0, a.x, lds);
   constexpr int DT = kTrialsPerWave * NWD;
   int *Y = (int *)lds;
   const int col = TWV * wt + 8 * (lane & 31) + 4 * (lane >> 5);
@@ -465,14 +513,14 @@ __device__ __forceinline__ void search_tile_mfma(SA &sa, int tt, int tw, unsigne
   }
 }
 
-template <int NWD, int NWT, int NP, int WG>
+template <int NWD, int NWT, int NP, int WG, bool DMA>
 __global__ void __launch_bounds__(64 * NWD * NWT)
 __attribute__((amdgpu_waves_per_eu(WG * NWD * NWT / 4, WG * NWD * NWT / 4)))
 k_search_mfma(MfmaSearchArgs sa) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   int tt, tw;
   tile_of_block(sa.m.ntw, sa.m.ntt, &tt, &tw);
-  search_tile_mfma<NWD, NWT, NP, WG>(sa, tt, tw, lds);
+  search_tile_mfma<NWD, NWT, NP, WG, DMA>(sa, tt, tw, lds);
 }
 
 // Multi-beam fused search: one workgroup per (beam, tile).  Beam b owns the blocks
@@ -502,7 +550,7 @@ k_search_mfma_batch(const MfmaSearchArgs *__restrict__ beams, const int32_t *__r
   if (k >= q + (xcd < rem ? 1 : 0)) return;
   const int L = xcd * q + min(xcd, rem) + k;
   const int tt = L / sa.m.ntw, tw = L - tt * sa.m.ntw;
-  search_tile_mfma<NWD, NWT, NP, WG>(sa, tt, tw, lds);
+  search_tile_mfma<NWD, NWT, NP, WG, false>(sa, tt, tw, lds);
 }
 
 // Persistent multi-beam search: a grid that fills the GPU once; each workgroup claims
@@ -529,7 +577,7 @@ k_search_mfma_persist(const MfmaSearchArgs *__restrict__ beams, const int2 *__re
     CArgs &sa = ((CArgs *)beams)[b];
     const int tt = L / sa.m.ntw, tw = L - tt * sa.m.ntw;
     // the tile ends with a workgroup barrier, after which thread 0 may claim the next item
-    search_tile_mfma<NWD, NWT, NP, WG>(sa, tt, tw, lds);
+    search_tile_mfma<NWD, NWT, NP, WG, false>(sa, tt, tw, lds);
   }
 }
 
@@ -578,7 +626,9 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
   out.group_begin.assign(ntw + 1, 0);
   // per (wave along DM, channel): first segment (window-relative, a multiple of 8) and count
   std::vector<int32_t> so(NWD * C), nseg(NWD * C);
-  // per channel: window origin (absolute delay of window byte 0) and bytes per copy
+  // per channel: window origin (absolute delay of window byte 0, a multiple of 8, so
+  // that every copy block of the direct staging starts 8-byte aligned in the converted
+  // row) and bytes per copy
   std::vector<int32_t> wlo(C), clen(C);
   for (int tw = 0; tw < ntw; ++tw) {
     out.group_begin[tw] = (int)out.groups.size();
@@ -603,16 +653,16 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
         for (int w = 0; w < NWD; ++w) nseg[w * C + c] = 0;
         continue;
       }
-      wlo[c] = slo;
+      wlo[c] = slo / 8 * 8;   // delays are >= 0
       int smax = 0;   // largest segment start
       for (int w = 0; w < NWD; ++w) {
         if (l[w] == INT32_MAX) {
           nseg[w * C + c] = 0;
           continue;
         }
-        const int o = (l[w] - slo) / 8 * 8;   // on the 8-byte grid, at or below the band
+        const int o = (l[w] - wlo[c]) / 8 * 8;   // on the 8-byte grid, at or below the band
         so[w * C + c] = o;
-        nseg[w * C + c] = (h[w] - (slo + o) + 15) / 16;
+        nseg[w * C + c] = (h[w] - (wlo[c] + o) + 15) / 16;
         smax = std::max(smax, o + 16 * (nseg[w * C + c] - 1));
       }
       // the last lane reads 16 bytes from window byte smax + TW - 8: chunks up to that
@@ -620,6 +670,8 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
       clen[c] = 16 * ((smax + TW - 8) / 16 + 1);
       if ((int64_t)kCopies * clen[c] + kRecBytes > BUF - kSlotBytes || clen[c] / 16 > maxunits)
         return false;
+      // the last piece of the channel's region (window bytes clen - 8 .. clen + 7)
+      out.xspan = std::max(out.xspan, (int64_t)wlo[c] + clen[c] + 8);
     }
     int c = 0;
     while (c < C) {
@@ -652,6 +704,14 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
         off += kCopies * clen[cc];
       }
       gi.nunits = (int)out.units.size() - gi.unit_begin;
+      gi.block_begin = (int)out.blocks.size();
+      for (int cc = cbeg; cc < c; ++cc) {
+        const int npiece = kCopies * clen[cc] / 16;   // 16-byte pieces of the region
+        for (int j = 0; 64 * j < npiece; ++j)
+          out.blocks.push_back(
+              MBlock{cc, wlo[cc] + 8 * 64 * j, region[cc] + 16 * 64 * j, std::min(64, npiece - 64 * j)});
+      }
+      gi.nblocks = (int)out.blocks.size() - gi.block_begin;
       gi.kb_base = (int)out.kbr.size();
       gi.kb_first = (int)(out.recs.size() / kRecBytes);
       gi.rec_off = off;
@@ -750,6 +810,7 @@ static dedisp_status ensure_mfma(dedisp_plan p, int k, MfmaCfgTables **out) {
       DD_HIP(upload(&c.d_kbr, c.kbr));
       DD_HIP(upload(&c.d_groups, c.groups));
       DD_HIP(upload(&c.d_units, c.units));
+      DD_HIP(upload(&c.d_blocks, c.blocks));
       DD_HIP(upload(&c.d_recs, c.recs));
     }
   }
@@ -771,6 +832,7 @@ static void fill_args(dedisp_plan p, const MfmaCfgTables &c, const uint8_t *x, i
   a.ntot = c.d_ntot;
   a.groups = c.d_groups;
   a.units = c.d_units;
+  a.blocks = c.d_blocks;
   a.recs = c.d_recs;
   a.nout = nout;
   (void)p;
@@ -812,43 +874,62 @@ dedisp_status run_dedisperse_u8_mfma(dedisp_plan p, const uint8_t *x, int64_t ns
 // ---- fused search ----------------------------------------------------------------
 struct MfmaSearchLayout {
   int64_t ntt = 0;
-  size_t off_part = 0, total = 0;
+  int64_t xs_stride = 0;          // converted row length (0: staging through registers)
+  size_t off_part = 0, off_xs = 0, total = 0;
 };
 
-static MfmaSearchLayout search_layout(const dedisp_plan_s *p, int k, int32_t nw, int64_t nout) {
+// Workspace of shape k: noise tables, per-(trial, time tile) candidates and, for the
+// direct staging (xspan > 0: the shape's reach past a tile's first output), the
+// converted block [nchan][xs_stride].
+static MfmaSearchLayout search_layout(const dedisp_plan_s *p, int k, int32_t nw, int64_t nout,
+                                      int64_t xspan) {
   const MfmaCfg cf = kMfmaCfgs[k];
   const int tw = cf.nwt * kOutsPerProduct * cf.np, tstep = search_step(tw / 64);
   MfmaSearchLayout L;
   L.ntt = (nout + tstep - 1) / tstep;
   L.off_part = (2 * sizeof(double) * (size_t)p->ndm * nw + 255) & ~(size_t)255;
-  L.total = L.off_part + ((sizeof(CandRec) * (size_t)p->ndm * L.ntt + 255) & ~(size_t)255);
+  L.off_xs = L.off_part + ((sizeof(CandRec) * (size_t)p->ndm * L.ntt + 255) & ~(size_t)255);
+  L.total = L.off_xs;
+  if (xspan > 0) {
+    L.xs_stride = ((L.ntt - 1) * tstep + xspan + 255) & ~(int64_t)255;
+    L.total += (size_t)p->nchan * (size_t)L.xs_stride;
+  }
   return L;
+}
+
+// The most any shape's search can take: the converted block's rows reach at most
+// max_span + 16 bytes plus a tile's outputs past a tile's first output.
+static int64_t xspan_bound(const dedisp_plan_s *p, int k) {
+  const MfmaCfg cf = kMfmaCfgs[k];
+  return (int64_t)p->max_span + kPhases + 16 + 16 + cf.nwt * kOutsPerProduct * cf.np;
 }
 
 size_t mfma_search_work_bytes(const dedisp_plan_s *p, int32_t nw, int64_t nout) {
   size_t b = 0;
-  for (int k = 0; k < kNumMfmaCfgs; ++k) b = std::max(b, search_layout(p, k, nw, nout).total);
+  for (int k = 0; k < kNumMfmaCfgs; ++k)
+    b = std::max(b, search_layout(p, k, nw, nout, xspan_bound(p, k)).total);
   return b;
 }
 
 int mfma_search_count() { return kNumMfmaCfgs; }
 
-template <int NWD, int NWT, int NP, int WG>
+template <int NWD, int NWT, int NP, int WG, bool DMA>
 static hipError_t launch_search_cfg(const MfmaSearchArgs &sa, hipStream_t s) {
   static bool done[64] = {};
   static std::mutex mu;
-  hipError_t e = allow_lds_mfma((const void *)k_search_mfma<NWD, NWT, NP, WG>, done, &mu,
+  hipError_t e = allow_lds_mfma((const void *)k_search_mfma<NWD, NWT, NP, WG, DMA>, done, &mu,
                                 2 * (kMfmaBufBytes / WG));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_search_mfma<NWD, NWT, NP, WG>), dim3(sa.m.ntw * sa.m.ntt),
+  hipLaunchKernelGGL((k_search_mfma<NWD, NWT, NP, WG, DMA>), dim3(sa.m.ntw * sa.m.ntt),
                      dim3(64 * NWD * NWT), 2 * sa.m.bufbytes, s, sa);
   return hipGetLastError();
 }
 
-static hipError_t launch_search_mfma(int k, const MfmaSearchArgs &sa, hipStream_t s) {
+static hipError_t launch_search_mfma(int k, bool dma, const MfmaSearchArgs &sa, hipStream_t s) {
   switch (k) {
 #define DD_MFMA_SEARCH_CASE(i, x, y, n, g) \
-  case i: return launch_search_cfg<x, y, n, g>(sa, s);
+  case i: return dma ? launch_search_cfg<x, y, n, g, true>(sa, s) \
+                     : launch_search_cfg<x, y, n, g, false>(sa, s);
     DD_MFMA_CONFIGS(DD_MFMA_SEARCH_CASE)
 #undef DD_MFMA_SEARCH_CASE
     default: return hipErrorInvalidValue;
@@ -858,7 +939,7 @@ static hipError_t launch_search_mfma(int k, const MfmaSearchArgs &sa, hipStream_
 dedisp_status run_search_mfma(dedisp_plan p, int k, const uint8_t *x, int64_t nsamp,
                               int64_t in_stride, int64_t nout, const WidthList &wl,
                               const double *mu, const double *sigma, double *snr, int32_t *t,
-                              int32_t *w, void *work, hipStream_t s) {
+                              int32_t *w, void *work, hipStream_t s, bool dma) {
   if (k < 0 || k >= kNumMfmaCfgs || p->wmode != DEDISP_W_UNIT || wl.w[wl.n - 1] > 32)
     return DEDISP_ERR_UNSUPPORTED;
   MfmaCfgTables *cfg = nullptr;
@@ -868,11 +949,22 @@ dedisp_status run_search_mfma(dedisp_plan p, int k, const uint8_t *x, int64_t ns
     if (st != DEDISP_OK) return st;
   }
   if (!cfg) return DEDISP_ERR_UNSUPPORTED;
-  const MfmaSearchLayout L = search_layout(p, k, wl.n, nout);
+  // the direct staging needs its converted block within the workspace the caller sized
+  // with dedisp_work_bytes, and 32-bit buffer offsets
+  if (dma && cfg->xspan > xspan_bound(p, k)) dma = false;
+  MfmaSearchLayout L = search_layout(p, k, wl.n, nout, dma ? cfg->xspan : 0);
+  if (dma && L.xs_stride > INT32_MAX) {
+    dma = false;
+    L = search_layout(p, k, wl.n, nout, 0);
+  }
   if (L.ntt * cfg->ntw > INT32_MAX / 2) return DEDISP_ERR_UNSUPPORTED;
   MfmaSearchArgs sa{};
   fill_args(p, *cfg, x, nsamp, in_stride, nout, sa.m);
   sa.m.ntt = (int32_t)L.ntt;
+  if (dma) {
+    sa.m.xs = (const uint8_t *)work + L.off_xs;
+    sa.m.xs_stride = L.xs_stride;
+  }
   double *M = (double *)work;
   sa.M = M;
   sa.S = M + (size_t)p->ndm * wl.n;
@@ -880,10 +972,12 @@ dedisp_status run_search_mfma(dedisp_plan p, int k, const uint8_t *x, int64_t ns
   sa.wmask = 0;
   for (int i = 0; i < wl.n; ++i) sa.wmask |= 1u << (wl.w[i] - 1);
   sa.part = (CandRec *)((char *)work + L.off_part);
-  DD_HIP(launch_norm(p, wl, mu, sigma, M, (double *)sa.S, s));
+  // the noise tables, and the converted block of the direct staging in the same launch
+  ConvertJob cv{x, in_stride, nsamp, (uint8_t *)sa.m.xs, L.xs_stride, p->nchan};
+  DD_HIP(launch_norm(p, wl, mu, sigma, M, (double *)sa.S, s, dma ? &cv : nullptr));
   KernelTimer kt(p, s);
   DD_HIP(kt.begin());
-  DD_HIP(launch_search_mfma(k, sa, s));
+  DD_HIP(launch_search_mfma(k, dma, sa, s));
   DD_HIP(kt.end());
   DD_HIP(launch_reduce(p->ndm, (int32_t)L.ntt, sa.part, snr, t, w, s));
   return DEDISP_OK;
@@ -940,7 +1034,7 @@ dedisp_status run_search_noalloc(dedisp_plan p, const uint8_t *x, int64_t nsamp,
     if (!p->mfma->cfg[k].ok)
       return fail(DEDISP_ERR_UNSUPPORTED, "the plan does not fit the matrix-core search");
   }
-  const MfmaSearchLayout L = search_layout(p, k, wl.n, nout);
+  const MfmaSearchLayout L = search_layout(p, k, wl.n, nout, 0);
   if (L.total > kNoAllocScratchBytes)
     return fail(DEDISP_ERR_INVALID_ARG,
                 "workspace of " + std::to_string(L.total) + " bytes exceeds the " +
@@ -949,7 +1043,7 @@ dedisp_status run_search_noalloc(dedisp_plan p, const uint8_t *x, int64_t nsamp,
   void *work = nullptr;
   dedisp_status st = scratch_of_current_device(&work);
   if (st != DEDISP_OK) return st;
-  st = run_search_mfma(p, k, x, nsamp, in_stride, nout, wl, mu, sigma, snr, t, w, work, s);
+  st = run_search_mfma(p, k, x, nsamp, in_stride, nout, wl, mu, sigma, snr, t, w, work, s, false);
   if (st == DEDISP_OK) p->last_search_tile = 8 + k;
   return st;
 }
@@ -1032,7 +1126,7 @@ dedisp_status mfma_batch_create(const std::vector<dedisp_plan> &plans,
     dedisp_plan p = plans[b];
     const int64_t no = nsamp[b] - p->max_span + 1;
     B->nout.push_back(no);
-    const MfmaSearchLayout L = search_layout(p, chosen, wl.n, no);
+    const MfmaSearchLayout L = search_layout(p, chosen, wl.n, no, 0);
     B->lay.push_back(L);
     B->off.push_back(off);
     off += (L.total + 255) & ~(size_t)255;
