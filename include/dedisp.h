@@ -157,7 +157,10 @@ dedisp_status dedisp_merge_candidates(int32_t ndm, const double *d_snr_b, const 
                                       int64_t *d_t, int32_t *d_w, void *stream);
 
 /* Workspace (device bytes) needed by dedisp_detect / dedisp_search for nsamp
- * samples and nw widths. */
+ * samples and nw widths: the noise tables, per-(trial, time tile) candidates and,
+ * for the search of uint8 blocks with unit weights, the largest of the tile kernels'
+ * own buffers (the matrix-core search writes a converted copy of the block,
+ * nchan x about nsamp bytes, into it on every call). */
 dedisp_status dedisp_work_bytes(dedisp_plan plan, int64_t nsamp, int32_t nw, size_t *bytes);
 
 /* Boxcar S/N search (eq. snr with the Section 4 boxcar) of a dedispersed block:
