@@ -26,14 +26,14 @@
 // are staged while the previous group is multiplied (two LDS buffers): in the fused
 // search from a converted copy of the block (x ^ 0x80, written by the noise-table launch)
 // with buffer-to-LDS loads, 16 bytes a lane, so that piece m of a region (its 16 bytes
-// at region + 16 m) is one load of window bytes 8 m .. 8 m + 15; in the dedispersion and
-// the multi-beam search from x through registers (aligned loads, byte shifts, the
-// conversion, two LDS stores).  The host plans, per pair of segments (a K block), a
-// 48-byte record:
-// per segment and trial a 32-bit run mask (bit j set when window byte o_g - 8 + j lies in
-// the trial's run; phase u takes bits 8 - u .. 23 - u), and the LDS base address of each
-// segment; the records of a channel group are copied into LDS with the windows, and every
-// lane forms its 16 mask bytes and its read address from them.
+// at region + 16 m) is one load of window bytes 8 m .. 8 m + 15; in the dedispersion, the
+// multi-beam search and the allocation-free search from x through registers (aligned
+// loads, byte shifts, the conversion, two LDS stores).  The host plans, per pair of
+// segments (a K block), a 48-byte record: per segment and trial a 32-bit run mask (bit j
+// set when window byte o_g - 8 + j lies in the trial's run; phase u takes bits 8 - u ..
+// 23 - u), and the LDS base address of each segment; the records of a channel group are
+// copied into LDS with the windows, and every lane forms its 16 mask bytes and its read
+// address from them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
