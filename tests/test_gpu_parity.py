@@ -275,6 +275,38 @@ def test_u8_dedisperse_batched_unaligned_rows(dd, orc):
         assert np.array_equal(y[b].astype(np.int64), orc.dedisperse_u8(x[b], s, n)), b
 
 
+
+@pytest.mark.parametrize("tile", [8, 9])
+def test_fused_search_unaligned_rows(dd, orc, tile):
+    """Fused search on the matrix cores (windows staged from the converted block) of a
+    block whose rows start 3 bytes into rows of odd length, so the conversion takes its
+    byte path; trials out of DM order, a channel some trials skip, ragged trial and time
+    counts; detection against the oracle."""
+    rng = np.random.default_rng(2025)
+    C, D = 37, 50
+    f = workloads.channel_centres(1.35, 0.3, C)
+    dms = ((np.arange(D) * 37) % D) * 3.0
+    s = np.zeros((D, C), np.int32)
+    n = np.zeros((D, C), np.int32)
+    for d in range(D):
+        s[d] = np.floor(4.15 * dms[d] * (1.0 / f ** 2 - 1.0 / f.max() ** 2)).astype(np.int32)
+        n[d] = rng.integers(1, 8, size=C)
+    n[::3, 5] = 0
+    span = int(np.max(s + n))
+    T = span + 2300
+    p = dd.Plan(f, 0.01, 1e-3, dms, rule="explicit", start=s, ntap=n)
+    big = rng.integers(0, 256, size=(C, T + 5), dtype=np.uint8)
+    xd = _dev(big)[:, 3:]           # rows start 3 bytes into rows of T + 5 bytes
+    assert xd.stride(0) == T + 5
+    x = np.ascontiguousarray(big[:, 3:])
+    yo = orc.dedisperse_u8(x, s, n).astype(np.float64)
+    widths = list(range(1, 33))
+    mu, sg = np.full(C, 127.5), np.full(C, 73.9)
+    p.set_tile(tile)
+    snr, t, W = p.search(xd, widths, mu, sg)
+    assert p.last_search_tile() == tile
+    _check_detect(orc, yo, n, widths, mu, sg, snr, t, W)
+
 def test_edge_cases(dd, orc):
     rng = np.random.default_rng(77)
     # Descending channel order, a channel with ntap = 0, nout = 1 and a single trial.
