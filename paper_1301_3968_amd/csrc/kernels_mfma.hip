@@ -304,17 +304,24 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
   // block loads the 16 converted bytes from window byte 8 l of the block into LDS at
   // the block's offset + 16 l (the loads land in LDS without registers and are waited
   // for with the other vector-memory loads before the group's barrier)
+  auto dma_block = [&](const v4i d, unsigned char *buf) {   // d: c, src, dst, nl
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(a.xs + (int64_t)d[0] * a.xs_stride), (short)0, (int)a.xs_stride, kBufWord3);
+    if (lane < d[3])
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void *)(buf + d[2]), 16,
+                                               (int)(T0 + d[1]) + 8 * lane, 0, 0, 0);
+  };
+  // the block descriptors are read two at a time (one scalar round trip per pair)
   auto dma_stage = [&](int g, unsigned char *buf) {
     const int bb = ldc(&a.groups[g].block_begin, 0), nb = ldc(&a.groups[g].nblocks, 0);
-    for (int b = wave; b < nb; b += NW) {
-      const int c = ldc(&a.blocks[bb + b].c, 0), src = ldc(&a.blocks[bb + b].src, 0);
-      const int dst = ldc(&a.blocks[bb + b].dst, 0), nl = ldc(&a.blocks[bb + b].nl, 0);
-      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          (void *)(a.xs + (int64_t)c * a.xs_stride), (short)0, (int)a.xs_stride, kBufWord3);
-      if (lane < nl)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void *)(buf + dst), 16,
-                                                 (int)(T0 + src) + 8 * lane, 0, 0, 0);
+    const v4i *bd = (const v4i *)(a.blocks + bb);
+    int b = wave;
+    for (; b + NW < nb; b += 2 * NW) {
+      const v4i d0 = ldc(bd, b), d1 = ldc(bd, b + NW);
+      dma_block(d0, buf);
+      dma_block(d1, buf);
     }
+    if (b < nb) dma_block(ldc(bd, b), buf);
   };
   stage_recs(gb, lds);
   if constexpr (DMA) {
@@ -334,10 +341,11 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
   for (int g = gb; g < ge; ++g) {
     const int par = (g - gb) & 1;
     unsigned char *buf = lds + par * a.bufbytes;
-    if (g + 1 < ge) {
-      stage_recs(g + 1, lds + (par ^ 1) * a.bufbytes);
-      if constexpr (DMA) dma_stage(g + 1, lds + (par ^ 1) * a.bufbytes);
-      else fetch(g + 1);
+    if constexpr (!DMA) {
+      if (g + 1 < ge) {
+        stage_recs(g + 1, lds + (par ^ 1) * a.bufbytes);
+        fetch(g + 1);
+      }
     }
     const int kbase = ldc(&a.groups[g].kb_base, 0), kf = ldc(&a.groups[g].kb_first, 0);
     const int ro = ldc(&a.groups[g].rec_off, 0);
@@ -353,7 +361,7 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
       m_next = *(const uint32_t *)(rb + moff);
       b_next = *(const int32_t *)(rb + kRecBase + 4 * (lane >> 5));
     }
-    for (int kb = k0; kb < k1; ++kb, rb += kRecBytes) {
+    auto kblock = [&](int kb) {
       const uint32_t m32 = m_next;
       const unsigned char *bp = buf + b_next + loff;
       if (kb + 1 < k1) {
@@ -371,7 +379,19 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
         const v4i bq = *(const v4i *)(bp + 2 * kOutsPerProduct * q);
         acc[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(mk, bq, acc[q], 0, 0, 0);
       }
+      rb += kRecBytes;
+    };
+    int kb = k0;
+    if constexpr (DMA) {
+      // the next group's copies are issued after this group's first K block, so that the
+      // scalar reads of their descriptors wait while its products run
+      if (kb < k1) kblock(kb++);
+      if (g + 1 < ge) {
+        stage_recs(g + 1, lds + (par ^ 1) * a.bufbytes);
+        dma_stage(g + 1, lds + (par ^ 1) * a.bufbytes);
+      }
     }
+    for (; kb < k1; ++kb) kblock(kb);
     __builtin_amdgcn_s_setprio(0);
     if constexpr (!DMA) {
       if (g + 1 < ge) store(lds + (par ^ 1) * a.bufbytes);
