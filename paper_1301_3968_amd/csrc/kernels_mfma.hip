@@ -341,12 +341,6 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
   for (int g = gb; g < ge; ++g) {
     const int par = (g - gb) & 1;
     unsigned char *buf = lds + par * a.bufbytes;
-    if constexpr (!DMA) {
-      if (g + 1 < ge) {
-        stage_recs(g + 1, lds + (par ^ 1) * a.bufbytes);
-        fetch(g + 1);
-      }
-    }
     const int kbase = ldc(&a.groups[g].kb_base, 0), kf = ldc(&a.groups[g].kb_first, 0);
     const int ro = ldc(&a.groups[g].rec_off, 0);
     const int k0 = ldc(a.kbr, (int64_t)kbase + wd), k1 = ldc(a.kbr, (int64_t)kbase + wd + 1);
@@ -381,15 +375,14 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
       }
       rb += kRecBytes;
     };
+    // the next group's staging is issued after this group's first K block, so that the
+    // scalar reads of its descriptors wait while this group's first products run
     int kb = k0;
-    if constexpr (DMA) {
-      // the next group's copies are issued after this group's first K block, so that the
-      // scalar reads of their descriptors wait while its products run
-      if (kb < k1) kblock(kb++);
-      if (g + 1 < ge) {
-        stage_recs(g + 1, lds + (par ^ 1) * a.bufbytes);
-        dma_stage(g + 1, lds + (par ^ 1) * a.bufbytes);
-      }
+    if (kb < k1) kblock(kb++);
+    if (g + 1 < ge) {
+      stage_recs(g + 1, lds + (par ^ 1) * a.bufbytes);
+      if constexpr (DMA) dma_stage(g + 1, lds + (par ^ 1) * a.bufbytes);
+      else fetch(g + 1);
     }
     for (; kb < k1; ++kb) kblock(kb);
     __builtin_amdgcn_s_setprio(0);
