@@ -46,6 +46,7 @@
 
 #include "boxcar_row.h"
 #include "internal.h"
+#include "norm_reduce.h"
 
 namespace dd {
 
@@ -459,6 +460,8 @@ struct MfmaSearchArgs {
   int32_t nw;
   uint32_t wmask;         // bit W - 1 for every listed width W <= 32
   CandRec *part;          // [ndm][ntt]
+  const int32_t *ntap;    // the plan's tap counts [ndm][nchan] (multi-beam noise tables)
+  int32_t nchan, ndm;
 };
 
 // Time-tile step of the search: the tile's 64 SP outputs less a halo of >= 31 outputs,
@@ -595,6 +598,44 @@ k_search_mfma_persist(const MfmaSearchArgs *__restrict__ beams, const int2 *__re
 }
 
 __global__ void k_reset_counter(int32_t *counter) { *counter = 0; }
+
+// Beam of trial i of the multi-beam list: the last b with tbase[b] <= i.
+__device__ __forceinline__ int beam_of_trial(const int32_t *tbase, int nbeam, int i) {
+  int lo = 0, hi = nbeam - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ldc(tbase, mid) <= i) lo = mid; else hi = mid - 1;
+  }
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// Noise tables of every beam's trials in one launch (unit weights): workgroup i takes
+// trial i - tbase[b] of beam b.
+__global__ void __launch_bounds__(64 * kBucketWaves)
+k_norm_beams(const MfmaSearchArgs *__restrict__ beams, const int32_t *__restrict__ tbase,
+             int32_t nbeam, WidthList wl, const double *__restrict__ mu,
+             const double *__restrict__ sigma) {
+  typedef const __attribute__((address_space(4))) MfmaSearchArgs CArgs;
+  const int i = blockIdx.x, b = beam_of_trial(tbase, nbeam, i);
+  CArgs &sa = ((CArgs *)beams)[b];
+  const int d = i - ldc(tbase, b);
+  norm_buckets_trial(sa.ntap + (int64_t)d * sa.nchan, sa.nchan, DEDISP_W_UNIT, nullptr, mu,
+                     sigma, wl, (double *)sa.M + (int64_t)d * wl.n,
+                     (double *)sa.S + (int64_t)d * wl.n);
+}
+
+// Per-trial best over the time tiles of every beam in one launch; outputs in the
+// order of the trial list (beam by beam).
+__global__ void __launch_bounds__(kReduceThreads)
+k_reduce_beams(const MfmaSearchArgs *__restrict__ beams, const int32_t *__restrict__ tbase,
+               int32_t nbeam, double *__restrict__ snr, int32_t *__restrict__ t,
+               int32_t *__restrict__ w) {
+  typedef const __attribute__((address_space(4))) MfmaSearchArgs CArgs;
+  const int i = blockIdx.x, b = beam_of_trial(tbase, nbeam, i);
+  CArgs &sa = ((CArgs *)beams)[b];
+  const int d = i - ldc(tbase, b);
+  best_of_row(sa.part + (int64_t)d * sa.m.ntt, sa.m.ntt, snr + i, t + i, w + i);
+}
 
 }  // namespace
 
@@ -1074,6 +1115,8 @@ struct MfmaBatch {
   size_t work_bytes = 0;
   size_t args_off = 0;                      // workspace offset of the eager argument table
   int32_t *d_base = nullptr;
+  std::vector<int32_t> tbase;               // first trial of each beam, then the total
+  int32_t *d_tbase = nullptr;
   MfmaSearchArgs *d_args_graph = nullptr;   // argument table of the captured graph
   std::vector<MfmaSearchArgs> args;         // argument table of the last enqueue
   ArgStage stage;                           // pinned staging of the eager table
@@ -1088,6 +1131,7 @@ void mfma_batch_free(MfmaBatch *B) {
   if (!B) return;
   B->stage.release();
   (void)hipFree(B->d_base);
+  (void)hipFree(B->d_tbase);
   (void)hipFree(B->d_args_graph);
   (void)hipFree(B->d_items);
   (void)hipFree(B->d_counter);
@@ -1152,6 +1196,16 @@ dedisp_status mfma_batch_create(const std::vector<dedisp_plan> &plans,
     }
   }
   B->base.push_back((int32_t)blocks);
+  int64_t trials = 0;
+  for (int b = 0; b < B->nbeam; ++b) {
+    B->tbase.push_back((int32_t)trials);
+    trials += plans[b]->ndm;
+  }
+  B->tbase.push_back((int32_t)trials);
+  if (trials > INT32_MAX / 2) {
+    mfma_batch_free(B);
+    return DEDISP_OK;   // too many trials for one launch: not this path
+  }
   // the persistent launch (the default; DEDISP_BATCH_LAUNCH=grid selects one workgroup
   // per tile instead): every (beam, tile) as a work item, beam by beam, each beam's
   // tiles in the one-plan kernel's order (time tiles in groups of kTimeGroup, DM tile
@@ -1172,6 +1226,7 @@ dedisp_status mfma_batch_create(const std::vector<dedisp_plan> &plans,
   B->args_off = off;
   B->work_bytes = off + sizeof(MfmaSearchArgs) * B->nbeam;
   hipError_t e = upload(&B->d_base, B->base);
+  if (e == hipSuccess) e = upload(&B->d_tbase, B->tbase);
   if (e == hipSuccess)
     e = dev_malloc((void **)&B->d_args_graph, sizeof(MfmaSearchArgs) * B->nbeam);
   if (e == hipSuccess && B->persistent) {
@@ -1228,8 +1283,9 @@ static hipError_t launch_batch_mfma(const MfmaBatch *B, const MfmaSearchArgs *ta
   }
 }
 
-// Noise tables of every beam, the argument table, one launch over every beam's tiles,
-// the per-beam reductions.  Outputs of beam b start at out_off[b].  Eager calls
+// The argument table, the noise tables of every beam in one launch, one launch over every
+// beam's tiles, the per-trial reductions of every beam in one launch.  Outputs of beam b
+// start at out_off[b], its first trial in the list.  Eager calls
 // (for_graph false) copy the argument table into the caller's workspace through the
 // pinned staging buffer; a captured sequence (for_graph true) reads the batch's own
 // graph table, which mfma_batch_upload fills once the capture has ended.  The two
@@ -1252,21 +1308,26 @@ dedisp_status mfma_batch_enqueue(MfmaBatch *B, const void *const *in, const int6
     sa.wmask = 0;
     for (int i = 0; i < B->wl.n; ++i) sa.wmask |= 1u << (B->wl.w[i] - 1);
     sa.part = (CandRec *)((char *)work + B->off[b] + B->lay[b].off_part);
-    DD_HIP(launch_norm(p, B->wl, mu, sigma, M, (double *)sa.S, s));
+    sa.ntap = p->dev.ntap;
+    sa.nchan = p->nchan;
+    sa.ndm = p->ndm;
+    if (out_off[b] != B->tbase[b]) return fail(DEDISP_ERR_INVALID_ARG, "beam output offsets");
   }
   MfmaSearchArgs *table = B->d_args_graph;
   if (!for_graph) {
     table = (MfmaSearchArgs *)((char *)work + B->args_off);
     DD_HIP(B->stage.copy(table, B->args.data(), sizeof(MfmaSearchArgs) * B->nbeam, s));
   }
+  const unsigned ntrial = (unsigned)B->tbase.back();
+  hipLaunchKernelGGL(k_norm_beams, dim3(ntrial), dim3(64 * kBucketWaves), 0, s, table, B->d_tbase,
+                     B->nbeam, B->wl, mu, sigma);
+  DD_HIP(hipGetLastError());
   if (kt) DD_HIP(kt->begin());
   DD_HIP(launch_batch_mfma(B, table, s));
   if (kt) DD_HIP(kt->end());
-  for (int b = 0; b < B->nbeam; ++b) {
-    const int64_t o = out_off[b];
-    DD_HIP(launch_reduce(B->plans[b]->ndm, B->args[b].m.ntt, B->args[b].part, snr + o, t + o,
-                         w + o, s));
-  }
+  hipLaunchKernelGGL(k_reduce_beams, dim3(ntrial), dim3(kReduceThreads), 0, s, table, B->d_tbase,
+                     B->nbeam, snr, t, w);
+  DD_HIP(hipGetLastError());
   return DEDISP_OK;
 }
 
