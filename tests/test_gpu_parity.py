@@ -327,10 +327,22 @@ def test_edge_cases(dd, orc):
         _check_detect(orc, yo, n, widths, np.full(C, 100.0), np.full(C, 10.0), snr, t, W)
     with pytest.raises(dd.DedispError):
         p.dedisperse(_dev(rng.integers(0, 256, size=(C, span - 1), dtype=np.uint8)))
-    # One channel, one trial.
+    # A channel no trial uses (no window staged for it) in the fused search.
+    n2 = n.copy()
+    n2[:, 3] = 0
+    p2 = dd.Plan(f, 0.01, 1e-3, [0.0, 1.0, 2.0], rule="explicit", start=s, ntap=n2)
+    x = rng.integers(0, 256, size=(C, span + 300), dtype=np.uint8)
+    snr, t, W = p2.search(_dev(x), [1, 2, 3], np.full(C, 100.0), np.full(C, 10.0))
+    yo = orc.dedisperse_u8(x, s, n2).astype(np.float64)
+    _check_detect(orc, yo, n2, [1, 2, 3], np.full(C, 100.0), np.full(C, 10.0), snr, t, W)
+    # One channel, one trial: dedispersion and the fused search.
     p1 = dd.Plan([1.4], 0.01, 1e-3, [0.0])
     x = rng.integers(0, 256, size=(1, 33), dtype=np.uint8)
     assert np.array_equal(p1.dedisperse(_dev(x)).cpu().numpy()[0], x[0].astype(np.int32))
+    _, n1 = p1.tables()
+    snr, t, W = p1.search(_dev(x), [1, 2, 5], np.full(1, 120.0), np.full(1, 30.0))
+    _check_detect(orc, x.astype(np.float64), np.asarray(n1), [1, 2, 5], np.full(1, 120.0),
+                  np.full(1, 30.0), snr, t, W)
 
 
 @pytest.mark.parametrize("tile", [-1, 0, 9, -2])
