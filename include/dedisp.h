@@ -202,7 +202,7 @@ dedisp_status dedisp_search(dedisp_plan plan, const void *d_in, int32_t in_dtype
  *     the array, else INVALID_ARG; other inputs UNSUPPORTED.
  * Every call on one GPU uses that GPU's array: calls that overlap on one GPU (on
  * different streams, or from different threads) race; calls in stream order do not.
- * The shape is the plan's tuned or forced matrix-core shape, else the default one. */
+ * The shape is the plan's tuned or forced matrix-core shape, else the first one. */
 #define DEDISP_NOALLOC_SCRATCH_BYTES (16u << 20)
 dedisp_status dedisp_search_noalloc(dedisp_plan plan, const void *d_in, int32_t in_dtype,
                                     int64_t nsamp, int64_t in_stride, const int32_t *widths,
@@ -288,8 +288,9 @@ dedisp_status dedisp_autotune(dedisp_plan plan, const void *d_in, int64_t nsamp,
                               void *stream, int32_t *chosen);
 /* Force a shape of the fused uint8 search (index into its candidate list: the
  * shapes of the packed-add kernel, then those of the int8 matrix-core kernel; the
- * autotuner times them all), -1 for the default (the first matrix-core shape, or
- * packed-add shape 0 when the plan does not fit it), or -2 to always use the
+ * autotuner times them all), -1 for the default (the matrix-core shape of two
+ * workgroups per CU, else the first matrix-core shape, else packed-add shape 0,
+ * the first that takes the plan), or -2 to always use the
  * general kernels: the unfused search (dedisperse into a temporary, then detect),
  * the prefix-difference uint8 dedispersion, the untiled fp32 dedispersion and the
  * untiled per-tap adjoint. */

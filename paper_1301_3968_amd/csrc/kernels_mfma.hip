@@ -1074,13 +1074,17 @@ dedisp_status run_search_noalloc(dedisp_plan p, const uint8_t *x, int64_t nsamp,
   if (p->wmode != DEDISP_W_UNIT || wl.w[wl.n - 1] > 32)
     return fail(DEDISP_ERR_UNSUPPORTED,
                 "the allocation-free search takes unit weights and widths up to 32");
-  // the plan's matrix-core shape: the forced or tuned one, else the default
-  const int k = (p->tile_choice >= 8 && p->tile_choice < 8 + kNumMfmaCfgs) ? p->tile_choice - 8 : 0;
+  // the plan's matrix-core shape: the forced or tuned one, else the first of the untuned
+  // search's order (two workgroups per CU, then one) whose tables the plan has
+  const bool chosen = p->tile_choice >= 8 && p->tile_choice < 8 + kNumMfmaCfgs;
+  int k = chosen ? p->tile_choice - 8 : 1;
   int dev = 0;
   DD_HIP(hipGetDevice(&dev));
   {
     // the plan's device tables must exist already: building them would allocate
     std::lock_guard<std::mutex> lk(p->mu);
+    if (!chosen && p->mfma && !(p->mfma->tried[1] && p->mfma->cfg[1].ok) && p->mfma->tried[0])
+      k = 0;
     if (!p->uploaded || p->device != dev || !p->mfma || !p->mfma->tried[k])
       return fail(DEDISP_ERR_INVALID_ARG,
                   "plan tables are not on this device yet: run dedisp_search (or "

@@ -592,8 +592,8 @@ static hipError_t upload(T **dst, const std::vector<T> &v) {
 }
 
 // Search candidates: the kNumCfgs shapes of k_search, then the shapes of the
-// matrix-core search (kernels_mfma.hip).  Without a choice the first matrix-core
-// shape runs (k_search shape kDefaultCfg if the plan does not fit it).
+// matrix-core search (kernels_mfma.hip).  Without a choice the order of kUntunedOrder
+// applies.
 static int num_candidates() { return kNumCfgs + mfma_search_count(); }
 
 static int cfg_index(const dedisp_plan_s *p) {
@@ -810,14 +810,24 @@ static dedisp_status search_ci(dedisp_plan p, int ci, const uint8_t *x, int64_t 
   return DEDISP_OK;
 }
 
+// Without a tuned or forced shape: the matrix-core shape of two workgroups per CU (32
+// trials x 1024 outputs each, the faster one with the direct staging), else the one of one
+// workgroup per CU, else the packed-add default.
+static const int kUntunedOrder[] = {kNumCfgs + 1, kNumCfgs, kDefaultCfg};
+
 dedisp_status run_search_tiled(dedisp_plan p, const uint8_t *x, int64_t nsamp, int64_t in_stride,
                                int64_t nout, const WidthList &wl, const double *mu,
                                const double *sigma, double *snr, int32_t *t, int32_t *w,
                                void *work, hipStream_t s) {
-  const int ci = cfg_index(p);
-  dedisp_status st = search_ci(p, ci, x, nsamp, in_stride, nout, wl, mu, sigma, snr, t, w, work, s);
-  if (st == DEDISP_ERR_UNSUPPORTED && p->tile_choice < 0 && ci != kDefaultCfg)
-    st = search_ci(p, kDefaultCfg, x, nsamp, in_stride, nout, wl, mu, sigma, snr, t, w, work, s);
+  if (p->tile_choice >= 0 && p->tile_choice < num_candidates())
+    return search_ci(p, p->tile_choice, x, nsamp, in_stride, nout, wl, mu, sigma, snr, t, w,
+                     work, s);
+  dedisp_status st = DEDISP_ERR_UNSUPPORTED;
+  for (const int ci : kUntunedOrder) {
+    if (ci >= num_candidates()) continue;
+    st = search_ci(p, ci, x, nsamp, in_stride, nout, wl, mu, sigma, snr, t, w, work, s);
+    if (st != DEDISP_ERR_UNSUPPORTED) break;
+  }
   return st;
 }
 
