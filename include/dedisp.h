@@ -286,6 +286,16 @@ dedisp_status dedisp_autotune(dedisp_plan plan, const void *d_in, int64_t nsamp,
                               const int32_t *widths, int32_t nw, const double *d_chan_mean,
                               const double *d_chan_sigma, void *d_work, size_t work_bytes,
                               void *stream, int32_t *chosen);
+/* Test support, host only (no device work): builds the host tables of matrix-core shape
+ * `shape` (0 .. 4, the search's candidates 8 .. 12) for the plan and checks them: the
+ * register staging's units and the direct staging's copy blocks fill the same LDS
+ * pieces with the same window bytes, every K block's segments are read inside their
+ * channel's staged region, window origins are multiples of 8 and the converted rows
+ * reach every copy block.  *pieces (optional): LDS pieces compared.  Returns OK,
+ * UNSUPPORTED when the plan does not fit the shape or a check fails (message in
+ * dedisp_last_error), INVALID_ARG for a null plan or a shape out of range. */
+dedisp_status dedisp_check_search_tables(dedisp_plan plan, int32_t shape, int64_t *pieces);
+
 /* Force a shape of the fused uint8 search (index into its candidate list: the
  * shapes of the packed-add kernel, then those of the int8 matrix-core kernel; the
  * autotuner times them all), -1 for the default (the matrix-core shape of two

@@ -21,7 +21,7 @@ WMODES = {"unit": W_UNIT, "channel": W_CHANNEL, "tap": W_TAP}
 EXPORTS = [
     "dedisp_profile_init", "dedisp_plan_create", "dedisp_plan_destroy", "dedisp_plan_tables",
     "dedisp_plan_info", "dedisp_plan_out_len", "dedisp_dedisperse", "dedisp_work_bytes",
-    "dedisp_detect", "dedisp_merge_candidates", "dedisp_search", "dedisp_search_noalloc",
+    "dedisp_detect", "dedisp_merge_candidates", "dedisp_check_search_tables", "dedisp_search", "dedisp_search_noalloc",
     "dedisp_dedisperse_backward",
     "dedisp_backward_sparse",
     "dedisp_dedisperse_gather", "dedisp_trial_dms", "dedisp_batch_create", "dedisp_batch_destroy",
@@ -78,6 +78,7 @@ def lib():
         "dedisp_search": [P, P, i32, i64, i64, P, i32, P, P, P, P, P, P, sz, P],
         "dedisp_search_noalloc": [P, P, i32, i64, i64, P, i32, P, P, P, P, P, P],
         "dedisp_merge_candidates": [i32, P, P, P, i64, P, P, P, P],
+        "dedisp_check_search_tables": [P, i32, P],
         "dedisp_dedisperse_backward": [P, P, i64, i64, i64, i32, P, i32, i64, i64, i64, P, P, P, P],
         "dedisp_backward_sparse": [P, i32, P, P, P, P, P, i32, i64, i64, i64, i32, P, P],
         "dedisp_dedisperse_gather": [P, i32, P, P, P, P, i32, i64, i64, i64, i32, P, P, P],

@@ -259,6 +259,12 @@ dedisp_status dedisp_merge_candidates(int32_t ndm, const double *d_snr_b, const 
   return DEDISP_OK;
 }
 
+dedisp_status dedisp_check_search_tables(dedisp_plan p, int32_t shape, int64_t *pieces) {
+  if (!p) return fail(DEDISP_ERR_INVALID_ARG, "null plan");
+  if (pieces) *pieces = 0;
+  return dd::mfma_check_tables(p, shape, pieces);
+}
+
 dedisp_status dedisp_search(dedisp_plan p, const void *d_in, int32_t in_dtype, int64_t nsamp,
                             int64_t in_stride, const int32_t *widths, int32_t nw,
                             const double *d_chan_mean, const double *d_chan_sigma, double *d_snr,

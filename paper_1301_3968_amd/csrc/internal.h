@@ -212,6 +212,8 @@ dedisp_status run_dedisperse_u8_mfma(dedisp_plan p, const uint8_t *x, int64_t ns
 // tables, the tile kernel, the reduction over time tiles; kernels_mfma.hip).
 // Returns DEDISP_ERR_UNSUPPORTED (launching nothing) when the plan does not fit.
 int mfma_search_count();
+// Host-only consistency check of a matrix-core shape's tables (kernels_mfma.hip).
+dedisp_status mfma_check_tables(const dedisp_plan_s *p, int k, int64_t *pieces);
 size_t mfma_search_work_bytes(const dedisp_plan_s *p, int32_t nw, int64_t nout);
 dedisp_status run_search_mfma(dedisp_plan p, int k, const uint8_t *x, int64_t nsamp,
                               int64_t in_stride, int64_t nout, const WidthList &wl,

@@ -812,6 +812,68 @@ static bool build_mfma_cfg(const dedisp_plan_s *p, int ci, MfmaCfgTables &out) {
   return out.ok;
 }
 
+// Host-only consistency check of shape k's tables (test support): the staging units
+// (register staging) and the copy blocks (direct staging) fill the same LDS pieces of each
+// group with the same window bytes; every K-block segment's lanes read inside its channel's
+// staged region (window bytes o + 8 n + 256 q' .. + 15 for column n < 32 and product q' of
+// the tile, so o + TW <= the region's bytes per copy); window origins are multiples of 8;
+// and the converted rows reach every copy block.  *pieces: LDS pieces compared.
+dedisp_status mfma_check_tables(const dedisp_plan_s *p, int k, int64_t *pieces) {
+  if (k < 0 || k >= kNumMfmaCfgs) return fail(DEDISP_ERR_INVALID_ARG, "shape out of range");
+  MfmaCfgTables c;
+  if (!build_mfma_cfg(p, k, c)) return fail(DEDISP_ERR_UNSUPPORTED, "plan does not fit the shape");
+  const int TW = c.tw;
+  auto bad = [](const std::string &m) { return fail(DEDISP_ERR_UNSUPPORTED, "table check: " + m); };
+  int64_t n = 0;
+  for (size_t g = 0; g < c.groups.size(); ++g) {
+    const MGroup &G = c.groups[g];
+    // LDS piece offset -> (channel, window sample of its first byte), from both stagings
+    std::vector<std::pair<int32_t, std::pair<int32_t, int32_t>>> from_units, from_blocks;
+    for (int u = G.unit_begin; u < G.unit_begin + G.nunits; ++u)
+      for (int h = 0; h < kCopies; ++h)
+        from_units.push_back({c.units[u].dst + 16 * h, {c.units[u].c, c.units[u].src + 8 * h}});
+    for (int b = G.block_begin; b < G.block_begin + G.nblocks; ++b) {
+      const MBlock &B = c.blocks[b];
+      if (B.nl < 1 || B.nl > 64 || B.src % 8) return bad("copy block shape");
+      if ((int64_t)B.src + 8 * (B.nl - 1) + 16 > c.xspan) return bad("converted row too short");
+      for (int l = 0; l < B.nl; ++l) from_blocks.push_back({B.dst + 16 * l, {B.c, B.src + 8 * l}});
+    }
+    std::sort(from_units.begin(), from_units.end());
+    std::sort(from_blocks.begin(), from_blocks.end());
+    if (from_units != from_blocks) return bad("units and copy blocks differ in group " + std::to_string(g));
+    n += (int64_t)from_units.size();
+    if (from_units.empty()) continue;
+    // the group's window area [0, rec_off): per channel region [first piece, last piece + 16)
+    std::vector<int32_t> lo(p->nchan, INT32_MAX), hi(p->nchan, INT32_MIN), org(p->nchan, 0);
+    for (auto &e : from_units) {
+      const int ch = e.second.first;
+      if (e.first < lo[ch]) {
+        lo[ch] = e.first;
+        org[ch] = e.second.second;   // window sample of the region's first byte
+      }
+      hi[ch] = std::max(hi[ch], e.first + 16);
+      if (e.first + 16 > G.rec_off) return bad("window piece over the records");
+    }
+    for (int ch = 0; ch < p->nchan; ++ch)
+      if (lo[ch] != INT32_MAX && (org[ch] % 8)) return bad("window origin not a multiple of 8");
+    // every segment of the group's K blocks
+    for (int kb = G.kb_first; kb < G.kb_first + G.nkb; ++kb)
+      for (int sg = 0; sg < 2; ++sg) {
+        int32_t ad = 0;
+        std::memcpy(&ad, c.recs.data() + (size_t)kb * kRecBytes + kRecBase + 4 * sg, 4);
+        if (ad % 16) return bad("segment base not 16-byte aligned");
+        int ch = -1;
+        for (int cc = 0; cc < p->nchan; ++cc)
+          if (lo[cc] != INT32_MAX && ad >= lo[cc] && ad < hi[cc]) ch = cc;
+        if (ch < 0) return bad("segment base outside every staged region");
+        const int64_t o = (ad - lo[ch]) / 2;              // window byte of the segment
+        if (2 * (o + TW) > (int64_t)(hi[ch] - lo[ch])) return bad("segment reads past its region");
+      }
+  }
+  if (pieces) *pieces = n;
+  return DEDISP_OK;
+}
+
 static hipError_t allow_lds_mfma(const void *fn, bool *done, std::mutex *mu, int bytes) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);

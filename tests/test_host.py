@@ -235,3 +235,44 @@ def test_merge_candidates_rejects_bad_arguments():
     assert L.dedisp_merge_candidates(4, None, p, p, 0, p, p, p, None) == _lib.ERR_INVALID_ARG
     assert L.dedisp_merge_candidates(4, p, p, p, -1, p, p, p, None) == _lib.ERR_INVALID_ARG
     assert b"t_offset" in L.dedisp_last_error()
+
+
+@pytest.mark.parametrize("which", ["cfg1", "cfg2", "explicit", "short"])
+def test_matrix_core_staging_tables_consistent(dd, which):
+    """For every matrix-core shape the plan fits, the host tables of the two window
+    stagings fill the same LDS pieces with the same window bytes and every K block reads
+    inside its channel's staged region (the library's own host-side check)."""
+    from paper_1301_3968_amd import _lib
+    rng = np.random.default_rng(88)
+    if which == "cfg1":
+        wl = workloads.cfg1()
+        p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule=wl.rule)
+    elif which == "cfg2":
+        wl = workloads.cfg2(nsamp=4096)
+        p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule="allnonzero")
+    elif which == "short":   # 37 trials: no DM tile full
+        wl = workloads.cfg2(nsamp=3000, ndm=37)
+        p = dd.Plan(wl.freqs_ghz, wl.chan_bw_ghz, wl.dt_s, wl.dms, rule="allnonzero")
+    else:                    # trials out of DM order, a channel no trial uses, runs of 1..7
+        C, D = 37, 50
+        f = workloads.channel_centres(1.35, 0.3, C)
+        dms = ((np.arange(D) * 37) % D) * 3.0
+        s = np.zeros((D, C), np.int32)
+        n = rng.integers(1, 8, size=(D, C)).astype(np.int32)
+        for d in range(D):
+            s[d] = np.floor(4.15 * dms[d] * (1.0 / f ** 2 - 1.0 / f.max() ** 2)).astype(np.int32)
+        n[:, 5] = 0
+        p = dd.Plan(f, 0.01, 1e-3, dms, rule="explicit", start=s, ntap=n)
+    fits = 0
+    for shape in range(5):
+        pieces = ctypes.c_int64(-1)
+        st = _lib.lib().dedisp_check_search_tables(p.handle, shape, ctypes.byref(pieces))
+        msg = _lib.lib().dedisp_last_error().decode()
+        if st == _lib.ERR_UNSUPPORTED:
+            assert "does not fit" in msg, msg
+            continue
+        assert st == 0, msg
+        assert pieces.value > 0
+        fits += 1
+    assert fits >= 1
+    assert _lib.lib().dedisp_check_search_tables(p.handle, 5, None) == _lib.ERR_INVALID_ARG
