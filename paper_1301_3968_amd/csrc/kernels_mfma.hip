@@ -32,8 +32,8 @@
 // segments (a K block), a 48-byte record: per segment and trial a 32-bit run mask (bit j
 // set when window byte o_g - 8 + j lies in the trial's run; phase u takes bits 8 - u ..
 // 23 - u), and the LDS base address of each segment; the records of a channel group are
-// copied into LDS with the windows, and every lane forms its 16 mask bytes and its read
-// address from them.
+// copied into LDS with the windows, and every lane forms its 16 mask bytes (two 8-byte
+// entries of a 2 KB LDS table indexed by mask bytes) and its read address from them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -70,8 +70,10 @@ constexpr int kTrialsPerWave = 4;           // trials of a wave (x 8 output phas
 constexpr int kPhases = 8;                  // output phases (rows per trial)
 constexpr int kOutsPerProduct = 32 * kPhases;
 constexpr int kCopies = 2;                  // 8-byte-shifted copies of each staged window
-constexpr int kMfmaBufBytes = 80 * 1024;    // LDS per staging buffer (two per workgroup) at
+constexpr int kMfmaBufBytes = 78 * 1024;    // LDS per staging buffer (two per workgroup) at
                                             // one workgroup per CU
+constexpr int kLutBytes = 2048;             // after the two buffers: the 8 mask bytes of every
+                                            // byte value (byte j is bit j of the value)
 constexpr int kSlotBytes = 16;              // the end of the second buffer, never staged into:
                                             // the persistent batch's item broadcast
 // K-block record: 8 x u32 run masks (index 4 g + trial for segment g; bit j: window byte
@@ -324,6 +326,18 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
     }
     if (b < nb) dma_block(ldc(bd, b), buf);
   };
+  // the mask-expansion table (written before the first group's barrier, read only after it)
+  typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+  unsigned char *lut = lds + 2 * (kMfmaBufBytes / WG);
+  for (int e = tid; e < 256; e += 64 * NW) {
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      lo |= ((uint32_t)(e >> j) & 1u) << (8 * j);
+      hi |= ((uint32_t)(e >> (j + 4)) & 1u) << (8 * j);
+    }
+    *(v2u *)(lut + 8 * e) = (v2u){lo, hi};
+  }
   stage_recs(gb, lds);
   if constexpr (DMA) {
     dma_stage(gb, lds);
@@ -364,11 +378,10 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
         b_next = *(const int32_t *)(rb + kRecBytes + kRecBase + 4 * (lane >> 5));
       }
       // 16 mask bytes of lane (row lane % 32 = trial 8 m + phase u, segment lane / 32):
-      // byte j is bit 8 - u + j of the run mask
-      v4i mk;
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        mk[k] = (int32_t)((__builtin_amdgcn_ubfe(m32, msh + 4 * k, 4) * 0x204081u) & 0x01010101u);
+      // byte j is bit 8 - u + j of the run mask, 8 bytes at a time from the table
+      const v2u e0 = *(const v2u *)(lut + 8 * __builtin_amdgcn_ubfe(m32, msh, 8));
+      const v2u e1 = *(const v2u *)(lut + 8 * __builtin_amdgcn_ubfe(m32, msh + 8, 8));
+      const v4i mk = {(int32_t)e0[0], (int32_t)e0[1], (int32_t)e1[0], (int32_t)e1[1]};
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
         const v4i bq = *(const v4i *)(bp + 2 * kOutsPerProduct * q);
@@ -891,10 +904,10 @@ static hipError_t launch_mfma_cfg(const MfmaArgs &a, int nbatch, hipStream_t s) 
   static bool done[64] = {};
   static std::mutex mu;
   hipError_t e = allow_lds_mfma((const void *)k_dedisp_mfma<NWD, NWT, NP, WG>, done, &mu,
-                                2 * (kMfmaBufBytes / WG));
+                                2 * (kMfmaBufBytes / WG) + kLutBytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_dedisp_mfma<NWD, NWT, NP, WG>), dim3(a.ntw * a.ntt, nbatch),
-                     dim3(64 * NWD * NWT), 2 * a.bufbytes, s, a);
+                     dim3(64 * NWD * NWT), 2 * a.bufbytes + kLutBytes, s, a);
   return hipGetLastError();
 }
 
@@ -1034,10 +1047,10 @@ static hipError_t launch_search_cfg(const MfmaSearchArgs &sa, hipStream_t s) {
   static bool done[64] = {};
   static std::mutex mu;
   hipError_t e = allow_lds_mfma((const void *)k_search_mfma<NWD, NWT, NP, WG, DMA>, done, &mu,
-                                2 * (kMfmaBufBytes / WG));
+                                2 * (kMfmaBufBytes / WG) + kLutBytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_search_mfma<NWD, NWT, NP, WG, DMA>), dim3(sa.m.ntw * sa.m.ntt),
-                     dim3(64 * NWD * NWT), 2 * sa.m.bufbytes, s, sa);
+                     dim3(64 * NWD * NWT), 2 * sa.m.bufbytes + kLutBytes, s, sa);
   return hipGetLastError();
 }
 
@@ -1318,22 +1331,22 @@ static hipError_t launch_batch_mfma_cfg(const MfmaBatch *B, const MfmaSearchArgs
     static bool pdone[64] = {};
     static std::mutex pmu;
     hipError_t e = allow_lds_mfma((const void *)k_search_mfma_persist<NWD, NWT, NP, WG>, pdone,
-                                  &pmu, 2 * (kMfmaBufBytes / WG));
+                                  &pmu, 2 * (kMfmaBufBytes / WG) + kLutBytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, B->d_counter);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((k_search_mfma_persist<NWD, NWT, NP, WG>), dim3(B->pgrid),
-                       dim3(64 * NWD * NWT), 2 * (kMfmaBufBytes / WG), s, table, B->d_items,
+                       dim3(64 * NWD * NWT), 2 * (kMfmaBufBytes / WG) + kLutBytes, s, table, B->d_items,
                        B->nitems, B->d_counter);
     return hipGetLastError();
   }
   static bool done[64] = {};
   static std::mutex mu;
   hipError_t e = allow_lds_mfma((const void *)k_search_mfma_batch<NWD, NWT, NP, WG>, done, &mu,
-                                2 * (kMfmaBufBytes / WG));
+                                2 * (kMfmaBufBytes / WG) + kLutBytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_search_mfma_batch<NWD, NWT, NP, WG>), dim3(B->base.back()),
-                     dim3(64 * NWD * NWT), 2 * (kMfmaBufBytes / WG), s, table, B->d_base,
+                     dim3(64 * NWD * NWT), 2 * (kMfmaBufBytes / WG) + kLutBytes, s, table, B->d_base,
                      B->nbeam);
   return hipGetLastError();
 }
