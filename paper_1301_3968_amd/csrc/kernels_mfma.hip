@@ -398,7 +398,13 @@ __device__ __forceinline__ TileAcc<NP> mfma_tile(MA &a, int tw, int64_t T0, cons
       if constexpr (DMA) dma_stage(g + 1, lds + (par ^ 1) * a.bufbytes);
       else fetch(g + 1);
     }
-    for (; kb < k1; ++kb) kblock(kb);
+    // two K blocks an iteration (half the register copies of the next record's mask and
+    // base, and one pointer step for two)
+    for (; kb + 1 < k1; kb += 2) {
+      kblock(kb);
+      kblock(kb + 1);
+    }
+    if (kb < k1) kblock(kb);
     __builtin_amdgcn_s_setprio(0);
     if constexpr (!DMA) {
       if (g + 1 < ge) store(lds + (par ^ 1) * a.bufbytes);
